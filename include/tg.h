@@ -1,0 +1,158 @@
+/*
+ * tg.h -- C ABI of libtg.so: per-edge and global counts of typed 3- and
+ * 4-node graphlets on AMD MI355X (gfx950).
+ *
+ * What is counted (Sections 3.2 and 4, "Local Typed Graphlet Counting" and
+ * "Global Typed Graphlet Counting"): for an undirected simple graph whose
+ * nodes carry a type phi in [0, L), and for every edge (i, j), the number of
+ * connected induced subgraphs on 3 or 4 nodes that contain both i and j,
+ * split by graphlet shape and by the multiset of node types of the subgraph
+ * (typed graphlet instances are equal when their type multisets are equal).
+ * The global count of a (shape, multiset) is the number of such subgraphs in
+ * the graph; it equals the per-edge sum divided by the shape's edge count
+ * (Eq. 17).
+ *
+ * Shapes, in the paper's order h1..h8: wedge (3-node path), triangle, 4-path,
+ * 4-star, 4-cycle, tailed triangle, chordal cycle (diamond), 4-clique.
+ *
+ * Conventions used by every entry point:
+ *  - Graph: CSR with int32 row_ptr[n+1] and col_idx[nnz]; both directions of
+ *    each edge stored; each row strictly increasing; no self loops; nnz < 2^31.
+ *  - Node types: uint8 types[n], each < L, 1 <= L <= 16.
+ *  - Canonical edge order: the e-th slot (i, j) with i < j when the CSR is read
+ *    row by row.  m = nnz / 2 edges.
+ *  - Per-edge row (width tg_edge_row_width(L) = 2L + 3L(L+1)), relative to the
+ *    edge's own types (phi_i, phi_j): wedge[t] for t < L, triangle[t], then for
+ *    4-path, 4-star, 4-cycle, tailed triangle, chordal cycle, 4-clique one
+ *    block of P = L(L+1)/2 entries each, indexed by p(t, u) = u(u+1)/2 + t for
+ *    t <= u: the types of the two other nodes.
+ *  - Global key (tg_num_keys(L) = 2 C(L+2,3) + 6 C(L+3,4) keys): shape offset
+ *    plus the colex rank of the sorted type multiset (a<=b<=c[<=d]):
+ *    C(a,1) + C(b+1,2) + C(c+2,3) [+ C(d+3,4)].  Offsets follow shape order,
+ *    3-node shapes taking C(L+2,3) keys each and 4-node shapes C(L+3,4).
+ *  - Counts are uint64.
+ *
+ * Memory: pointers documented as "device" must point to device memory of the
+ * current HIP device (e.g. torch tensors); "host" pointers to host memory.
+ * The caller owns every input and output buffer.  Scratch memory is allocated
+ * and released by the library, stream-ordered on the caller's stream.
+ *
+ * Streams and errors: all device work is enqueued on `stream`.  Argument
+ * errors are reported before anything is enqueued.  Device-detected problems
+ * (invalid graph when validation is on, a global sum that is not a multiple of
+ * its shape's edge count) are reported after the call synchronises the
+ * stream, which it does only when `check` (or `validate`) is set.  On any
+ * non-OK status the outputs are unspecified.  tg_last_error() gives a
+ * thread-local message for the last failure.  No C++ exception crosses the ABI.
+ */
+#ifndef TG_H_
+#define TG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TG_OK = 0,
+  TG_ERR_INVALID_ARG = 1,     /* null pointer, bad size, bad range */
+  TG_ERR_INVALID_GRAPH = 2,   /* CSR violates the conventions above (validate=1) */
+  TG_ERR_TYPE_RANGE = 3,      /* a node type >= L (validate=1) */
+  TG_ERR_UNSUPPORTED_L = 4,   /* L outside [1, 16] */
+  TG_ERR_OUT_OF_MEMORY = 5,   /* scratch allocation failed */
+  TG_ERR_INTERNAL = 6,        /* a global sum was not divisible (check=1) */
+  TG_ERR_HIP = 7              /* a HIP runtime call failed */
+} tg_status;
+
+typedef enum {
+  TG_WEDGE = 0, TG_TRIANGLE, TG_PATH4, TG_STAR4, TG_CYCLE4, TG_TAILED_TRIANGLE, TG_CHORDAL_CYCLE, TG_CLIQUE4,
+  TG_NUM_SHAPES
+} tg_shape;
+
+/* Edge scheduling.  Counts are identical for every choice; only time changes.
+ * NONE: edges in canonical order with a fixed light/heavy split by degree.
+ * DEGREE: edges binned and ordered by the degree-product cost d_i * d_j.
+ * LEARNED: edges binned and ordered by a cost model (tg_cost_model). */
+typedef enum { TG_SCHED_NONE = 0, TG_SCHED_DEGREE = 1, TG_SCHED_LEARNED = 2 } tg_schedule;
+
+typedef struct tg_cost_model tg_cost_model;
+
+typedef struct {
+  tg_schedule schedule;        /* default TG_SCHED_DEGREE */
+  const tg_cost_model* model;  /* required for TG_SCHED_LEARNED, else ignored */
+  int validate;                /* 1: O(m) device check of the CSR and types (synchronises) */
+  int check;                   /* 1: synchronise and verify global divisibility (default 1) */
+  int64_t edge_begin;          /* per-edge rows are written for canonical edges */
+  int64_t edge_end;            /*   [edge_begin, edge_end); edge_end < 0 means m */
+  float* phase_ms;             /* host, TG_NUM_PHASES floats, or NULL: when set, the call records
+                                  HIP events on `stream` around each phase, synchronises at the end
+                                  and stores each phase's elapsed milliseconds */
+} tg_options;
+
+/* Phases timed through tg_options.phase_ms. */
+enum {
+  TG_PHASE_PREP = 0,     /* degrees, typed degrees, edge ids, degree-ordered out-lists */
+  TG_PHASE_TAU,          /* typed triangle counts per edge */
+  TG_PHASE_TABLES,       /* per-node sums of typed degrees and triangle counts */
+  TG_PHASE_SCHEDULE,     /* edge classes and cost buckets, node tiers */
+  TG_PHASE_CYCLES,       /* typed 4-cycles through every edge */
+  TG_PHASE_COMBINE,      /* per-edge orbits, graphlets, rows and global sums */
+  TG_PHASE_FINALIZE,     /* division of global sums by shape edge counts */
+  TG_NUM_PHASES
+};
+
+/* Fills *opt with the defaults above. */
+void tg_options_default(tg_options* opt);
+
+/* K(L) = 2 C(L+2,3) + 6 C(L+3,4) global keys (Eq. 1 per shape); 0 if L is
+ * outside [1, 16]. */
+size_t tg_num_keys(int L);
+
+/* R(L) = 2L + 3L(L+1) entries per edge row; 0 if L is outside [1, 16]. */
+size_t tg_edge_row_width(int L);
+
+/* Host.  Decodes a global key into its shape and sorted types; types[3] is
+ * 0xFF for 3-node shapes. */
+tg_status tg_key_decode(int L, size_t key, int* shape, uint8_t types[4]);
+
+/* Host.  Encodes (shape, types) into a global key; the types may come in any
+ * order (the key depends on the multiset only, Section 4.5); types[3] is
+ * ignored for 3-node shapes. */
+tg_status tg_key_encode(int L, int shape, const uint8_t types[4], size_t* key);
+
+/* Host.  Global key of column `col` of a per-edge row whose edge has types
+ * (phi_i, phi_j). */
+tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_t* key);
+
+/* Counts every typed 3/4-node graphlet of one graph (Algorithm 1's problem,
+ * per edge, plus Eq. 17's global counts).
+ *   n, nnz          node count and CSR slot count (nnz = 2m)
+ *   row_ptr         device, int32[n+1]
+ *   col_idx         device, int32[nnz]
+ *   node_types      device, uint8[n]
+ *   L               number of node types, 1..16
+ *   global_counts   device, uint64[tg_num_keys(L)]; always written
+ *   edge_counts     device, uint64[(edge_end-edge_begin) * R(L)], or NULL for
+ *                   global counts only
+ *   edge_endpoints  device, int32[(edge_end-edge_begin) * 2] receiving (i, j)
+ *                   with i < j of each canonical edge in range, or NULL
+ *   opt             host, or NULL for defaults
+ */
+tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                   const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
+                   int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char* tg_status_string(tg_status s);
+
+/* Thread-local detail about the last non-OK status returned on this thread. */
+const char* tg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TG_H_ */

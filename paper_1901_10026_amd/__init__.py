@@ -1,0 +1,183 @@
+"""Python binding of libtg.so (typed 3/4-node graphlet counting on MI355X).
+
+This module only marshals arguments: torch tensors provide device memory and
+the HIP stream, and every step of the computation runs in the library's
+kernels.  There is no CPU fallback; if the library is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+_CSRC = os.path.join(_HERE, "csrc")
+_INCLUDE = os.path.join(_ROOT, "include")
+_LIB = os.path.join(_HERE, "libtg.so")
+_lib = None
+
+SHAPES = ("wedge", "triangle", "path4", "star4", "cycle4", "tailed_triangle", "chordal_cycle", "clique4")
+SCHEDULES = {"none": 0, "degree": 1, "learned": 2}
+STATUS = {0: "TG_OK", 1: "TG_ERR_INVALID_ARG", 2: "TG_ERR_INVALID_GRAPH", 3: "TG_ERR_TYPE_RANGE",
+          4: "TG_ERR_UNSUPPORTED_L", 5: "TG_ERR_OUT_OF_MEMORY", 6: "TG_ERR_INTERNAL", 7: "TG_ERR_HIP"}
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+class TGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def build(force: bool = True) -> str:
+    """Compile libtg.so for gfx950 with hipcc (cross-compiles without a GPU)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["hipcc", *HIPCC_FLAGS, f"-I{_INCLUDE}", f"-I{_CSRC}", os.path.join(_CSRC, "tg_api.hip"), "-o", tmp]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def declared_symbols():
+    """Function names declared in include/tg.h."""
+    text = open(os.path.join(_INCLUDE, "tg.h")).read()
+    return sorted(set(re.findall(r"\b(tg_[a-z0-9_]+)\s*\(", text)))
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int), ("model", ctypes.c_void_p), ("validate", ctypes.c_int),
+                ("check", ctypes.c_int), ("edge_begin", ctypes.c_int64), ("edge_end", ctypes.c_int64),
+                ("phase_ms", ctypes.c_void_p)]
+
+
+PHASES = ("prep", "tau", "tables", "schedule", "cycles", "combine", "finalize")
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        raise RuntimeError(f"libtg.so is not built ({_LIB}); run paper_1901_10026_amd.build() or "
+                           "__graft_entry__.build() first")
+    L = ctypes.CDLL(_LIB)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    L.tg_options_default.restype = None
+    L.tg_options_default.argtypes = [ctypes.POINTER(_Options)]
+    L.tg_num_keys.restype = sz
+    L.tg_num_keys.argtypes = [i32]
+    L.tg_edge_row_width.restype = sz
+    L.tg_edge_row_width.argtypes = [i32]
+    L.tg_key_decode.restype = i32
+    L.tg_key_decode.argtypes = [i32, sz, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint8)]
+    L.tg_key_encode.restype = i32
+    L.tg_key_encode.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(sz)]
+    L.tg_edge_row_key.restype = i32
+    L.tg_edge_row_key.argtypes = [i32, ctypes.c_uint8, ctypes.c_uint8, sz, ctypes.POINTER(sz)]
+    L.tg_count.restype = i32
+    L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_status_string.restype = ctypes.c_char_p
+    L.tg_status_string.argtypes = [i32]
+    L.tg_last_error.restype = ctypes.c_char_p
+    L.tg_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise TGError(st, lib().tg_last_error().decode())
+
+
+def num_keys(L: int) -> int:
+    return int(lib().tg_num_keys(L))
+
+
+def edge_row_width(L: int) -> int:
+    return int(lib().tg_edge_row_width(L))
+
+
+def key_encode(L: int, shape: int, types) -> int:
+    arr = (ctypes.c_uint8 * 4)(*(list(types) + [0] * (4 - len(types))))
+    out = ctypes.c_size_t()
+    _check(lib().tg_key_encode(L, shape, arr, ctypes.byref(out)))
+    return int(out.value)
+
+
+def key_decode(L: int, key: int):
+    shape = ctypes.c_int()
+    arr = (ctypes.c_uint8 * 4)()
+    _check(lib().tg_key_decode(L, key, ctypes.byref(shape), arr))
+    k = 3 if shape.value < 2 else 4
+    return int(shape.value), tuple(int(arr[q]) for q in range(k))
+
+
+def edge_row_key(L: int, phi_i: int, phi_j: int, col: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().tg_edge_row_key(L, phi_i, phi_j, col, ctypes.byref(out)))
+    return int(out.value)
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedule="degree", validate=False,
+          check=True, edge_range=None, model=None, out_global=None, out_edges=None, phase_ms=None):
+    """Counts every typed 3/4-node graphlet of one graph with tg_count.
+
+    row_ptr, col_idx (int32) and types (uint8) are CUDA (HIP) tensors on the
+    same device.  Returns (global uint64 [K(L)], per-edge uint64 [E, R(L)] or
+    None, endpoints int32 [E, 2] or None) as torch tensors; uint64 results are
+    stored in torch.uint64 tensors.
+    """
+    import torch
+    dev = row_ptr.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (types, torch.uint8)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("row_ptr/col_idx must be contiguous int32 and types contiguous uint8 on one device")
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    m = nnz // 2
+    e0, e1 = (0, m) if edge_range is None else (int(edge_range[0]), int(edge_range[1]))
+    K = num_keys(L)
+    R = edge_row_width(L)
+    if K == 0:
+        raise TGError(4, "L must be in [1, 16]")
+    g = out_global if out_global is not None else torch.empty(K, dtype=torch.uint64, device=dev)
+    rows = None
+    if per_edge:
+        rows = out_edges if out_edges is not None else torch.empty((max(e1 - e0, 0), R), dtype=torch.uint64,
+                                                                   device=dev)
+    ends = torch.empty((max(e1 - e0, 0), 2), dtype=torch.int32, device=dev) if endpoints else None
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.schedule = SCHEDULES[schedule]
+    opt.model = model.handle if model is not None else None
+    opt.validate = 1 if validate else 0
+    opt.check = 1 if check else 0
+    opt.edge_begin = e0
+    opt.edge_end = e1
+    times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
+    opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    st = lib().tg_count(n, nnz, row_ptr.data_ptr(), col_idx.data_ptr() if nnz else None,
+                        types.data_ptr() if n else None, L, g.data_ptr(),
+                        rows.data_ptr() if rows is not None and rows.numel() else None,
+                        ends.data_ptr() if ends is not None and ends.numel() else None,
+                        ctypes.byref(opt), _stream_handle(torch, dev))
+    _check(st)
+    if times is not None:
+        phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
+    return g, rows, ends

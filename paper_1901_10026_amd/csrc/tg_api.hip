@@ -1,0 +1,540 @@
+// C ABI of libtg.so: argument checks, scratch management, launch sequence.
+// The kernels live in tg_kernels.hip, compiled into this translation unit.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "tg.h"
+#include "tg_kernels.hip"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tg_status fail(tg_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+int64_t binom(int64_t n, int64_t k) {
+  if (k < 0 || n < k) return 0;
+  int64_t r = 1;
+  for (int64_t q = 1; q <= k; ++q) r = r * (n - k + q) / q;
+  return r;
+}
+
+int64_t per_shape(int L, int K) { return binom(L + K - 1, K); }
+
+int64_t nkeys(int L) { return 2 * per_shape(L, 3) + 6 * per_shape(L, 4); }
+
+// Per-edge log2 cost predicted by a learned model (defined with the model).
+tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t n, const int32_t* rp, const int32_t* ci,
+                                    const uint8_t* ty, int L, const tg::Work& W, int64_t m, float* out,
+                                    hipStream_t st);
+
+#define TG_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t err_ = (call);                                                                 \
+    if (err_ != hipSuccess)                                                                   \
+      return fail(TG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(err_));           \
+  } while (0)
+
+#define TG_LAUNCHED(name)                                                                     \
+  do {                                                                                        \
+    hipError_t err_ = hipGetLastError();                                                      \
+    if (err_ != hipSuccess)                                                                   \
+      return fail(TG_ERR_HIP, std::string("launch of ") + name + ": " + hipGetErrorString(err_)); \
+  } while (0)
+
+// Stream-ordered scratch: every allocation is released on the same stream when
+// the owner goes out of scope.  The default pool keeps freed memory cached.
+struct Scratch {
+  hipStream_t stream;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+  }
+  template <class T>
+  hipError_t get(T** out, int64_t count) {
+    *out = nullptr;
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(T), stream);
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return hipSuccess;
+  }
+};
+
+void keep_pool_cached() {
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done[dev] = true;
+}
+
+// HIP events around each phase, on the caller's stream.
+struct PhaseTimer {
+  hipStream_t st;
+  float* out;
+  hipEvent_t ev[TG_NUM_PHASES + 1];
+  int created = 0;
+  int marked = 0;
+  PhaseTimer(hipStream_t s, float* o) : st(s), out(o) {
+    if (!out) return;
+    for (int q = 0; q < TG_NUM_PHASES; ++q) out[q] = 0.0f;
+    for (int q = 0; q <= TG_NUM_PHASES; ++q) {
+      if (hipEventCreate(&ev[q]) != hipSuccess) return;
+      ++created;
+    }
+  }
+  ~PhaseTimer() {
+    for (int q = 0; q < created; ++q) (void)hipEventDestroy(ev[q]);
+  }
+  // start of phase q (q == TG_NUM_PHASES: end of the last phase)
+  void mark(int q) {
+    if (created == TG_NUM_PHASES + 1 && q == marked) {
+      if (hipEventRecord(ev[q], st) == hipSuccess) ++marked;
+    }
+  }
+  void finish() {
+    if (marked != TG_NUM_PHASES + 1) return;
+    if (hipEventSynchronize(ev[TG_NUM_PHASES]) != hipSuccess) return;
+    for (int q = 0; q < TG_NUM_PHASES; ++q) (void)hipEventElapsedTime(&out[q], ev[q], ev[q + 1]);
+  }
+};
+
+inline unsigned grid_for(int64_t items, int64_t per_block, int64_t cap = (1ll << 30)) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+int64_t dense_budget_bytes() {
+  const char* s = std::getenv("TG_DENSE_BUDGET_MB");
+  int64_t mb = s ? std::atoll(s) : 4096;
+  if (mb < 64) mb = 64;
+  return mb << 20;
+}
+
+// Exclusive scan of in[0, n) into out[0, n], out[n] = total.
+tg_status scan(Scratch& S, hipStream_t st, int64_t n, const int32_t* in, int32_t* out) {
+  const int64_t nb = (n + 1023) / 1024;
+  int32_t* sums;
+  TG_HIP(S.get(&sums, nb + 1));
+  if (nb > 0) {
+    k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(n, in, out, sums);
+    TG_LAUNCHED("k_scan_blocks");
+  }
+  k_scan_sums<<<1, 64, 0, st>>>(nb, sums, sums + nb);
+  TG_LAUNCHED("k_scan_sums");
+  k_scan_add<<<grid_for(n + 1, 256, 8192), 256, 0, st>>>(n, out, sums, sums + nb);
+  TG_LAUNCHED("k_scan_add");
+  return TG_OK;
+}
+
+tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                         const uint8_t* ty, int L) {
+  int32_t* flags;
+  TG_HIP(S.get(&flags, 1));
+  TG_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), st));
+  int32_t h = 0;
+  k_validate_rows<<<grid_for(n + 1, 256, 8192), 256, 0, st>>>(n, nnz, rp, ty, L, flags);
+  TG_LAUNCHED("k_validate_rows");
+  TG_HIP(hipMemcpyAsync(&h, flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  if (h & TG_VFLAG_ROWPTR) return fail(TG_ERR_INVALID_GRAPH, "row_ptr is not a valid offset array for nnz slots");
+  if (h & TG_VFLAG_TYPE) return fail(TG_ERR_TYPE_RANGE, "a node type is >= L");
+  k_validate_slots<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, rp, ci, flags);
+  TG_LAUNCHED("k_validate_slots");
+  TG_HIP(hipMemcpyAsync(&h, flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  if (h & TG_VFLAG_RANGE) return fail(TG_ERR_INVALID_GRAPH, "a column index is outside [0, n)");
+  if (h & TG_VFLAG_SELFLOOP) return fail(TG_ERR_INVALID_GRAPH, "self loop");
+  if (h & TG_VFLAG_ORDER) return fail(TG_ERR_INVALID_GRAPH, "a row is not strictly increasing (unsorted or duplicate)");
+  k_validate_symmetry<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, rp, ci, flags);
+  TG_LAUNCHED("k_validate_symmetry");
+  TG_HIP(hipMemcpyAsync(&h, flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  if (h & TG_VFLAG_ASYMMETRIC) return fail(TG_ERR_INVALID_GRAPH, "edge stored in one direction only");
+  return TG_OK;
+}
+
+tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L,
+                     uint64_t* global_counts, uint64_t* edge_counts, int32_t* edge_endpoints,
+                     const tg_options* opt_in, hipStream_t st) {
+  tg_options opt;
+  tg_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31))
+    return fail(TG_ERR_INVALID_ARG, "n and nnz must be in [0, 2^31)");
+  if (n * (int64_t)L >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "n * L must be below 2^31");
+  if (!rp || !global_counts || (nnz > 0 && !ci) || (n > 0 && !ty))
+    return fail(TG_ERR_INVALID_ARG, "null input or output pointer");
+  if (nnz % 2) return fail(TG_ERR_INVALID_GRAPH, "nnz is odd: some edge is stored in one direction only");
+  if (opt.schedule < TG_SCHED_NONE || opt.schedule > TG_SCHED_LEARNED)
+    return fail(TG_ERR_INVALID_ARG, "unknown schedule");
+  if (opt.schedule == TG_SCHED_LEARNED && !opt.model)
+    return fail(TG_ERR_INVALID_ARG, "TG_SCHED_LEARNED needs a cost model");
+  const int64_t m = nnz / 2;
+  const int64_t eb = opt.edge_begin, ee = opt.edge_end < 0 ? m : opt.edge_end;
+  if (eb < 0 || eb > ee || ee > m) return fail(TG_ERR_INVALID_ARG, "edge range outside [0, m]");
+  const int64_t K = nkeys(L), P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
+  keep_pool_cached();
+  Scratch S(st);
+  PhaseTimer timer(st, opt.phase_ms);
+
+  k_fill_u64<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, K, 0);
+  TG_LAUNCHED("k_fill_u64");
+  if (opt.validate && n > 0) {
+    tg_status vs = validate_graph(S, st, n, nnz, rp, ci, ty, L);
+    if (vs != TG_OK) return vs;
+  } else if (opt.validate) {
+    int32_t h0 = -1;
+    TG_HIP(hipMemcpyAsync(&h0, rp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (h0 != 0 || nnz != 0) return fail(TG_ERR_INVALID_GRAPH, "empty graph must have row_ptr[0] == 0 and nnz == 0");
+  }
+  if (m == 0) return TG_OK;
+
+  Work W;
+  TG_HIP(S.get(&W.deg, n));
+  TG_HIP(S.get(&W.D, n * L));
+  TG_HIP(S.get(&W.n_upper, n));
+  TG_HIP(S.get(&W.n_out, n));
+  TG_HIP(S.get(&W.wedge_work, n));
+  TG_HIP(S.get(&W.nbr_deg_sum, n));
+  TG_HIP(S.get(&W.upper_off, n + 1));
+  TG_HIP(S.get(&W.out_off, n + 1));
+  TG_HIP(S.get(&W.ei, m));
+  TG_HIP(S.get(&W.ej, m));
+  TG_HIP(S.get(&W.s2e, nnz));
+  TG_HIP(S.get(&W.out_col, m));
+  TG_HIP(S.get(&W.tau, m * L));
+  TG_HIP(S.get(&W.Pn, n * LL));
+  TG_HIP(S.get(&W.Un, n * LL));
+  TG_HIP(S.get(&W.C4, m * P));
+  TG_HIP(S.get(&W.elist, m));
+  TG_HIP(S.get(&W.nlist, n));
+  TG_HIP(S.get(&W.counters, 256));
+
+  // ---- prep
+  timer.mark(TG_PHASE_PREP);
+  k_degree<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, rp, W.deg);
+  TG_LAUNCHED("k_degree");
+  k_node_stats<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, ty, L, W.D, W.n_upper, W.n_out, W.wedge_work,
+                                               W.nbr_deg_sum);
+  TG_LAUNCHED("k_node_stats");
+  if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
+  if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
+  k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
+                                               W.s2e, W.out_col);
+  TG_LAUNCHED("k_fill_edges");
+
+  // ---- typed triangles per edge, node tables
+  timer.mark(TG_PHASE_TAU);
+  k_tau<<<grid_for(m, 4), 256, 0, st>>>(m, nullptr, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  TG_LAUNCHED("k_tau");
+  timer.mark(TG_PHASE_TABLES);
+  k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D, W.tau,
+                                                                                     W.s2e, W.Pn, W.Un);
+  TG_LAUNCHED("k_node_tables");
+
+  // ---- schedule: edge classes and cost buckets, node tiers
+  timer.mark(TG_PHASE_SCHEDULE);
+  const int mode = opt.schedule == TG_SCHED_NONE ? 0 : (opt.schedule == TG_SCHED_DEGREE ? 1 : 2);
+  const float* pred = nullptr;
+  if (mode == 2) {
+    float* p;
+    TG_HIP(S.get(&p, m));
+    tg_status s = tg_internal_predict_costs(opt.model, n, rp, ci, ty, L, W, m, p, st);
+    if (s != TG_OK) return s;
+    pred = p;
+  }
+  int32_t* cnt = W.counters;           // [0,128) edge bins, [128,132) node tiers, [132] max heavy |T|
+  TG_HIP(hipMemsetAsync(cnt, 0, 256 * sizeof(int32_t), st));
+  k_edge_bin_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, mode, pred, cnt,
+                                                           (uint32_t*)(cnt + 132));
+  TG_LAUNCHED("k_edge_bin_count");
+  k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128);
+  TG_LAUNCHED("k_node_tier_count");
+  int32_t h_cnt[256];
+  TG_HIP(hipMemcpyAsync(h_cnt, cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  int32_t cur[256];
+  memset(cur, 0, sizeof(cur));
+  int64_t acc = 0;
+  for (int b = 0; b < 128; ++b) { cur[b] = (int32_t)acc; acc += h_cnt[b]; }
+  int64_t n_heavy = 0;
+  for (int b = 64; b < 128; ++b) n_heavy += h_cnt[b];
+  const int64_t n_light_edges = m - n_heavy;
+  int64_t nacc = 0;
+  for (int t = 0; t < 4; ++t) { cur[128 + t] = (int32_t)nacc; nacc += h_cnt[128 + t]; }
+  const int64_t max_t_heavy = (uint32_t)h_cnt[132];
+  TG_HIP(hipMemcpyAsync(cnt, cur, sizeof(cur), hipMemcpyHostToDevice, st));
+  k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, mode, pred, cnt,
+                                                             W.elist);
+  TG_LAUNCHED("k_edge_bin_scatter");
+  k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128, W.nlist);
+  TG_LAUNCHED("k_node_tier_scatter");
+
+  // ---- non-induced typed 4-cycles per edge
+  timer.mark(TG_PHASE_CYCLES);
+  k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
+  TG_LAUNCHED("k_fill_u64");
+  const int64_t n_t1 = h_cnt[129], n_t2 = h_cnt[130], n_t3 = h_cnt[131];
+  if (n_t1 > 0) {
+    k_c4_hash<1, 8><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[129], rp, ci, W.deg, ty, L, W.s2e,
+                                                             W.C4);
+    TG_LAUNCHED("k_c4_hash<1>");
+  }
+  if (n_t2 > 0) {
+    k_c4_hash<4, 12><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[130], rp, ci, W.deg, ty, L, W.s2e,
+                                                              W.C4);
+    TG_LAUNCHED("k_c4_hash<4>");
+  }
+  if (n_t3 > 0) {
+    // heaviest nodes first, in groups sharing one launch per phase
+    std::vector<int32_t> hx(n_t3);
+    std::vector<uint64_t> hw(n_t3);
+    std::vector<int32_t> hd(n_t3);
+    TG_HIP(hipMemcpyAsync(hx.data(), W.nlist + cur[131], n_t3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    // gather W and degree of the listed nodes on the host side of the copy
+    {
+      int32_t* d_idx;
+      uint64_t* d_w;
+      int32_t* d_d;
+      TG_HIP(S.get(&d_idx, n_t3));
+      TG_HIP(S.get(&d_w, n_t3));
+      TG_HIP(S.get(&d_d, n_t3));
+      k_gather_node_info<<<grid_for(n_t3, 256, 8192), 256, 0, st>>>(n_t3, W.nlist + cur[131], W.wedge_work, W.deg,
+                                                                    d_w, d_d);
+      TG_LAUNCHED("k_gather_node_info");
+      TG_HIP(hipMemcpyAsync(hw.data(), d_w, n_t3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipMemcpyAsync(hd.data(), d_d, n_t3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<int64_t> order(n_t3);
+    for (int64_t q = 0; q < n_t3; ++q) order[q] = q;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return hw[a] != hw[b] ? hw[a] > hw[b] : hx[a] < hx[b];
+    });
+    const int64_t stride = n * L + n;
+    int64_t G = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
+    G = std::max<int64_t>(1, std::min<int64_t>(G, std::min<int64_t>(256, n_t3)));
+    const int64_t ngroups = (n_t3 + G - 1) / G;
+    std::vector<int32_t> gx(n_t3);
+    std::vector<int64_t> gp(ngroups * (G + 1), 0);
+    for (int64_t g = 0; g < ngroups; ++g) {
+      int64_t acc2 = 0;
+      for (int64_t q = 0; q < G; ++q) {
+        int64_t idx = g * G + q;
+        gp[g * (G + 1) + q] = acc2;
+        if (idx < n_t3) {
+          gx[idx] = hx[order[idx]];
+          acc2 += hd[order[idx]];
+        }
+      }
+      gp[g * (G + 1) + G] = acc2;
+    }
+    int32_t* d_gx;
+    int64_t* d_gp;
+    uint32_t* dense;
+    TG_HIP(S.get(&d_gx, n_t3));
+    TG_HIP(S.get(&d_gp, ngroups * (G + 1)));
+    TG_HIP(S.get(&dense, G * stride));
+    TG_HIP(hipMemcpyAsync(d_gx, gx.data(), n_t3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    TG_HIP(hipMemcpyAsync(d_gp, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
+    TG_LAUNCHED("k_fill_u32");
+    for (int64_t g = 0; g < ngroups; ++g) {
+      const int Gg = (int)std::min<int64_t>(G, n_t3 - g * G);
+      const int64_t slots = gp[g * (G + 1) + Gg];
+      for (int phase = 0; phase < 3; ++phase) {
+        k_c4_group<<<grid_for(slots, 4), 256, 0, st>>>(phase, Gg, d_gx + g * G, d_gp + g * (G + 1), dense, stride, n,
+                                                      rp, ci, W.deg, ty, L, W.s2e, W.C4);
+        TG_LAUNCHED("k_c4_group");
+      }
+    }
+  }
+
+  // ---- per-edge combine
+  timer.mark(TG_PHASE_COMBINE);
+  EdgeArgs A;
+  A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
+  A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
+  A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
+  const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
+  if (n_light_edges > 0) {
+    const size_t lds = gbytes + 4 * 4 * LL * sizeof(uint64_t) + 4 * TG_T_WAVE_CAP * (sizeof(int32_t) + 1);
+    k_combine_wave<<<grid_for(n_light_edges, 4, 2048), 256, lds, st>>>(A, n_light_edges, W.elist, (int)K);
+    TG_LAUNCHED("k_combine_wave");
+  }
+  if (n_heavy > 0) {
+    const unsigned grid = grid_for(n_heavy, 1, 1024);
+    int32_t* t_over = nullptr;
+    int64_t t_cap = 0;
+    if (max_t_heavy > TG_T_WG_CAP) {
+      t_cap = max_t_heavy;
+      TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
+    }
+    const size_t lds = gbytes + 4 * LL * sizeof(uint64_t) + 4 * sizeof(int32_t) +
+                       TG_T_WG_CAP * (sizeof(int32_t) + 1);
+    k_combine_wg<<<grid, 256, lds, st>>>(A, n_heavy, W.elist + n_light_edges, (int)K, t_over, t_cap);
+    TG_LAUNCHED("k_combine_wg");
+  }
+
+  // ---- Eq. 17 and outputs
+  timer.mark(TG_PHASE_FINALIZE);
+  int32_t* flag = cnt + 200;
+  TG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+  k_finalize<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, L, flag);
+  TG_LAUNCHED("k_finalize");
+  if (edge_endpoints && ee > eb) {
+    k_copy_endpoints<<<grid_for(ee - eb, 256, 8192), 256, 0, st>>>(eb, ee, W.ei, W.ej, edge_endpoints);
+    TG_LAUNCHED("k_copy_endpoints");
+  }
+  timer.mark(TG_NUM_PHASES);
+  if (opt.check) {
+    int32_t hf = 0;
+    TG_HIP(hipMemcpyAsync(&hf, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (hf) return fail(TG_ERR_INTERNAL, "a global sum is not a multiple of its shape's edge count");
+  }
+  timer.finish();
+  return TG_OK;
+}
+
+tg_status tg_internal_predict_costs(const tg_cost_model*, int64_t, const int32_t*, const int32_t*, const uint8_t*,
+                                    int, const tg::Work&, int64_t, float*, hipStream_t) {
+  return fail(TG_ERR_INVALID_ARG, "learned schedule is not available in this build");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI --
+
+extern "C" {
+
+void tg_options_default(tg_options* opt) {
+  if (!opt) return;
+  opt->schedule = TG_SCHED_DEGREE;
+  opt->model = nullptr;
+  opt->validate = 0;
+  opt->check = 1;
+  opt->edge_begin = 0;
+  opt->edge_end = -1;
+  opt->phase_ms = nullptr;
+}
+
+size_t tg_num_keys(int L) { return (L < 1 || L > 16) ? 0 : (size_t)nkeys(L); }
+
+size_t tg_edge_row_width(int L) { return (L < 1 || L > 16) ? 0 : (size_t)(2 * L + 3 * L * (L + 1)); }
+
+tg_status tg_key_encode(int L, int shape, const uint8_t types[4], size_t* key) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (shape < 0 || shape >= TG_NUM_SHAPES || !types || !key) return fail(TG_ERR_INVALID_ARG, "bad shape or pointer");
+  const int k = shape < 2 ? 3 : 4;
+  int v[4];
+  for (int a = 0; a < k; ++a) {
+    if (types[a] >= L) return fail(TG_ERR_TYPE_RANGE, "type >= L");
+    v[a] = types[a];
+  }
+  std::sort(v, v + k);
+  int64_t r = 0;
+  for (int a = 0; a < k; ++a) r += binom(v[a] + a, a + 1);
+  const int64_t off = shape <= 2 ? shape * per_shape(L, 3) : 2 * per_shape(L, 3) + (shape - 2) * per_shape(L, 4);
+  *key = (size_t)(off + r);
+  return TG_OK;
+}
+
+tg_status tg_key_decode(int L, size_t key, int* shape, uint8_t types[4]) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (!shape || !types || key >= (size_t)nkeys(L)) return fail(TG_ERR_INVALID_ARG, "bad key or pointer");
+  const int64_t c3 = per_shape(L, 3), c4 = per_shape(L, 4);
+  int64_t k = (int64_t)key;
+  int h, K;
+  if (k < 2 * c3) { h = (int)(k / c3); k -= h * c3; K = 3; }
+  else { h = 2 + (int)((k - 2 * c3) / c4); k -= 2 * c3 + (h - 2) * c4; K = 4; }
+  // colex unranking: the largest element first
+  int v[4] = {0, 0, 0, 0};
+  for (int a = K - 1; a >= 0; --a) {
+    int x = a;  // element x = type + a, find the largest with binom(x, a+1) <= k
+    while (binom(x + 1, a + 1) <= k) ++x;
+    k -= binom(x, a + 1);
+    v[a] = x - a;
+  }
+  *shape = h;
+  for (int a = 0; a < 4; ++a) types[a] = a < K ? (uint8_t)v[a] : (uint8_t)0xFF;
+  return TG_OK;
+}
+
+tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_t* key) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (phi_i >= L || phi_j >= L) return fail(TG_ERR_TYPE_RANGE, "type >= L");
+  const int64_t P = (int64_t)L * (L + 1) / 2;
+  if (!key || col >= (size_t)(2 * L + 6 * P)) return fail(TG_ERR_INVALID_ARG, "bad column or pointer");
+  uint8_t ty[4] = {phi_i, phi_j, 0, 0};
+  int shape;
+  if ((int64_t)col < 2 * L) {
+    shape = (int)col / L;
+    ty[2] = (uint8_t)(col % L);
+  } else {
+    const int64_t c = (int64_t)col - 2 * L;
+    shape = 2 + (int)(c / P);
+    const int64_t p = c % P;
+    int u = 0;
+    while ((int64_t)(u + 1) * (u + 2) / 2 <= p) ++u;
+    ty[2] = (uint8_t)(p - (int64_t)u * (u + 1) / 2);
+    ty[3] = (uint8_t)u;
+  }
+  return tg_key_encode(L, shape, ty, key);
+}
+
+tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                   const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
+                   int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream) {
+  try {
+    return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, edge_counts, edge_endpoints, opt,
+                      stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+const char* tg_status_string(tg_status s) {
+  switch (s) {
+    case TG_OK: return "TG_OK";
+    case TG_ERR_INVALID_ARG: return "TG_ERR_INVALID_ARG";
+    case TG_ERR_INVALID_GRAPH: return "TG_ERR_INVALID_GRAPH";
+    case TG_ERR_TYPE_RANGE: return "TG_ERR_TYPE_RANGE";
+    case TG_ERR_UNSUPPORTED_L: return "TG_ERR_UNSUPPORTED_L";
+    case TG_ERR_OUT_OF_MEMORY: return "TG_ERR_OUT_OF_MEMORY";
+    case TG_ERR_INTERNAL: return "TG_ERR_INTERNAL";
+    case TG_ERR_HIP: return "TG_ERR_HIP";
+  }
+  return "unknown status";
+}
+
+const char* tg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

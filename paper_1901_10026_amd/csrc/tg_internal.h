@@ -1,0 +1,83 @@
+// Internal declarations shared by the kernel and API translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tg_device.h"
+
+// validation flags (device-side, OR-ed together)
+#define TG_VFLAG_ROWPTR 1
+#define TG_VFLAG_TYPE 2
+#define TG_VFLAG_RANGE 4
+#define TG_VFLAG_SELFLOOP 8
+#define TG_VFLAG_ORDER 16
+#define TG_VFLAG_ASYMMETRIC 32
+
+// light/heavy limits
+#define TG_C4_LIGHT_W 128     // wedge work handled by one wavefront with an LDS hash
+#define TG_C4_LIGHT_CAP 256
+#define TG_C4_MED_W 2048      // wedge work handled by one workgroup with an LDS hash
+#define TG_C4_MED_CAP 4096
+#define TG_T_WAVE_CAP 128     // |T_ij| handled by one wavefront
+#define TG_T_WG_CAP 4096      // |T_ij| kept in LDS by a workgroup (larger: global scratch)
+#define TG_GACC_MAX_KEYS 5120 // global keys accumulated in LDS per workgroup
+
+namespace tg {
+
+struct Graph {
+  int64_t n, nnz, m;
+  int L;
+  const int32_t* rp;
+  const int32_t* ci;
+  const uint8_t* ty;
+};
+
+// Device scratch of one tg_count call.
+struct Work {
+  int32_t* deg;          // n
+  uint32_t* D;           // n*L typed degree
+  int32_t* n_upper;      // n
+  int32_t* n_out;        // n
+  uint64_t* wedge_work;  // n   W(v)
+  uint64_t* nbr_deg_sum; // n   s(v)
+  int32_t* upper_off;    // n+1
+  int32_t* out_off;      // n+1
+  int32_t* scan_tmp;     // blocks + 1
+  int32_t* ei;           // m
+  int32_t* ej;           // m
+  int32_t* s2e;          // nnz
+  int32_t* out_col;      // m
+  uint32_t* tau;         // m*L
+  uint64_t* Pn;          // n*L*L
+  uint64_t* Un;          // n*L*L
+  uint64_t* C4;          // m*P
+  int32_t* elist;        // m     edge ids grouped by class and bucket
+  int32_t* nlist;        // n     node ids grouped by tier
+  int32_t* counters;     // small
+  uint64_t* ecost;       // m     per-edge cost used for binning
+};
+
+struct EdgeArgs {
+  const int32_t* rp;
+  const int32_t* ci;
+  const uint8_t* ty;
+  const int32_t* deg;
+  const uint32_t* D;
+  const int32_t* ei;
+  const int32_t* ej;
+  const int32_t* s2e;
+  const int32_t* out_off;
+  const int32_t* out_col;
+  const uint32_t* tau;
+  const uint64_t* Pn;
+  const uint64_t* Un;
+  const uint64_t* C4;
+  int L;
+  uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or null
+  int64_t edge_begin, edge_end;
+  uint64_t* global_sums;  // K(L)
+  int gacc_in_lds;
+};
+
+}  // namespace tg

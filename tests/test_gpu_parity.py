@@ -1,0 +1,166 @@
+"""Parity of the gfx950 path (through the C-ABI) with the oracle: bit-exact
+per-edge rows and global counts."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from _gpu import gpu_count, note
+from _graphs import all_graphs, complete, complete_bipartite, csr_from_edges, cycle, star
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_same(got_rows, got_glob, want_rows, want_glob, what):
+    if want_glob is not None:
+        assert np.array_equal(got_glob, want_glob), f"{what}: global counts differ"
+    if want_rows is not None:
+        bad = np.nonzero((got_rows != want_rows).any(axis=1))[0]
+        assert len(bad) == 0, f"{what}: {len(bad)} edge rows differ, first edge {bad[:5]}"
+
+
+def test_tiny_graphs_match_brute_force():
+    for idx in range(200):
+        g = graphgen.tiny_graph(idx)
+        note(f"tiny{idx} n={g.n} m={g.m} L={g.L}")
+        rb, _, gb = oracle.brute(g.row_ptr, g.col_idx, g.types, g.L)
+        for sched in ("none", "degree"):
+            gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, schedule=sched, validate=True)
+            assert_same(rr, gg, rb, gb, f"tiny{idx}/{sched}")
+
+
+def test_every_graph_on_five_nodes():
+    ty = np.array([0, 1, 0, 1, 2], np.uint8)
+    for q, (rp, ci) in enumerate(all_graphs(5)):
+        if len(ci) == 0:
+            continue
+        rb, _, gb = oracle.brute(rp, ci, ty, 3)
+        gg, rr, _ = gpu_count(rp, ci, ty, 3)
+        assert_same(rr, gg, rb, gb, f"5-node graph {q}")
+
+
+def test_chung_lu_2k_all_edges():
+    g = graphgen.chung_lu_small()
+    note(f"cl-2k n={g.n} m={g.m}")
+    want_rows, want_glob = oracle.count_all(g.row_ptr, g.col_idx, g.types, g.L, nthreads=8)
+    for sched in ("none", "degree"):
+        gg, rr, ends = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, schedule=sched, endpoints=True)
+        assert_same(rr, gg, want_rows, want_glob, f"cl-2k/{sched}")
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    assert np.array_equal(ends[:, 0], ei) and np.array_equal(ends[:, 1], ej)
+
+
+def test_edge_ranges_and_global_only():
+    g = graphgen.chung_lu_small()
+    gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    for e0, e1 in ((0, 1), (17, 900), (g.m - 5, g.m), (300, 300)):
+        g2, r2, ends = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, edge_range=(e0, e1), endpoints=True)
+        assert np.array_equal(g2, gg)
+        assert np.array_equal(r2, rr[e0:e1])
+        assert ends.shape == (e1 - e0, 2)
+    g3, r3, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, per_edge=False)
+    assert r3 is None and np.array_equal(g3, gg)
+
+
+@pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5)])
+def test_complete_graphs_hit_heavy_paths(n, L):
+    # |T_ij| = n - 2 exceeds one wavefront's capacity for n >= 131, and the
+    # highest-ranked nodes carry enough wedges for the grouped dense path.
+    rp, ci = complete(n)
+    ty = (np.arange(n) % L).astype(np.uint8)
+    note(f"K_{n} L={L}")
+    gg, rr, _ = gpu_count(rp, ci, ty, L)
+    c = np.bincount(ty, minlength=L)
+    for k, shape in ((3, 1), (4, 7)):
+        for ms in itertools.combinations_with_replacement(range(L), k):
+            want = 1
+            for t in range(L):
+                want *= math.comb(int(c[t]), ms.count(t))
+            assert gg[oracle.key(L, shape, ms)] == want
+    assert gg.sum() == math.comb(n, 3) + math.comb(n, 4)
+    ei, ej = oracle.canonical_edges(rp, ci)
+    sample = np.linspace(0, len(ei) - 1, 40).astype(np.int64)
+    want_rows, _ = oracle.count_edges(rp, ci, ty, L, ei[sample], ej[sample])
+    assert np.array_equal(rr[sample], want_rows)
+
+
+@pytest.mark.parametrize("s", [3, 100, 5000])
+def test_big_star(s):
+    rp, ci = star(s)
+    ty = (np.arange(s + 1) % 2).astype(np.uint8)
+    note(f"star {s}")
+    gg, rr, _ = gpu_count(rp, ci, ty, 2)
+    rb_rows, glob = oracle.count_all(rp, ci, ty, 2)
+    assert_same(rr, gg, rb_rows, glob, f"star{s}")
+
+
+@pytest.mark.parametrize("a,b", [(2, 3), (3, 3000), (40, 60)])
+def test_complete_bipartite(a, b):
+    rp, ci = complete_bipartite(a, b)
+    ty = np.array([0] * a + [1] * b, np.uint8)
+    note(f"K_{a},{b}")
+    gg, rr, _ = gpu_count(rp, ci, ty, 2)
+    want_rows, want_glob = oracle.count_all(rp, ci, ty, 2, nthreads=8)
+    assert_same(rr, gg, want_rows, want_glob, f"K{a},{b}")
+    assert gg[oracle.key(2, 4, [0, 0, 1, 1])] == math.comb(a, 2) * math.comb(b, 2)
+
+
+def test_cycles_and_l1():
+    for n in (4, 5, 9):
+        rp, ci = cycle(n)
+        ty = np.zeros(n, np.uint8)
+        rb, _, gb = oracle.brute(rp, ci, ty, 1)
+        gg, rr, _ = gpu_count(rp, ci, ty, 1)
+        assert_same(rr, gg, rb, gb, f"C{n}")
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_many_types(L):
+    # dense random graph with all types present; L = 16 also exercises global
+    # accumulation outside LDS
+    rp, ci = graphgen.gnp(60, 0.4, 9)
+    ty = (np.arange(60) % L).astype(np.uint8)
+    want_rows, want_glob = oracle.count_all(rp, ci, ty, L, nthreads=8)
+    gg, rr, _ = gpu_count(rp, ci, ty, L)
+    assert_same(rr, gg, want_rows, want_glob, f"gnp60/L{L}")
+
+
+def test_empty_and_edgeless_graphs():
+    rp = np.zeros(1, np.int32)
+    gg, rr, _ = gpu_count(rp, np.zeros(0, np.int32), np.zeros(0, np.uint8), 3)
+    assert (gg == 0).all() and rr.shape == (0, 42)
+    rp = np.zeros(6, np.int32)
+    gg, rr, _ = gpu_count(rp, np.zeros(0, np.int32), np.zeros(5, np.uint8), 2, validate=True)
+    assert (gg == 0).all() and rr.shape == (0, 22)
+
+
+@pytest.mark.parametrize("case,status", [
+    ("unsorted", "TG_ERR_INVALID_GRAPH"), ("asymmetric", "TG_ERR_INVALID_GRAPH"),
+    ("selfloop", "TG_ERR_INVALID_GRAPH"), ("duplicate", "TG_ERR_INVALID_GRAPH"),
+    ("range", "TG_ERR_INVALID_GRAPH"), ("rowptr", "TG_ERR_INVALID_GRAPH"), ("type", "TG_ERR_TYPE_RANGE"),
+])
+def test_validation_reports_bad_graphs(case, status):
+    import paper_1901_10026_amd as tg
+    rp, ci = csr_from_edges(5, [(0, 1), (0, 2), (1, 2), (2, 3), (3, 4)])
+    rp, ci = rp.copy(), ci.copy()
+    ty = np.zeros(5, np.uint8)
+    if case == "unsorted":
+        ci[rp[2]], ci[rp[2] + 1] = ci[rp[2] + 1], ci[rp[2]]
+    elif case == "asymmetric":
+        ci[rp[3]:rp[4]] = [1, 2]   # row 3 was [2, 4]: adds 3->1 without 1->3, drops 3->4
+    elif case == "selfloop":
+        ci[rp[4]] = 4
+    elif case == "duplicate":
+        ci[rp[2] + 1] = ci[rp[2]]
+    elif case == "range":
+        ci[rp[4]] = 9
+    elif case == "rowptr":
+        rp[2] = rp[3] + 1
+    elif case == "type":
+        ty[3] = 7
+    with pytest.raises(tg.TGError) as e:
+        gpu_count(rp, ci, ty, 2, validate=True)
+    assert e.value.name == status, str(e.value)
