@@ -1,0 +1,102 @@
+"""Full-size parity at the benchmark's workload (Chung-Lu, 1M nodes, ~9.8M
+edges, L=5) in the benchmark's launch configuration: sampled per-edge rows
+against the oracle, plus properties that hold at any size."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from _gpu import note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_1m()
+    note(f"cl-1m n={g.n} m={g.m} L={g.L}")
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    glob, rows, _ = tg.count(rp, ci, ty, g.L, per_edge=True, schedule="degree")
+    torch.cuda.synchronize()
+    return g, rp, ci, ty, glob, rows
+
+
+def stratified_sample(g, per_decile=12, heaviest=8, seed=7):
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    d = np.diff(g.row_ptr).astype(np.int64)
+    cost = d[ei] * d[ej]
+    order = np.argsort(cost, kind="stable")
+    rng = np.random.default_rng(seed)
+    picks = []
+    for part in np.array_split(order, 10):
+        picks.extend(rng.choice(part, size=per_decile, replace=False))
+    picks.extend(order[-heaviest:])
+    return np.unique(np.array(picks, dtype=np.int64)), ei, ej
+
+
+def test_sampled_rows_match_oracle(big):
+    g, _, _, _, _, rows = big
+    idx, ei, ej = stratified_sample(g)
+    note(f"oracle on {len(idx)} sampled edges")
+    want, _ = oracle.count_edges(g.row_ptr, g.col_idx, g.types, g.L, ei[idx], ej[idx], nthreads=16)
+    got = rows[idx.tolist()].cpu().numpy().view(np.uint64) if False else \
+        rows.index_select(0, __import__("torch").from_numpy(idx).to(rows.device)).cpu().numpy().view(np.uint64)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} sampled edges differ: {idx[bad][:5]}"
+
+
+def test_global_equals_row_sums(big):
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, _, _, ty, glob, rows = big
+    L = g.L
+    R = tg.edge_row_width(L)
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    pair = torch.from_numpy((g.types[ei].astype(np.int64) * L + g.types[ej]).astype(np.int64)).to(rows.device)
+    r64 = rows.view(torch.int64)
+    acc = np.zeros(tg.num_keys(L), dtype=object)
+    for c in range(L * L):
+        sel = (pair == c).nonzero().flatten()
+        if sel.numel() == 0:
+            continue
+        colsum = r64.index_select(0, sel).sum(0).cpu().numpy()
+        a, b = divmod(c, L)
+        for col in range(R):
+            acc[tg.edge_row_key(L, a, b, col)] += int(colsum[col])
+    gl = glob.cpu().numpy().view(np.uint64)
+    div = [2, 3, 3, 3, 4, 4, 5, 6]
+    for k in range(len(acc)):
+        shape = tg.key_decode(L, k)[0]
+        assert acc[k] % div[shape] == 0
+        assert acc[k] // div[shape] == int(gl[k]), f"key {k}"
+
+
+def test_typed_counts_partition_untyped_counts(big):
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, glob, _ = big
+    zeros = torch.zeros_like(ty)
+    g1, _, _ = tg.count(rp, ci, zeros, 1, per_edge=False, schedule="none")
+    torch.cuda.synchronize()
+    g1 = g1.cpu().numpy().view(np.uint64)
+    gl = glob.cpu().numpy().view(np.uint64)
+    per_shape = np.zeros(8, dtype=object)
+    for k in range(len(gl)):
+        per_shape[tg.key_decode(g.L, k)[0]] += int(gl[k])
+    assert [int(x) for x in per_shape] == [int(x) for x in g1]
+
+
+def test_schedules_agree_at_full_size(big):
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, glob, rows = big
+    g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, schedule="none")
+    torch.cuda.synchronize()
+    assert torch.equal(g2.view(torch.int64), glob.view(torch.int64))
+    assert torch.equal(r2.view(torch.int64), rows.view(torch.int64))
