@@ -80,9 +80,25 @@ typedef enum { TG_SCHED_NONE = 0, TG_SCHED_DEGREE = 1, TG_SCHED_LEARNED = 2 } tg
 
 typedef struct tg_cost_model tg_cost_model;
 
+/* Launch-shape choices (defaults from tg_tuning_default; tg_autotune picks
+ * them by timing).  Counts never depend on them. */
+typedef struct {
+  int32_t heavy_min_degree;   /* tg_count: edges with min(d_i, d_j) above this use one workgroup */
+  int32_t heavy_log2_cost;    /* tg_count: edges whose log2 schedule cost exceeds this use one
+                                 workgroup (64 = never) */
+  int32_t combine_grid;       /* tg_count: workgroups of the one-wavefront-per-edge launch */
+  int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
+                                 (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
+                                 3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */
+} tg_tuning;
+
+/* Fills *t with the library's defaults. */
+void tg_tuning_default(tg_tuning* t);
+
 typedef struct {
   tg_schedule schedule;        /* default TG_SCHED_DEGREE */
   const tg_cost_model* model;  /* required for TG_SCHED_LEARNED, else ignored */
+  const tg_tuning* tuning;     /* NULL: defaults */
   int validate;                /* 1: O(m) device check of the CSR and types (synchronises) */
   int check;                   /* 1: synchronise and verify global divisibility (default 1) */
   int64_t edge_begin;          /* per-edge rows are written for canonical edges */
@@ -144,6 +160,30 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
 tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
                    int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream);
+
+/* Counts many small typed graphs in one call (the batch form of tg_count's
+ * global counts, Eq. 17 per graph).  Graph g has n_g = node_off[g+1] -
+ * node_off[g] <= 512 nodes with local ids, L_g = L_per_graph[g] in [1, 8]
+ * types, and writes tg_num_keys(L_g) counts at global_counts + key_off[g].
+ *   G               number of graphs
+ *   node_off        device, int64[G+1], node_off[0] = 0
+ *   slot_off        device, int64[G+1], CSR slots of graph g are
+ *                   [slot_off[g], slot_off[g+1]) of col_idx_local
+ *   row_ptr_local   device, int32[node_off[G] + G]: graph g's row pointer
+ *                   (n_g + 1 entries starting at 0) at node_off[g] + g
+ *   col_idx_local   device, int32[slot_off[G]], local node ids
+ *   node_types      device, uint8[node_off[G]]
+ *   L_per_graph     device, uint8[G]
+ *   key_off         device, int64[G+1], key_off[g+1] - key_off[g] = tg_num_keys(L_g)
+ *   global_counts   device, uint64[key_off[G]]
+ * The call reads the graph sizes back to the host (one synchronisation),
+ * buckets graphs by size, and replays a cached HIP graph of one persistent
+ * launch per bucket.  Same conventions and errors as tg_count; only `check`
+ * and `tuning` of opt are used. */
+tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
+                         const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
+                         const int64_t* key_off, uint64_t* global_counts, const tg_options* opt,
+                         hipStream_t stream);
 
 /* Human-readable name of a status code (static string). */
 const char* tg_status_string(tg_status s);

@@ -54,8 +54,36 @@ def declared_symbols():
     return sorted(set(re.findall(r"\b(tg_[a-z0-9_]+)\s*\(", text)))
 
 
+class Tuning(ctypes.Structure):
+    """Launch-shape choices (tg_tuning); counts never depend on them."""
+    _fields_ = [("heavy_min_degree", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
+                ("combine_grid", ctypes.c_int32), ("batch_variant", ctypes.c_int32 * 9)]
+
+    def as_dict(self):
+        return {"heavy_min_degree": self.heavy_min_degree, "heavy_log2_cost": self.heavy_log2_cost,
+                "combine_grid": self.combine_grid, "batch_variant": list(self.batch_variant)}
+
+    @classmethod
+    def default(cls):
+        t = cls()
+        lib().tg_tuning_default(ctypes.byref(t))
+        return t
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls.default()
+        for k in ("heavy_min_degree", "heavy_log2_cost", "combine_grid"):
+            if k in d:
+                setattr(t, k, int(d[k]))
+        if "batch_variant" in d:
+            for q, v in enumerate(d["batch_variant"]):
+                t.batch_variant[q] = int(v)
+        return t
+
+
 class _Options(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_int), ("model", ctypes.c_void_p), ("validate", ctypes.c_int),
+    _fields_ = [("schedule", ctypes.c_int), ("model", ctypes.c_void_p), ("tuning", ctypes.c_void_p),
+                ("validate", ctypes.c_int),
                 ("check", ctypes.c_int), ("edge_begin", ctypes.c_int64), ("edge_end", ctypes.c_int64),
                 ("phase_ms", ctypes.c_void_p)]
 
@@ -86,6 +114,10 @@ def lib():
     L.tg_edge_row_key.argtypes = [i32, ctypes.c_uint8, ctypes.c_uint8, sz, ctypes.POINTER(sz)]
     L.tg_count.restype = i32
     L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_count_batch.restype = i32
+    L.tg_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_tuning_default.restype = None
+    L.tg_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
     L.tg_status_string.restype = ctypes.c_char_p
     L.tg_status_string.argtypes = [i32]
     L.tg_last_error.restype = ctypes.c_char_p
@@ -133,7 +165,7 @@ def _stream_handle(torch, device):
 
 
 def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedule="degree", validate=False,
-          check=True, edge_range=None, model=None, out_global=None, out_edges=None, phase_ms=None):
+          check=True, edge_range=None, model=None, out_global=None, out_edges=None, phase_ms=None, tuning=None):
     """Counts every typed 3/4-node graphlet of one graph with tg_count.
 
     row_ptr, col_idx (int32) and types (uint8) are CUDA (HIP) tensors on the
@@ -166,6 +198,7 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     lib().tg_options_default(ctypes.byref(opt))
     opt.schedule = SCHEDULES[schedule]
     opt.model = model.handle if model is not None else None
+    opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
     opt.validate = 1 if validate else 0
     opt.check = 1 if check else 0
     opt.edge_begin = e0
@@ -181,3 +214,37 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     if times is not None:
         phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
     return g, rows, ends
+
+
+def key_offsets(L_per_graph):
+    """Prefix sums of tg_num_keys(L_g): where each graph's counts start."""
+    import numpy as np
+    ks = np.array([num_keys(int(l)) for l in range(0, 17)], dtype=np.int64)
+    sizes = ks[np.asarray(L_per_graph, dtype=np.int64)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    return off
+
+
+def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_off, *, out=None, check=True,
+                tuning=None):
+    """Global typed-graphlet counts of many small graphs with tg_count_batch.
+
+    All arguments are device tensors (int64 offsets, int32 CSR with local ids,
+    uint8 types and L); key_off comes from key_offsets().  Returns the uint64
+    counts, graph g's at out[key_off[g]:key_off[g+1]].
+    """
+    import torch
+    dev = node_off.device
+    G = node_off.numel() - 1
+    total = int(key_off[-1].item()) if key_off.numel() else 0
+    g = out if out is not None else torch.empty(total, dtype=torch.uint64, device=dev)
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.check = 1 if check else 0
+    opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
+    st = lib().tg_count_batch(G, node_off.data_ptr(), slot_off.data_ptr(), row_ptr.data_ptr(), col_idx.data_ptr(),
+                              types.data_ptr(), L_per_graph.data_ptr(), key_off.data_ptr(), g.data_ptr(),
+                              ctypes.byref(opt), _stream_handle(torch, dev))
+    _check(st)
+    return g

@@ -12,6 +12,7 @@
 
 #include "tg.h"
 #include "tg_kernels.hip"
+#include "tg_batch.hip"
 
 namespace {
 
@@ -258,6 +259,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // ---- schedule: edge classes and cost buckets, node tiers
   timer.mark(TG_PHASE_SCHEDULE);
   const int mode = opt.schedule == TG_SCHED_NONE ? 0 : (opt.schedule == TG_SCHED_DEGREE ? 1 : 2);
+  tg_tuning tune;
+  tg_tuning_default(&tune);
+  if (opt.tuning) tune = *opt.tuning;
+  BinParams bp{mode, std::max(1, tune.heavy_min_degree), std::min(64, std::max(0, tune.heavy_log2_cost))};
   const float* pred = nullptr;
   if (mode == 2) {
     float* p;
@@ -268,7 +273,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   }
   int32_t* cnt = W.counters;           // [0,128) edge bins, [128,132) node tiers, [132] max heavy |T|
   TG_HIP(hipMemsetAsync(cnt, 0, 256 * sizeof(int32_t), st));
-  k_edge_bin_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, mode, pred, cnt,
+  k_edge_bin_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
                                                            (uint32_t*)(cnt + 132));
   TG_LAUNCHED("k_edge_bin_count");
   k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128);
@@ -287,7 +292,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   for (int t = 0; t < 4; ++t) { cur[128 + t] = (int32_t)nacc; nacc += h_cnt[128 + t]; }
   const int64_t max_t_heavy = (uint32_t)h_cnt[132];
   TG_HIP(hipMemcpyAsync(cnt, cur, sizeof(cur), hipMemcpyHostToDevice, st));
-  k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, mode, pred, cnt,
+  k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
                                                              W.elist);
   TG_LAUNCHED("k_edge_bin_scatter");
   k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128, W.nlist);
@@ -384,7 +389,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
   if (n_light_edges > 0) {
     const size_t lds = gbytes + 4 * 4 * LL * sizeof(uint64_t) + 4 * TG_T_WAVE_CAP * (sizeof(int32_t) + 1);
-    k_combine_wave<<<grid_for(n_light_edges, 4, 2048), 256, lds, st>>>(A, n_light_edges, W.elist, (int)K);
+    k_combine_wave<<<grid_for(n_light_edges, 4, std::max(1, tune.combine_grid)), 256, lds, st>>>(A, n_light_edges,
+                                                                                               W.elist, (int)K);
     TG_LAUNCHED("k_combine_wave");
   }
   if (n_heavy > 0) {
@@ -422,6 +428,159 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   return TG_OK;
 }
 
+
+// ------------------------------------------------------------------ batch --
+
+struct BatchLaunch {
+  int variant;
+  int64_t offset, count;
+};
+
+// Cached HIP graph of the per-bucket launches: replayed while the call's
+// pointers and bucket plan repeat.
+struct BatchGraphCache {
+  bool valid = false;
+  int device = -1;
+  std::vector<uint64_t> sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    valid = false;
+  }
+};
+
+BatchGraphCache& batch_cache() {
+  static thread_local BatchGraphCache c;
+  return c;
+}
+
+tg_status enqueue_batch_variant(int variant, const BatchArgs& A, int64_t count, const int32_t* list, int32_t* queue,
+                                hipStream_t st) {
+  const unsigned grid4 = grid_for(count, 4, 4096), grid1 = grid_for(count, 1, 2048);
+  switch (variant) {
+    case 0: k_batch<1, 1, false><<<grid4, 256, 0, st>>>(A, count, list, queue); break;
+    case 1: k_batch<2, 1, false><<<grid4, 256, 0, st>>>(A, count, list, queue); break;
+    case 2: k_batch<2, 4, true><<<grid1, 256, 0, st>>>(A, count, list, queue); break;
+    case 3: k_batch<4, 1, false><<<grid4, 256, 0, st>>>(A, count, list, queue); break;
+    case 4: k_batch<4, 4, true><<<grid1, 256, 0, st>>>(A, count, list, queue); break;
+    case 5: k_batch<8, 4, true><<<grid1, 256, 0, st>>>(A, count, list, queue); break;
+    default: return fail(TG_ERR_INVALID_ARG, "unknown batch kernel variant");
+  }
+  TG_LAUNCHED("k_batch");
+  return TG_OK;
+}
+
+// largest size class W (words per bit row) a variant handles
+int variant_wmax(int v) {
+  static const int w[6] = {1, 2, 2, 4, 4, 8};
+  return (v >= 0 && v < 6) ? w[v] : 0;
+}
+
+tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
+                     const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off, uint64_t* out,
+                     const tg_options* opt_in, hipStream_t st) {
+  tg_options opt;
+  tg_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  tg_tuning tune;
+  tg_tuning_default(&tune);
+  if (opt.tuning) tune = *opt.tuning;
+  if (G < 0 || G >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "G must be in [0, 2^31)");
+  if (G == 0) return TG_OK;
+  if (!node_off || !slot_off || !rp || !ci || !ty || !Lg || !key_off || !out)
+    return fail(TG_ERR_INVALID_ARG, "null input or output pointer");
+  for (int w = 0; w <= 8; ++w)
+    if (variant_wmax(tune.batch_variant[w]) < std::max(1, w))
+      return fail(TG_ERR_INVALID_ARG, "tuning assigns a size class to a kernel variant that is too small");
+  keep_pool_cached();
+  Scratch S(st);
+  int32_t* ctr;      // [0,72) sub-bucket counts, [80] bad flag, [96,112) queues, [120] divisibility flag
+  int32_t* list;
+  TG_HIP(S.get(&ctr, 128));
+  TG_HIP(S.get(&list, G));
+  k_zero_i32<<<1, 128, 0, st>>>(ctr, 128);
+  TG_LAUNCHED("k_zero_i32");
+  k_batch_classify<<<grid_for(G, 256, 4096), 256, 0, st>>>(G, node_off, Lg, key_off, ctr + 80);
+  TG_LAUNCHED("k_batch_classify");
+  k_batch_subcount<<<grid_for(G, 256, 4096), 256, 0, st>>>(G, node_off, ctr);
+  TG_LAUNCHED("k_batch_subcount");
+  int32_t h[128];
+  TG_HIP(hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  if (h[80] & 1) return fail(TG_ERR_INVALID_ARG, "a graph has more than 512 nodes or a negative size");
+  if (h[80] & 2) return fail(TG_ERR_UNSUPPORTED_L, "a graph's L is outside [1, 8]");
+  if (h[80] & 4) return fail(TG_ERR_INVALID_ARG, "key_off does not match tg_num_keys(L_g)");
+  // list order: size class W from 8 down to 0, largest first inside a class
+  int32_t cur[128];
+  memset(cur, 0, sizeof(cur));
+  int64_t acc = 0;
+  int64_t cls_begin[9], cls_count[9];
+  for (int w = 8; w >= 0; --w) {
+    cls_begin[w] = acc;
+    for (int sb = 0; sb < 8; ++sb) { cur[w * 8 + sb] = (int32_t)acc; acc += h[w * 8 + sb]; }
+    cls_count[w] = acc - cls_begin[w];
+  }
+  TG_HIP(hipMemcpyAsync(ctr, cur, 72 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  k_batch_scatter<<<grid_for(G, 256, 4096), 256, 0, st>>>(G, node_off, ctr, list);
+  TG_LAUNCHED("k_batch_scatter");
+  // launches: consecutive classes with the same variant share one queue
+  std::vector<BatchLaunch> plan;
+  for (int w = 8; w >= 0; --w) {
+    if (cls_count[w] == 0) continue;
+    const int v = tune.batch_variant[w];
+    if (!plan.empty() && plan.back().variant == v && plan.back().offset + plan.back().count == cls_begin[w])
+      plan.back().count += cls_count[w];
+    else
+      plan.push_back({v, cls_begin[w], cls_count[w]});
+  }
+  if (plan.size() > 16) return fail(TG_ERR_INTERNAL, "too many batch launches");
+  BatchArgs A{node_off, slot_off, rp, ci, ty, Lg, key_off, out, ctr + 120};
+  // HIP graph: zero the queues and flag, then one persistent launch per bucket
+  int dev = 0;
+  TG_HIP(hipGetDevice(&dev));
+  std::vector<uint64_t> sig = {(uint64_t)dev, (uint64_t)G, (uint64_t)node_off, (uint64_t)slot_off, (uint64_t)rp,
+                               (uint64_t)ci, (uint64_t)ty, (uint64_t)Lg, (uint64_t)key_off, (uint64_t)out,
+                               (uint64_t)ctr, (uint64_t)list};
+  for (auto& l : plan) { sig.push_back((uint64_t)l.variant); sig.push_back((uint64_t)l.offset); sig.push_back((uint64_t)l.count); }
+  BatchGraphCache& C = batch_cache();
+  if (!C.valid || C.sig != sig) {
+    C.reset();
+    if (!C.cap_stream || C.device != dev) {
+      C.device = dev;
+      TG_HIP(hipStreamCreateWithFlags(&C.cap_stream, hipStreamNonBlocking));
+    }
+    TG_HIP(hipStreamBeginCapture(C.cap_stream, hipStreamCaptureModeThreadLocal));
+    k_zero_i32<<<1, 64, 0, C.cap_stream>>>(ctr + 96, 32);
+    tg_status s2 = TG_OK;
+    for (size_t q = 0; q < plan.size() && s2 == TG_OK; ++q)
+      s2 = enqueue_batch_variant(plan[q].variant, A, plan[q].count, list + plan[q].offset, ctr + 96 + (int)q,
+                                 C.cap_stream);
+    hipGraph_t gph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(C.cap_stream, &gph);
+    if (s2 != TG_OK) { if (gph) (void)hipGraphDestroy(gph); return s2; }
+    if (e2 != hipSuccess) return fail(TG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    C.graph = gph;
+    TG_HIP(hipGraphInstantiate(&C.exec, C.graph, nullptr, nullptr, 0));
+    C.sig = sig;
+    C.valid = true;
+  }
+  TG_HIP(hipGraphLaunch(C.exec, st));
+  if (opt.check) {
+    int32_t hf = 0;
+    TG_HIP(hipMemcpyAsync(&hf, ctr + 120, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (hf) return fail(TG_ERR_INTERNAL, "a global sum is not a multiple of its shape's edge count");
+  } else {
+    // the scratch (lists, queues) is released stream-ordered after the graph
+  }
+  return TG_OK;
+}
+
 tg_status tg_internal_predict_costs(const tg_cost_model*, int64_t, const int32_t*, const int32_t*, const uint8_t*,
                                     int, const tg::Work&, int64_t, float*, hipStream_t) {
   return fail(TG_ERR_INVALID_ARG, "learned schedule is not available in this build");
@@ -437,11 +596,35 @@ void tg_options_default(tg_options* opt) {
   if (!opt) return;
   opt->schedule = TG_SCHED_DEGREE;
   opt->model = nullptr;
+  opt->tuning = nullptr;
   opt->validate = 0;
   opt->check = 1;
   opt->edge_begin = 0;
   opt->edge_end = -1;
   opt->phase_ms = nullptr;
+}
+
+void tg_tuning_default(tg_tuning* t) {
+  if (!t) return;
+  t->heavy_min_degree = 4096;
+  t->heavy_log2_cost = 64;
+  t->combine_grid = 2048;
+  const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
+  for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
+}
+
+tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
+                         const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
+                         const int64_t* key_off, uint64_t* global_counts, const tg_options* opt,
+                         hipStream_t stream) {
+  try {
+    return batch_impl(G, node_off, slot_off, row_ptr_local, col_idx_local, node_types, L_per_graph, key_off,
+                      global_counts, opt, stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
 }
 
 size_t tg_num_keys(int L) { return (L < 1 || L > 16) ? 0 : (size_t)nkeys(L); }

@@ -684,46 +684,84 @@ __global__ void __launch_bounds__(256) k_combine_wg(EdgeArgs A, int64_t count, c
 
 // Edge class (0: one wavefront, 1: one workgroup) and cost bucket (0 = most
 // expensive).  cost: 0 none, 1 degree product, 2 given per-edge cost.
+struct BinParams {
+  int mode;              // 0 none, 1 degree product, 2 predicted log2 cost
+  int heavy_min_degree;  // min(d_i, d_j) above this: workgroup
+  int heavy_log2_cost;   // floor(log2 cost) above this: workgroup
+};
+
 __device__ __forceinline__ void edge_bin(int32_t e, const int32_t* ei, const int32_t* ej, const int32_t* deg,
-                                         const uint32_t* tau, int L, int mode, const float* pred, int* cls,
+                                         const uint32_t* tau, int L, BinParams bp, const float* pred, int* cls,
                                          int* bucket, uint32_t* tsum_out) {
   const int32_t i = ei[e], j = ej[e];
   const int32_t di = deg[i], dj = deg[j];
   uint32_t tsum = 0;
   for (int t = 0; t < L; ++t) tsum += tau[(int64_t)e * L + t];
   *tsum_out = tsum;
-  *cls = (tsum > TG_T_WAVE_CAP || min(di, dj) > 4096) ? 1 : 0;
-  if (mode == 0) { *bucket = 0; return; }
+  int heavy = (tsum > TG_T_WAVE_CAP || min(di, dj) > bp.heavy_min_degree) ? 1 : 0;
+  if (bp.mode == 0) { *cls = heavy; *bucket = 0; return; }
   double c;
-  if (mode == 1) c = (double)di * (double)dj;
+  if (bp.mode == 1) c = (double)di * (double)dj;
   else c = exp2((double)pred[e]);
   int lg = (int)floor(log2(c + 1.0));
   lg = lg < 0 ? 0 : (lg > 63 ? 63 : lg);
+  if (lg > bp.heavy_log2_cost) heavy = 1;
+  *cls = heavy;
   *bucket = 63 - lg;
 }
 
-__global__ void k_edge_bin_count(int64_t m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
-                                 const int32_t* __restrict__ deg, const uint32_t* __restrict__ tau, int L, int mode,
-                                 const float* __restrict__ pred, int32_t* __restrict__ counts,
-                                 uint32_t* __restrict__ max_t_heavy) {
+// Bin counts and scatter use a per-workgroup LDS histogram so that global
+// atomics are one per (workgroup tile, bin) rather than one per item.
+__global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t* __restrict__ ei,
+                                                        const int32_t* __restrict__ ej,
+                                                        const int32_t* __restrict__ deg,
+                                                        const uint32_t* __restrict__ tau, int L, BinParams bp,
+                                                        const float* __restrict__ pred, int32_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ max_t_heavy) {
+  __shared__ int32_t h[128];
+  __shared__ uint32_t tmax;
+  for (int q = threadIdx.x; q < 128; q += blockDim.x) h[q] = 0;
+  if (threadIdx.x == 0) tmax = 0;
+  __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     int cls, bucket;
     uint32_t tsum;
-    edge_bin((int32_t)e, ei, ej, deg, tau, L, mode, pred, &cls, &bucket, &tsum);
-    atomicAdd(&counts[cls * 64 + bucket], 1);
-    if (cls == 1) atomicMax(max_t_heavy, tsum);
+    edge_bin((int32_t)e, ei, ej, deg, tau, L, bp, pred, &cls, &bucket, &tsum);
+    atomicAdd(&h[cls * 64 + bucket], 1);
+    if (cls == 1) atomicMax(&tmax, tsum);
   }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 128; q += blockDim.x)
+    if (h[q]) atomicAdd(&counts[q], h[q]);
+  if (threadIdx.x == 0 && tmax) atomicMax(max_t_heavy, tmax);
 }
 
-__global__ void k_edge_bin_scatter(int64_t m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
-                                   const int32_t* __restrict__ deg, const uint32_t* __restrict__ tau, int L,
-                                   int mode, const float* __restrict__ pred, int32_t* __restrict__ cursor,
-                                   int32_t* __restrict__ list) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    int cls, bucket;
-    uint32_t tsum;
-    edge_bin((int32_t)e, ei, ej, deg, tau, L, mode, pred, &cls, &bucket, &tsum);
-    list[atomicAdd(&cursor[cls * 64 + bucket], 1)] = (int32_t)e;
+__global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32_t* __restrict__ ei,
+                                                          const int32_t* __restrict__ ej,
+                                                          const int32_t* __restrict__ deg,
+                                                          const uint32_t* __restrict__ tau, int L, BinParams bp,
+                                                          const float* __restrict__ pred,
+                                                          int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+  __shared__ int32_t h[128];
+  __shared__ int32_t base[128];
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < m; t0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int q = threadIdx.x; q < 128; q += blockDim.x) h[q] = 0;
+    __syncthreads();
+    const int64_t e = t0 + threadIdx.x;
+    int bin = -1, local = 0;
+    if (e < m) {
+      int cls, bucket;
+      uint32_t tsum;
+      edge_bin((int32_t)e, ei, ej, deg, tau, L, bp, pred, &cls, &bucket, &tsum);
+      bin = cls * 64 + bucket;
+      local = atomicAdd(&h[bin], 1);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 128; q += blockDim.x)
+      base[q] = h[q] ? atomicAdd(&cursor[q], h[q]) : 0;
+    __syncthreads();
+    if (bin >= 0) list[base[bin] + local] = (int32_t)e;
+    __syncthreads();
   }
 }
 
@@ -733,15 +771,36 @@ __device__ __forceinline__ int node_tier(uint64_t W) {
   return W == 0 ? 0 : (W <= TG_C4_LIGHT_W ? 1 : (W <= TG_C4_MED_W ? 2 : 3));
 }
 
-__global__ void k_node_tier_count(int64_t n, const uint64_t* __restrict__ W, int32_t* __restrict__ counts) {
+__global__ void __launch_bounds__(256) k_node_tier_count(int64_t n, const uint64_t* __restrict__ W,
+                                                         int32_t* __restrict__ counts) {
+  __shared__ int32_t h[4];
+  if (threadIdx.x < 4) h[threadIdx.x] = 0;
+  __syncthreads();
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&counts[node_tier(W[v])], 1);
+    atomicAdd(&h[node_tier(W[v])], 1);
+  __syncthreads();
+  if (threadIdx.x < 4 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_node_tier_scatter(int64_t n, const uint64_t* __restrict__ W, int32_t* __restrict__ cursor,
-                                    int32_t* __restrict__ list) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    list[atomicAdd(&cursor[node_tier(W[v])], 1)] = (int32_t)v;
+__global__ void __launch_bounds__(256) k_node_tier_scatter(int64_t n, const uint64_t* __restrict__ W,
+                                                           int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
+  __shared__ int32_t h[4];
+  __shared__ int32_t base[4];
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n; t0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x < 4) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t v = t0 + threadIdx.x;
+    int tier = -1, local = 0;
+    if (v < n) {
+      tier = node_tier(W[v]);
+      local = atomicAdd(&h[tier], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0;
+    __syncthreads();
+    if (tier >= 0) list[base[tier] + local] = (int32_t)v;
+    __syncthreads();
+  }
 }
 
 __global__ void k_gather_node_info(int64_t count, const int32_t* __restrict__ list, const uint64_t* __restrict__ W,

@@ -42,8 +42,8 @@ def test_sampled_rows_match_oracle(big):
     idx, ei, ej = stratified_sample(g)
     note(f"oracle on {len(idx)} sampled edges")
     want, _ = oracle.count_edges(g.row_ptr, g.col_idx, g.types, g.L, ei[idx], ej[idx], nthreads=16)
-    got = rows[idx.tolist()].cpu().numpy().view(np.uint64) if False else \
-        rows.index_select(0, __import__("torch").from_numpy(idx).to(rows.device)).cpu().numpy().view(np.uint64)
+    import torch
+    got = rows.index_select(0, torch.from_numpy(idx).to(rows.device)).cpu().numpy().view(np.uint64)
     bad = np.nonzero((got != want).any(axis=1))[0]
     assert len(bad) == 0, f"{len(bad)} sampled edges differ: {idx[bad][:5]}"
 
