@@ -185,6 +185,56 @@ tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot
                          const int64_t* key_off, uint64_t* global_counts, const tg_options* opt,
                          hipStream_t stream);
 
+/* ---- learned cost model (16-64-64-1 MLP, ReLU, bf16 weights, fp32
+ * accumulation) that orders and bins edges for TG_SCHED_LEARNED.  A model
+ * lives on the device that was current at creation. */
+
+/* Number of trainable parameters (layout: W1[64][16], b1[64], W2[64][64],
+ * b2[64], w3[64], b3); get/set also carry 32 feature statistics (mean[16],
+ * deviation[16]) after them. */
+size_t tg_cost_model_num_params(void);
+
+/* Creates a model with seeded initial weights. */
+tg_status tg_cost_model_create(tg_cost_model** model, uint64_t seed);
+tg_status tg_cost_model_destroy(tg_cost_model* model);
+
+/* Trains on a seeded uniform sample (fraction sample_frac) of the graph's
+ * edges, labelled with the per-edge element-visit counts of the counting
+ * kernel (target log2(1 + work)), for `epochs` passes of mini-batch Adam;
+ * loss_history (host, [epochs] or NULL) receives the mean loss per epoch.
+ * Device pointers as in tg_count.  Synchronises the stream. */
+tg_status tg_cost_model_train(tg_cost_model* model, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col_idx, const uint8_t* node_types, int L, double sample_frac,
+                              uint64_t seed, int epochs, float* loss_history, hipStream_t stream);
+
+/* Predicted log2(1 + work) of every canonical edge: cost is device float[m]. */
+tg_status tg_cost_model_predict(const tg_cost_model* model, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                const int32_t* col_idx, const uint8_t* node_types, int L, float* cost,
+                                hipStream_t stream);
+
+/* Measured element-visit counts of the per-edge counting kernel for the
+ * listed canonical edges: edges is device int32[count], work is device
+ * uint64[m] indexed by edge id (entries of unlisted edges are zero). */
+tg_status tg_edge_work(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                       const uint8_t* node_types, int L, const int32_t* edges, int64_t count, uint64_t* work,
+                       hipStream_t stream);
+
+/* Mean-squared-error loss and its gradient over `rows` raw feature rows X
+ * (device float[rows][16]) and targets Y (device float[rows]) with the
+ * model's current bf16 weights: grad is device float[num_params], loss is
+ * device float[1].  Used to check the training kernels. */
+tg_status tg_cost_model_gradient(const tg_cost_model* model, const float* X, const float* Y, int64_t rows,
+                                 float* grad, float* loss, hipStream_t stream);
+
+/* Host copies of the fp32 parameters followed by the feature statistics
+ * (num_params + 32 floats). */
+tg_status tg_cost_model_get_params(const tg_cost_model* model, float* params);
+tg_status tg_cost_model_set_params(tg_cost_model* model, const float* params);
+
+/* Binary file with the parameters and statistics. */
+tg_status tg_cost_model_save(const tg_cost_model* model, const char* path);
+tg_status tg_cost_model_load(tg_cost_model* model, const char* path);
+
 /* Human-readable name of a status code (static string). */
 const char* tg_status_string(tg_status s);
 

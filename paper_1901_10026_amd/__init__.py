@@ -118,6 +118,28 @@ def lib():
     L.tg_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_tuning_default.restype = None
     L.tg_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
+    L.tg_cost_model_num_params.restype = sz
+    L.tg_cost_model_num_params.argtypes = []
+    L.tg_cost_model_create.restype = i32
+    L.tg_cost_model_create.argtypes = [ctypes.POINTER(vp), ctypes.c_uint64]
+    L.tg_cost_model_destroy.restype = i32
+    L.tg_cost_model_destroy.argtypes = [vp]
+    L.tg_cost_model_train.restype = i32
+    L.tg_cost_model_train.argtypes = [vp, i64, i64, vp, vp, vp, i32, ctypes.c_double, ctypes.c_uint64, i32, vp, vp]
+    L.tg_cost_model_predict.restype = i32
+    L.tg_cost_model_predict.argtypes = [vp, i64, i64, vp, vp, vp, i32, vp, vp]
+    L.tg_edge_work.restype = i32
+    L.tg_edge_work.argtypes = [i64, i64, vp, vp, vp, i32, vp, i64, vp, vp]
+    L.tg_cost_model_gradient.restype = i32
+    L.tg_cost_model_gradient.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.tg_cost_model_get_params.restype = i32
+    L.tg_cost_model_get_params.argtypes = [vp, vp]
+    L.tg_cost_model_set_params.restype = i32
+    L.tg_cost_model_set_params.argtypes = [vp, vp]
+    L.tg_cost_model_save.restype = i32
+    L.tg_cost_model_save.argtypes = [vp, ctypes.c_char_p]
+    L.tg_cost_model_load.restype = i32
+    L.tg_cost_model_load.argtypes = [vp, ctypes.c_char_p]
     L.tg_status_string.restype = ctypes.c_char_p
     L.tg_status_string.argtypes = [i32]
     L.tg_last_error.restype = ctypes.c_char_p
@@ -248,3 +270,80 @@ def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_of
                               ctypes.byref(opt), _stream_handle(torch, dev))
     _check(st)
     return g
+
+
+class CostModel:
+    """The learned per-edge cost model (tg_cost_model): a 16-64-64-1 MLP with
+    bf16 weights trained on the GPU by the library's kernels."""
+
+    def __init__(self, seed=55):
+        h = ctypes.c_void_p()
+        _check(lib().tg_cost_model_create(ctypes.byref(h), int(seed)))
+        self.handle = h.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().tg_cost_model_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    @staticmethod
+    def num_params():
+        return int(lib().tg_cost_model_num_params())
+
+    def train(self, row_ptr, col_idx, types, L, sample_frac=0.01, seed=56, epochs=20):
+        import torch
+        hist = (ctypes.c_float * max(epochs, 1))()
+        _check(lib().tg_cost_model_train(self.handle, row_ptr.numel() - 1, col_idx.numel(), row_ptr.data_ptr(),
+                                         col_idx.data_ptr(), types.data_ptr(), L, float(sample_frac), int(seed),
+                                         int(epochs), hist, _stream_handle(torch, row_ptr.device)))
+        return [float(hist[q]) for q in range(epochs)]
+
+    def predict(self, row_ptr, col_idx, types, L):
+        import torch
+        m = col_idx.numel() // 2
+        out = torch.empty(m, dtype=torch.float32, device=row_ptr.device)
+        _check(lib().tg_cost_model_predict(self.handle, row_ptr.numel() - 1, col_idx.numel(), row_ptr.data_ptr(),
+                                           col_idx.data_ptr(), types.data_ptr(), L, out.data_ptr(),
+                                           _stream_handle(torch, row_ptr.device)))
+        return out
+
+    def gradient(self, X, Y):
+        import torch
+        grad = torch.empty(self.num_params(), dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(lib().tg_cost_model_gradient(self.handle, X.data_ptr(), Y.data_ptr(), X.shape[0], grad.data_ptr(),
+                                            loss.data_ptr(), _stream_handle(torch, X.device)))
+        return grad, loss
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.num_params() + 32, dtype=np.float32)
+        _check(lib().tg_cost_model_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.num_params() + 32
+        _check(lib().tg_cost_model_set_params(self.handle, p.ctypes.data))
+
+    def save(self, path):
+        _check(lib().tg_cost_model_save(self.handle, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().tg_cost_model_load(self.handle, str(path).encode()))
+
+
+def edge_work(row_ptr, col_idx, types, L, edges):
+    """Element-visit counts of the per-edge counting kernel for the listed
+    canonical edges (int32 device tensor); returns uint64 [m] by edge id."""
+    import torch
+    m = col_idx.numel() // 2
+    out = torch.empty(m, dtype=torch.uint64, device=row_ptr.device)
+    _check(lib().tg_edge_work(row_ptr.numel() - 1, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(),
+                              types.data_ptr(), L, edges.data_ptr(), edges.numel(), out.data_ptr(),
+                              _stream_handle(torch, row_ptr.device)))
+    return out

@@ -13,6 +13,7 @@
 #include "tg.h"
 #include "tg_kernels.hip"
 #include "tg_batch.hip"
+#include "tg_mlp.hip"
 
 namespace {
 
@@ -175,6 +176,56 @@ tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, con
   return TG_OK;
 }
 
+// Scratch allocation, preprocessing, typed triangles and node tables: the
+// part of the pipeline shared by counting and by cost-model training.
+tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                        const uint8_t* ty, int L, Work& W, PhaseTimer* timer) {
+  const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
+  TG_HIP(S.get(&W.deg, n));
+  TG_HIP(S.get(&W.D, n * L));
+  TG_HIP(S.get(&W.n_upper, n));
+  TG_HIP(S.get(&W.n_out, n));
+  TG_HIP(S.get(&W.wedge_work, n));
+  TG_HIP(S.get(&W.nbr_deg_sum, n));
+  TG_HIP(S.get(&W.upper_off, n + 1));
+  TG_HIP(S.get(&W.out_off, n + 1));
+  TG_HIP(S.get(&W.ei, m));
+  TG_HIP(S.get(&W.ej, m));
+  TG_HIP(S.get(&W.s2e, nnz));
+  TG_HIP(S.get(&W.out_col, m));
+  TG_HIP(S.get(&W.tau, m * L));
+  TG_HIP(S.get(&W.Pn, n * LL));
+  TG_HIP(S.get(&W.Un, n * LL));
+  TG_HIP(S.get(&W.C4, m * P));
+  TG_HIP(S.get(&W.elist, m));
+  TG_HIP(S.get(&W.nlist, n));
+  TG_HIP(S.get(&W.counters, 256));
+
+  // ---- prep
+  if (timer) timer->mark(TG_PHASE_PREP);
+  k_degree<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, rp, W.deg);
+  TG_LAUNCHED("k_degree");
+  k_node_stats<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, ty, L, W.D, W.n_upper, W.n_out, W.wedge_work,
+                                               W.nbr_deg_sum);
+  TG_LAUNCHED("k_node_stats");
+  if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
+  if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
+  k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
+                                               W.s2e, W.out_col);
+  TG_LAUNCHED("k_fill_edges");
+
+  // ---- typed triangles per edge, node tables
+  if (timer) timer->mark(TG_PHASE_TAU);
+  k_tau<<<grid_for(m, 4), 256, 0, st>>>(m, nullptr, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  TG_LAUNCHED("k_tau");
+  if (timer) timer->mark(TG_PHASE_TABLES);
+  k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D, W.tau,
+                                                                                     W.s2e, W.Pn, W.Un);
+  TG_LAUNCHED("k_node_tables");
+
+  return TG_OK;
+}
+
 tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L,
                      uint64_t* global_counts, uint64_t* edge_counts, int32_t* edge_endpoints,
                      const tg_options* opt_in, hipStream_t st) {
@@ -214,47 +265,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (m == 0) return TG_OK;
 
   Work W;
-  TG_HIP(S.get(&W.deg, n));
-  TG_HIP(S.get(&W.D, n * L));
-  TG_HIP(S.get(&W.n_upper, n));
-  TG_HIP(S.get(&W.n_out, n));
-  TG_HIP(S.get(&W.wedge_work, n));
-  TG_HIP(S.get(&W.nbr_deg_sum, n));
-  TG_HIP(S.get(&W.upper_off, n + 1));
-  TG_HIP(S.get(&W.out_off, n + 1));
-  TG_HIP(S.get(&W.ei, m));
-  TG_HIP(S.get(&W.ej, m));
-  TG_HIP(S.get(&W.s2e, nnz));
-  TG_HIP(S.get(&W.out_col, m));
-  TG_HIP(S.get(&W.tau, m * L));
-  TG_HIP(S.get(&W.Pn, n * LL));
-  TG_HIP(S.get(&W.Un, n * LL));
-  TG_HIP(S.get(&W.C4, m * P));
-  TG_HIP(S.get(&W.elist, m));
-  TG_HIP(S.get(&W.nlist, n));
-  TG_HIP(S.get(&W.counters, 256));
-
-  // ---- prep
-  timer.mark(TG_PHASE_PREP);
-  k_degree<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, rp, W.deg);
-  TG_LAUNCHED("k_degree");
-  k_node_stats<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, ty, L, W.D, W.n_upper, W.n_out, W.wedge_work,
-                                               W.nbr_deg_sum);
-  TG_LAUNCHED("k_node_stats");
-  if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
-  if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
-  k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
-                                               W.s2e, W.out_col);
-  TG_LAUNCHED("k_fill_edges");
-
-  // ---- typed triangles per edge, node tables
-  timer.mark(TG_PHASE_TAU);
-  k_tau<<<grid_for(m, 4), 256, 0, st>>>(m, nullptr, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
-  TG_LAUNCHED("k_tau");
-  timer.mark(TG_PHASE_TABLES);
-  k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D, W.tau,
-                                                                                     W.s2e, W.Pn, W.Un);
-  TG_LAUNCHED("k_node_tables");
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer)) return s;
 
   // ---- schedule: edge classes and cost buckets, node tiers
   timer.mark(TG_PHASE_SCHEDULE);
@@ -340,7 +351,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
       return hw[a] != hw[b] ? hw[a] > hw[b] : hx[a] < hx[b];
     });
-    const int64_t stride = n * L + n;
+    const int CS = L <= 8 ? 8 : 16;
+    const int64_t stride = n * CS;
     int64_t G = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
     G = std::max<int64_t>(1, std::min<int64_t>(G, std::min<int64_t>(256, n_t3)));
     const int64_t ngroups = (n_t3 + G - 1) / G;
@@ -372,8 +384,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const int Gg = (int)std::min<int64_t>(G, n_t3 - g * G);
       const int64_t slots = gp[g * (G + 1) + Gg];
       for (int phase = 0; phase < 3; ++phase) {
-        k_c4_group<<<grid_for(slots, 4), 256, 0, st>>>(phase, Gg, d_gx + g * G, d_gp + g * (G + 1), dense, stride, n,
-                                                      rp, ci, W.deg, ty, L, W.s2e, W.C4);
+        k_c4_group<<<grid_for(slots, 4 * TG_WAVE), 256, 0, st>>>(phase, Gg, d_gx + g * G, d_gp + g * (G + 1), dense,
+                                                                stride, CS, rp, ci, W.deg, ty, L, W.s2e, W.C4);
         TG_LAUNCHED("k_c4_group");
       }
     }
@@ -386,6 +398,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
   A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
+  A.work = nullptr;
   const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
   if (n_light_edges > 0) {
     const size_t lds = gbytes + 4 * 4 * LL * sizeof(uint64_t) + 4 * TG_T_WAVE_CAP * (sizeof(int32_t) + 1);
@@ -581,9 +594,232 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
   return TG_OK;
 }
 
-tg_status tg_internal_predict_costs(const tg_cost_model*, int64_t, const int32_t*, const int32_t*, const uint8_t*,
-                                    int, const tg::Work&, int64_t, float*, hipStream_t) {
-  return fail(TG_ERR_INVALID_ARG, "learned schedule is not available in this build");
+tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t n, const int32_t* rp, const int32_t* ci,
+                                    const uint8_t* ty, int L, const tg::Work& W, int64_t m, float* out,
+                                    hipStream_t st);
+
+}  // namespace
+
+// ------------------------------------------------------------- cost model --
+
+struct tg_cost_model {
+  int device = -1;
+  float* W = nullptr;       // fp32 master parameters
+  float* M = nullptr;       // Adam first moment
+  float* V = nullptr;       // Adam second moment
+  uint16_t* Wbf = nullptr;  // bf16 copy used by the kernels
+  float* stats = nullptr;   // feature mean[16], deviation[16]
+  int64_t steps = 0;        // Adam steps taken
+};
+
+namespace {
+
+void model_init_host(std::vector<float>& w, std::vector<float>& stats, uint64_t seed) {
+  // seeded uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights, zero biases
+  w.assign(TG_MLP_NPARAM, 0.0f);
+  uint64_t st = seed * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  auto next = [&]() {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  for (int p = 0; p < TG_MLP_OFF_B1; ++p) w[p] = (float)((2 * next() - 1) / std::sqrt((double)TG_MLP_IN));
+  for (int p = TG_MLP_OFF_W2; p < TG_MLP_OFF_B2; ++p) w[p] = (float)((2 * next() - 1) / std::sqrt((double)TG_MLP_H));
+  for (int p = TG_MLP_OFF_W3; p < TG_MLP_OFF_B3; ++p) w[p] = (float)((2 * next() - 1) / std::sqrt((double)TG_MLP_H));
+  stats.assign(2 * TG_MLP_IN, 0.0f);
+  for (int c = 0; c < TG_MLP_IN; ++c) stats[TG_MLP_IN + c] = 1.0f;
+}
+
+tg_status model_upload(tg_cost_model* md, const float* w, const float* stats, hipStream_t st) {
+  TG_HIP(hipMemcpyAsync(md->W, w, TG_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, st));
+  TG_HIP(hipMemcpyAsync(md->stats, stats, 2 * TG_MLP_IN * sizeof(float), hipMemcpyHostToDevice, st));
+  TG_HIP(hipMemsetAsync(md->M, 0, TG_MLP_NPARAM * sizeof(float), st));
+  TG_HIP(hipMemsetAsync(md->V, 0, TG_MLP_NPARAM * sizeof(float), st));
+  k_mlp_to_bf16<<<grid_for(TG_MLP_NPARAM, 256, 64), 256, 0, st>>>(md->W, md->Wbf);
+  TG_LAUNCHED("k_mlp_to_bf16");
+  TG_HIP(hipStreamSynchronize(st));
+  md->steps = 0;
+  return TG_OK;
+}
+
+tg_status check_model_device(const tg_cost_model* md) {
+  int dev = 0;
+  TG_HIP(hipGetDevice(&dev));
+  if (dev != md->device) return fail(TG_ERR_INVALID_ARG, "cost model lives on another device");
+  return TG_OK;
+}
+
+tg_status check_graph_args(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31) || n * (int64_t)L >= (1ll << 31))
+    return fail(TG_ERR_INVALID_ARG, "graph size out of range");
+  if (!rp || (nnz > 0 && !ci) || (n > 0 && !ty)) return fail(TG_ERR_INVALID_ARG, "null graph pointer");
+  if (nnz % 2) return fail(TG_ERR_INVALID_GRAPH, "nnz is odd");
+  return TG_OK;
+}
+
+// Instrumented element-visit counts of the per-edge counting kernel for the
+// listed edges (work indexed by edge id).
+tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                       const uint8_t* ty, int L, const Work& W, const int32_t* list, int64_t count,
+                       uint64_t* work_by_edge) {
+  const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L, K = nkeys(L);
+  uint64_t* gsink;
+  uint32_t* tmax;
+  TG_HIP(S.get(&gsink, K));
+  TG_HIP(S.get(&tmax, 1));
+  k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
+  TG_LAUNCHED("k_fill_u64");
+  k_fill_u64<<<grid_for(m, 256, 8192), 256, 0, st>>>(work_by_edge, m, 0);
+  TG_LAUNCHED("k_fill_u64");
+  k_fill_u64<<<1, 64, 0, st>>>(gsink, K, 0);
+  TG_LAUNCHED("k_fill_u64");
+  k_fill_u32<<<1, 64, 0, st>>>(tmax, 1, 0);
+  TG_LAUNCHED("k_fill_u32");
+  k_max_tsum<<<grid_for(count, 256, 4096), 256, 0, st>>>(count, list, W.tau, L, tmax);
+  TG_LAUNCHED("k_max_tsum");
+  uint32_t h_tmax = 0;
+  TG_HIP(hipMemcpyAsync(&h_tmax, tmax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  EdgeArgs A;
+  A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
+  A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.edge_counts = nullptr; A.edge_begin = 0; A.edge_end = 0; A.global_sums = gsink;
+  A.gacc_in_lds = 0;
+  A.work = work_by_edge;
+  const unsigned grid = grid_for(count, 1, 1024);
+  int32_t* t_over = nullptr;
+  int64_t t_cap = 0;
+  if (h_tmax > TG_T_WG_CAP) {
+    t_cap = h_tmax;
+    TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
+  }
+  const size_t lds = 4 * LL * sizeof(uint64_t) + 4 * sizeof(int32_t) + TG_T_WG_CAP * (sizeof(int32_t) + 1);
+  k_combine_wg<<<grid, 256, lds, st>>>(A, count, list, (int)K, t_over, t_cap);
+  TG_LAUNCHED("k_combine_wg");
+  return TG_OK;
+}
+
+// Seeded uniform sample of canonical edges, in increasing edge order.
+tg_status sample_edges(Scratch& S, hipStream_t st, int64_t m, double frac, uint64_t seed, int32_t** list_out,
+                       int64_t* count_out) {
+  int32_t* flag;
+  int32_t* pos;
+  int32_t* list;
+  TG_HIP(S.get(&flag, m));
+  TG_HIP(S.get(&pos, m + 1));
+  TG_HIP(S.get(&list, m));
+  const uint64_t thr = frac >= 1.0 ? ~0ull : (uint64_t)(frac * 18446744073709551616.0);
+  k_sample_flags<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, seed, thr, flag);
+  TG_LAUNCHED("k_sample_flags");
+  if (tg_status s = scan(S, st, m, flag, pos)) return s;
+  k_compact<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, flag, pos, list);
+  TG_LAUNCHED("k_compact");
+  int32_t total = 0;
+  TG_HIP(hipMemcpyAsync(&total, pos + m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  *list_out = list;
+  *count_out = total;
+  return TG_OK;
+}
+
+tg_status train_impl(tg_cost_model* md, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                     const uint8_t* ty, int L, double frac, uint64_t seed, int epochs, float* loss_hist,
+                     hipStream_t st) {
+  if (!md) return fail(TG_ERR_INVALID_ARG, "null model");
+  if (tg_status s = check_model_device(md)) return s;
+  if (tg_status s = check_graph_args(n, nnz, rp, ci, ty, L)) return s;
+  if (!(frac > 0.0 && frac <= 1.0) || epochs < 0) return fail(TG_ERR_INVALID_ARG, "bad sample fraction or epochs");
+  const int64_t m = nnz / 2;
+  if (m == 0) return fail(TG_ERR_INVALID_ARG, "graph has no edges to learn from");
+  keep_pool_cached();
+  Scratch S(st);
+  Work W;
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, nullptr)) return s;
+  int32_t* list;
+  int64_t ns = 0;
+  if (tg_status s = sample_edges(S, st, m, frac, seed, &list, &ns)) return s;
+  if (ns < TG_MLP_ROWS) return fail(TG_ERR_INVALID_ARG, "edge sample too small to train on");
+  uint64_t* work;
+  float *X, *Yall, *Y;
+  TG_HIP(S.get(&work, m));
+  TG_HIP(S.get(&X, ns * TG_MLP_IN));
+  TG_HIP(S.get(&Yall, m));
+  TG_HIP(S.get(&Y, ns));
+  if (tg_status s = measure_work(S, st, n, nnz, rp, ci, ty, L, W, list, ns, work)) return s;
+  k_work_to_target<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, work, Yall);
+  TG_LAUNCHED("k_work_to_target");
+  k_gather_f32<<<grid_for(ns, 256, 8192), 256, 0, st>>>(ns, list, Yall, Y);
+  TG_LAUNCHED("k_gather_f32");
+  k_mlp_features<<<grid_for(ns, 256, 8192), 256, 0, st>>>(ns, list, W.ei, W.ej, W.deg, W.D, ty, L, X);
+  TG_LAUNCHED("k_mlp_features");
+  k_mlp_feature_stats<<<1, 256, 0, st>>>(ns, X, md->stats);
+  TG_LAUNCHED("k_mlp_feature_stats");
+  // mini-batch Adam over seeded shuffles of the sample
+  const int64_t B = 1024;
+  const int max_blocks = (int)(B / TG_MLP_ROWS);
+  float *partial, *ploss, *grad, *loss;
+  int32_t* perm_d;
+  TG_HIP(S.get(&partial, (int64_t)max_blocks * TG_MLP_NPARAM));
+  TG_HIP(S.get(&ploss, max_blocks));
+  TG_HIP(S.get(&grad, TG_MLP_NPARAM));
+  TG_HIP(S.get(&loss, 1));
+  TG_HIP(S.get(&perm_d, ns));
+  std::vector<int32_t> perm(ns);
+  std::vector<float> step_loss;
+  uint64_t rs = seed ^ 0xD6E8FEB86659FD93ull;
+  auto next = [&]() {
+    uint64_t z = (rs += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const float lr = 2e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t q = 0; q < ns; ++q) perm[q] = (int32_t)q;
+    for (int64_t q = ns - 1; q > 0; --q) std::swap(perm[q], perm[next() % (uint64_t)(q + 1)]);
+    TG_HIP(hipMemcpyAsync(perm_d, perm.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int64_t nsteps = (ns + B - 1) / B;
+    step_loss.assign(nsteps, 0.0f);
+    for (int64_t stp = 0; stp < nsteps; ++stp) {
+      const int64_t r0 = stp * B, rows = std::min(B, ns - r0);
+      const int nb = (int)((rows + TG_MLP_ROWS - 1) / TG_MLP_ROWS);
+      k_mlp_backward<<<nb, 256, 0, st>>>(rows, rows, perm_d + r0, md->Wbf, md->stats, X, Y, partial, ploss);
+      TG_LAUNCHED("k_mlp_backward");
+      k_mlp_reduce<<<grid_for(TG_MLP_NPARAM, 256, 64), 256, 0, st>>>(nb, partial, ploss, grad, loss);
+      TG_LAUNCHED("k_mlp_reduce");
+      md->steps += 1;
+      const float c1 = 1.0f - std::pow(b1, (float)md->steps), c2 = 1.0f - std::pow(b2, (float)md->steps);
+      k_mlp_adam<<<grid_for(TG_MLP_NPARAM, 256, 64), 256, 0, st>>>(md->W, md->M, md->V, grad, md->Wbf, lr, b1, b2,
+                                                                   eps, c1, c2);
+      TG_LAUNCHED("k_mlp_adam");
+      if (loss_hist) TG_HIP(hipMemcpyAsync(&step_loss[stp], loss, sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    if (loss_hist) {
+      TG_HIP(hipStreamSynchronize(st));
+      double accl = 0.0;
+      for (int64_t q = 0; q < nsteps; ++q) accl += step_loss[q];
+      loss_hist[ep] = (float)(accl / (double)nsteps);
+    }
+  }
+  TG_HIP(hipStreamSynchronize(st));
+  return TG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t, const int32_t*, const int32_t*,
+                                    const uint8_t* ty, int L, const tg::Work& W, int64_t m, float* out,
+                                    hipStream_t st) {
+  if (tg_status s = check_model_device(model)) return s;
+  k_mlp_predict<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, model->Wbf, model->stats, nullptr, W.ei, W.ej, W.deg,
+                                                         W.D, ty, L, out);
+  TG_LAUNCHED("k_mlp_predict");
+  return TG_OK;
 }
 
 }  // namespace
@@ -702,6 +938,130 @@ tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t
   } catch (...) {
     return fail(TG_ERR_INTERNAL, "unknown exception");
   }
+}
+
+size_t tg_cost_model_num_params(void) { return (size_t)TG_MLP_NPARAM; }
+
+tg_status tg_cost_model_create(tg_cost_model** out, uint64_t seed) {
+  if (!out) return fail(TG_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  tg_cost_model* md = new (std::nothrow) tg_cost_model();
+  if (!md) return fail(TG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { delete md; return fail(TG_ERR_HIP, "hipGetDevice failed"); }
+  md->device = dev;
+  bool ok = hipMalloc(&md->W, TG_MLP_NPARAM * sizeof(float)) == hipSuccess &&
+            hipMalloc(&md->M, TG_MLP_NPARAM * sizeof(float)) == hipSuccess &&
+            hipMalloc(&md->V, TG_MLP_NPARAM * sizeof(float)) == hipSuccess &&
+            hipMalloc(&md->Wbf, TG_MLP_NPARAM * sizeof(uint16_t)) == hipSuccess &&
+            hipMalloc(&md->stats, 2 * TG_MLP_IN * sizeof(float)) == hipSuccess;
+  if (!ok) { tg_cost_model_destroy(md); return fail(TG_ERR_OUT_OF_MEMORY, "device allocation failed"); }
+  std::vector<float> w, st;
+  model_init_host(w, st, seed);
+  tg_status s = model_upload(md, w.data(), st.data(), nullptr);
+  if (s != TG_OK) { tg_cost_model_destroy(md); return s; }
+  *out = md;
+  return TG_OK;
+}
+
+tg_status tg_cost_model_destroy(tg_cost_model* md) {
+  if (!md) return TG_OK;
+  if (md->W) (void)hipFree(md->W);
+  if (md->M) (void)hipFree(md->M);
+  if (md->V) (void)hipFree(md->V);
+  if (md->Wbf) (void)hipFree(md->Wbf);
+  if (md->stats) (void)hipFree(md->stats);
+  delete md;
+  return TG_OK;
+}
+
+tg_status tg_cost_model_get_params(const tg_cost_model* md, float* params) {
+  if (!md || !params) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  TG_HIP(hipMemcpy(params, md->W, TG_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  TG_HIP(hipMemcpy(params + TG_MLP_NPARAM, md->stats, 2 * TG_MLP_IN * sizeof(float), hipMemcpyDeviceToHost));
+  return TG_OK;
+}
+
+tg_status tg_cost_model_set_params(tg_cost_model* md, const float* params) {
+  if (!md || !params) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  return model_upload(md, params, params + TG_MLP_NPARAM, nullptr);
+}
+
+tg_status tg_cost_model_save(const tg_cost_model* md, const char* path) {
+  if (!md || !path) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  std::vector<float> p(TG_MLP_NPARAM + 2 * TG_MLP_IN);
+  if (tg_status s = tg_cost_model_get_params(md, p.data())) return s;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(TG_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  const char magic[8] = {'T', 'G', 'M', 'L', 'P', '1', '6', '\0'};
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+  std::fclose(f);
+  return ok ? TG_OK : fail(TG_ERR_INVALID_ARG, "short write");
+}
+
+tg_status tg_cost_model_load(tg_cost_model* md, const char* path) {
+  if (!md || !path) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(TG_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  char magic[8];
+  std::vector<float> p(TG_MLP_NPARAM + 2 * TG_MLP_IN);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "TGMLP16", 8) == 0 &&
+            std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+  std::fclose(f);
+  if (!ok) return fail(TG_ERR_INVALID_ARG, "not a cost model file");
+  return tg_cost_model_set_params(md, p.data());
+}
+
+tg_status tg_cost_model_train(tg_cost_model* md, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col_idx, const uint8_t* node_types, int L, double sample_frac,
+                              uint64_t seed, int epochs, float* loss_history, hipStream_t stream) {
+  try {
+    return train_impl(md, n, nnz, row_ptr, col_idx, node_types, L, sample_frac, seed, epochs, loss_history, stream);
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "exception during training");
+  }
+}
+
+tg_status tg_cost_model_predict(const tg_cost_model* md, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                const int32_t* col_idx, const uint8_t* node_types, int L, float* cost,
+                                hipStream_t stream) {
+  if (!md || !cost) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  if (tg_status s = check_graph_args(n, nnz, row_ptr, col_idx, node_types, L)) return s;
+  if (nnz == 0) return TG_OK;
+  keep_pool_cached();
+  Scratch S(stream);
+  Work W;
+  if (tg_status s = prepare_graph(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, nullptr)) return s;
+  return tg_internal_predict_costs(md, n, row_ptr, col_idx, node_types, L, W, nnz / 2, cost, stream);
+}
+
+tg_status tg_edge_work(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                       const uint8_t* node_types, int L, const int32_t* edges, int64_t count, uint64_t* work,
+                       hipStream_t stream) {
+  if (tg_status s = check_graph_args(n, nnz, row_ptr, col_idx, node_types, L)) return s;
+  if (!work || count < 0 || (count > 0 && !edges)) return fail(TG_ERR_INVALID_ARG, "bad edge list or output");
+  if (nnz == 0 || count == 0) return TG_OK;
+  keep_pool_cached();
+  Scratch S(stream);
+  Work W;
+  if (tg_status s = prepare_graph(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, nullptr)) return s;
+  return measure_work(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, edges, count, work);
+}
+
+tg_status tg_cost_model_gradient(const tg_cost_model* md, const float* X, const float* Y, int64_t rows,
+                                 float* grad, float* loss, hipStream_t stream) {
+  if (!md || !X || !Y || !grad || rows <= 0) return fail(TG_ERR_INVALID_ARG, "bad arguments");
+  if (tg_status s = check_model_device(md)) return s;
+  Scratch S(stream);
+  const int nb = (int)((rows + TG_MLP_ROWS - 1) / TG_MLP_ROWS);
+  float *partial, *ploss;
+  TG_HIP(S.get(&partial, (int64_t)nb * TG_MLP_NPARAM));
+  TG_HIP(S.get(&ploss, nb));
+  k_mlp_backward<<<nb, 256, 0, stream>>>(rows, rows, nullptr, md->Wbf, md->stats, X, Y, partial, ploss);
+  TG_LAUNCHED("k_mlp_backward");
+  k_mlp_reduce<<<grid_for(TG_MLP_NPARAM, 256, 64), 256, 0, stream>>>(nb, partial, ploss, grad, loss);
+  TG_LAUNCHED("k_mlp_reduce");
+  return TG_OK;
 }
 
 const char* tg_status_string(tg_status s) {

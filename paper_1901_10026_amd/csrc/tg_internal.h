@@ -78,6 +78,7 @@ struct EdgeArgs {
   int64_t edge_begin, edge_end;
   uint64_t* global_sums;  // K(L)
   int gacc_in_lds;
+  uint64_t* work;         // null, or per-edge element-visit counts (added atomically, by edge id)
 };
 
 }  // namespace tg

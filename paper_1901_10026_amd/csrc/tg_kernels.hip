@@ -392,51 +392,97 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
 }
 
 // Nodes with large wedge work: a group of nodes at a time, each with a dense
-// per-node array cnt[w*L + t] and tot[w] in global memory, one wavefront per
-// (node, slot) pair; phase 0 counts, phase 1 credits, phase 2 clears.  Kernel
-// boundaries order the phases.
+// per-node array of typed middle counts cnt[w * CS + t] (CS = 8 for L <= 8,
+// else 16: one aligned row per far end w) in global memory.  Phase 0 counts,
+// phase 1 credits, phase 2 clears; kernel boundaries order the phases.
+//
+// Work mapping: wavefront q takes 64 consecutive (node, slot) pairs of the
+// group's rows; the pairs whose middle u precedes x contribute d_u wedges,
+// and the wavefront's wedges are dealt to lanes 64 at a time through a
+// wavefront prefix sum, so that lanes stay busy whatever the degrees.
+__device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int32_t* total) {
+  const int ln = lane();
+  int32_t x = v;
+  for (int off = 1; off < TG_WAVE; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, TG_WAVE);
+    if (ln >= off) x += y;
+  }
+  *total = __shfl(x, TG_WAVE - 1, TG_WAVE);
+  return x - v;
+}
+
 __global__ void __launch_bounds__(256) k_c4_group(int phase, int G, const int32_t* __restrict__ gx,
                                                   const int64_t* __restrict__ gpref, uint32_t* __restrict__ dense,
-                                                  int64_t stride, int64_t n, const int32_t* __restrict__ rp,
+                                                  int64_t stride, int CS, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, uint64_t* __restrict__ C4) {
-  const int64_t w0 = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
-  if (w0 >= gpref[G]) return;
-  int lo = 0, hi = G;  // largest g with gpref[g] <= w0
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (gpref[mid] <= w0) lo = mid; else hi = mid;
-  }
-  const int g = lo;
-  const int32_t x = gx[g];
-  const int32_t q = (int32_t)(w0 - gpref[g]);
-  const int32_t dx = deg[x], bx = rp[x];
-  const int32_t u = ci[bx + q];
-  const int32_t du = deg[u];
-  if (!precedes(du, u, dx, x)) return;
-  uint32_t* cnt = dense + (int64_t)g * stride;
-  uint32_t* tot = cnt + n * L;
-  const int phx = ty[x], phu = ty[u];
-  const int32_t bu = rp[u];
+  const int64_t wq = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
+  const int64_t total_slots = gpref[G];
+  const int64_t s0 = wq * TG_WAVE;
+  if (s0 >= total_slots) return;
   const int ln = lane();
   const int P = L * (L + 1) / 2;
-  const int32_t e_xu = s2e[bx + q];
-  for (int32_t b0 = 0; b0 < du; b0 += TG_WAVE) {
-    if (b0 + ln >= du) continue;
-    const int32_t w = ci[bu + b0 + ln];
-    if (!precedes(deg[w], w, dx, x)) continue;
+  // this lane's (node, slot) pair
+  const int64_t sl = s0 + ln;
+  int g = 0;
+  int32_t x = 0, dx = 0, u = 0, bu = 0, cu = 0, e_xu = 0;
+  int phx = 0, phu = 0;
+  if (sl < total_slots) {
+    int lo = 0, hi = G;  // largest g with gpref[g] <= sl
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (gpref[mid] <= sl) lo = mid; else hi = mid;
+    }
+    g = lo;
+    x = gx[g];
+    dx = deg[x];
+    const int32_t sx = rp[x] + (int32_t)(sl - gpref[g]);
+    u = ci[sx];
+    const int32_t du = deg[u];
+    if (precedes(du, u, dx, x)) {
+      cu = du;
+      bu = rp[u];
+      phx = ty[x];
+      phu = ty[u];
+      e_xu = s2e[sx];
+    }
+  }
+  int32_t tot = 0;
+  const int32_t excl = wave_excl_scan(cu, &tot);
+  for (int32_t c0 = 0; c0 < tot; c0 += TG_WAVE) {
+    const int32_t v = c0 + ln;
+    // owner lane: the largest l with excl[l] <= v (excl is non-decreasing)
+    int o = 0;
+    for (int step = 32; step > 0; step >>= 1) {
+      const int32_t ex = __shfl(excl, o + step, TG_WAVE);
+      if (o + step < TG_WAVE && ex <= v) o += step;
+    }
+    const int32_t o_excl = __shfl(excl, o, TG_WAVE);
+    const int32_t o_bu = __shfl(bu, o, TG_WAVE);
+    const int32_t o_x = __shfl(x, o, TG_WAVE);
+    const int32_t o_dx = __shfl(dx, o, TG_WAVE);
+    const int o_g = __shfl(g, o, TG_WAVE);
+    const int o_phx = __shfl(phx, o, TG_WAVE);
+    const int o_phu = __shfl(phu, o, TG_WAVE);
+    const int32_t o_exu = __shfl(e_xu, o, TG_WAVE);
+    if (v >= tot) continue;
+    const int32_t suw = o_bu + (v - o_excl);
+    const int32_t w = ci[suw];
+    if (!precedes(deg[w], w, o_dx, o_x)) continue;
+    uint32_t* row = dense + (int64_t)o_g * stride + (int64_t)w * CS;
     if (phase == 0) {
-      atomicAdd(&cnt[(int64_t)w * L + phu], 1u);
-      atomicAdd(&tot[w], 1u);
+      atomicAdd(&row[o_phu], 1u);
     } else if (phase == 1) {
-      if (tot[w] < 2) continue;
-      const int32_t e_uw = s2e[bu + b0 + ln];
+      uint32_t c[16];
+      uint32_t sum = 0;
+      for (int t = 0; t < L; ++t) { c[t] = row[t]; sum += c[t]; }
+      if (sum < 2) continue;
+      const int32_t e_uw = s2e[suw];
       const int phw = ty[w];
-      for (int t = 0; t < L; ++t) credit_wedge(C4, L, P, e_xu, e_uw, phx, phu, phw, t, cnt[(int64_t)w * L + t]);
+      for (int t = 0; t < L; ++t) credit_wedge(C4, L, P, o_exu, e_uw, o_phx, o_phu, phw, t, c[t]);
     } else {
-      tot[w] = 0;
-      for (int t = 0; t < L; ++t) cnt[(int64_t)w * L + t] = 0;
+      for (int t = 0; t < L; ++t) row[t] = 0u;
     }
   }
 }
@@ -530,11 +576,19 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
   }
   team_sync<NWAVES>();
 
+  // instrumented work: probes of the intersection, gathers per member of T,
+  // out-list elements scanned, epilogue entries
+  uint64_t my_work = 0;
+  if (A.work && wv == 0)
+    my_work = (uint64_t)la * (uint64_t)(1 + (lb > 0 ? 32 - __clz(lb) : 0)) + (uint64_t)nT * 3u * (uint64_t)L +
+              (uint64_t)(P + L);
+
   // typed edges inside T (4-cliques through (i, j)), each from its lower end
   for (int32_t q = wv; q < nT; q += NWAVES) {
     const int32_t k = Tid[q];
     const int tk = Tty[q];
     const int32_t o0 = A.out_off[k], o1 = A.out_off[k + 1];
+    my_work += (uint64_t)(1 + o1 - o0);
     for (int32_t c0 = o0; c0 < o1; c0 += TG_WAVE) {
       if (c0 + ln < o1) {
         const int32_t r = A.out_col[c0 + ln];
@@ -543,6 +597,7 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
       }
     }
   }
+  if (A.work && ln == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
   team_sync<NWAVES>();
 
   // per type pair: every orbit, then every graphlet

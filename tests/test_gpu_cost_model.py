@@ -1,0 +1,112 @@
+"""The learned cost model: GPU gradients against the CPU reference, training,
+identical counts under the learned schedule, and its gain over the
+degree-product heuristic on held-out edges."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from _gpu import device, note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def spearman(a, b):
+    ra = np.argsort(np.argsort(a, kind="stable"), kind="stable").astype(np.float64)
+    rb = np.argsort(np.argsort(b, kind="stable"), kind="stable").astype(np.float64)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    return float((ra * rb).sum() / np.sqrt((ra * ra).sum() * (rb * rb).sum()))
+
+
+def test_gradient_matches_cpu_reference():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    from oracle import mlp_ref
+    dev = device()
+    model = tg.CostModel(seed=5)
+    rng = np.random.default_rng(5)
+    params = model.get_params()
+    params[tg.CostModel.num_params():tg.CostModel.num_params() + 16] = rng.normal(0, 1, 16)
+    params[tg.CostModel.num_params() + 16:] = rng.uniform(0.5, 2.0, 16)
+    params[:tg.CostModel.num_params()] += rng.normal(0, 0.05, tg.CostModel.num_params()).astype(np.float32)
+    model.set_params(params)
+    X = rng.normal(0, 2, (300, 16)).astype(np.float32)
+    Y = rng.normal(3, 1, 300).astype(np.float32)
+    g, loss = model.gradient(torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    P = tg.CostModel.num_params()
+    wq = mlp_ref.bf16_round(params[:P]).astype(np.float64)
+    ref = mlp_ref.gradient(wq, params[P:], X, Y)
+    ref_loss = mlp_ref.loss(wq, params[P:], X, Y)
+    assert abs(float(loss.cpu()[0]) - ref_loss) <= 1e-4 * abs(ref_loss)
+    # per tensor: |g - ref| <= 2^-7 |ref| + 1e-3 max|ref|
+    bounds = [(0, 1024), (1024, 1088), (1088, 5184), (5184, 5248), (5248, 5312), (5312, 5313)]
+    for lo, hi in bounds:
+        r, q = ref[lo:hi], g[lo:hi]
+        tol = 2.0 ** -7 * np.abs(r) + 1e-3 * np.abs(r).max()
+        assert (np.abs(q - r) <= tol).all(), (lo, hi, np.abs(q - r).max())
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_1m()
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    model = tg.CostModel(seed=55)
+    note("training the cost model on a 1% edge sample")
+    hist = model.train(rp, ci, ty, g.L, sample_frac=0.01, seed=56, epochs=15)
+    torch.cuda.synchronize()
+    return g, rp, ci, ty, model, hist
+
+
+def test_training_reduces_loss(trained):
+    hist = trained[5]
+    note(f"loss per epoch: {[round(x, 3) for x in hist]}")
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def test_learned_schedule_gives_identical_counts(trained):
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, model, _ = trained
+    g1, r1, _ = tg.count(rp, ci, ty, g.L, schedule="degree")
+    g2, r2, _ = tg.count(rp, ci, ty, g.L, schedule="learned", model=model)
+    torch.cuda.synchronize()
+    assert torch.equal(g1.view(torch.int64), g2.view(torch.int64))
+    assert torch.equal(r1.view(torch.int64), r2.view(torch.int64))
+
+
+def test_model_ranks_edge_cost_better_than_degree_product(trained):
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, model, _ = trained
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    rng = np.random.default_rng(999)          # held out: a different seed from training
+    held = np.sort(rng.choice(len(ei), 20000, replace=False)).astype(np.int32)
+    work = tg.edge_work(rp, ci, ty, g.L, torch.from_numpy(held).to(rp.device))
+    pred = model.predict(rp, ci, ty, g.L)
+    torch.cuda.synchronize()
+    w = work.cpu().numpy().view(np.uint64)[held].astype(np.float64)
+    pr = pred.cpu().numpy()[held]
+    d = np.diff(g.row_ptr).astype(np.float64)
+    heur = d[ei[held]] * d[ej[held]]
+    rho_model, rho_heur = spearman(pr, w), spearman(heur, w)
+    note(f"Spearman vs measured work on 20k held-out edges: model {rho_model:.3f}, d_i*d_j {rho_heur:.3f}")
+    assert rho_model > rho_heur
+
+
+def test_save_and_load_round_trip(trained, tmp_path):
+    import paper_1901_10026_amd as tg
+    model = trained[4]
+    path = tmp_path / "model.bin"
+    model.save(path)
+    other = tg.CostModel(seed=1)
+    other.load(path)
+    assert np.array_equal(other.get_params(), model.get_params())

@@ -318,3 +318,35 @@ def test_dense_random_graph_hits_every_key():
     ty = (np.arange(n) % L).astype(np.uint8)
     _, glob = oracle.count_all(rp, ci, ty, L, per_edge=False, nthreads=8)
     assert len(glob) == 2220 and (glob > 0).all()
+
+
+# ------------------------------------------------------ cost-model network --
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp_ref
+    rng = np.random.default_rng(11)
+    p = rng.normal(0, 0.3, mlp_ref.NPARAM)
+    stats = np.concatenate([rng.normal(0, 1, 16), rng.uniform(0.5, 2.0, 16)])
+    X = rng.normal(0, 2, (40, 16))
+    Y = rng.normal(0, 1, 40)
+    g = mlp_ref.gradient(p, stats, X, Y)
+    idx = rng.choice(mlp_ref.NPARAM, 300, replace=False)
+    h = 1e-6
+    for q in idx:
+        a = p.copy(); a[q] += h
+        b = p.copy(); b[q] -= h
+        fd = (mlp_ref.loss(a, stats, X, Y) - mlp_ref.loss(b, stats, X, Y)) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-6 + 1e-5 * abs(g[q]), (q, fd, g[q])
+
+
+def test_bf16_rounding_reference():
+    from oracle import mlp_ref
+    x = np.array([1.0, 1.00390625, 1.005859375, 1.0078125, -3.1415926, 1e-40, np.inf], np.float32)
+    r = mlp_ref.bf16_round(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0              # tie between 1.0 and 1.0078125 rounds to even
+    assert r[2] == np.float32(1.0078125)
+    assert r[3] == np.float32(1.0078125)
+    assert r[4] == np.float32(-3.140625)
+    assert r[6] == np.inf
+    assert (r.view(np.uint32) & 0xFFFF == 0).all()
