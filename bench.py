@@ -76,6 +76,75 @@ def cpu_baseline(g, seconds, threads):
                        f"per-edge method (all rows) in {t_used:.1f} s on {threads} host threads")
 
 
+def time_count(tg, g, rp, ci, ty, out_g, out_e, steps, **kw):
+    import torch
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    s0.record(stream)
+    for _ in range(steps):
+        tg.count(rp, ci, ty, g.L, per_edge=True, out_global=out_g, out_edges=out_e, **kw)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    return s0.elapsed_time(s1) / steps
+
+
+def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=3):
+    """Degree-product schedule (default launch shapes), the same autotuned,
+    and the learned schedule (MLP trained on a 1% edge sample) autotuned; the
+    counts are the same in every case."""
+    import torch
+    res = {}
+    res["degree_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="degree")
+    log(f"degree schedule: {res['degree_ms']:.1f} ms")
+    t_deg, _ = tg.autotune(rp, ci, ty, g.L, out_g, out_e, schedule="degree")
+    res["degree_autotuned_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="degree", tuning=t_deg)
+    res["degree_tuning"] = t_deg.as_dict()
+    log(f"degree schedule, autotuned: {res['degree_autotuned_ms']:.1f} ms")
+    model = tg.CostModel(seed=55)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hist = model.train(rp, ci, ty, g.L, sample_frac=0.01, seed=56, epochs=15)
+    res["mlp_train_ms"] = (time.time() - t0) * 1e3
+    res["mlp_loss_first_last"] = [hist[0], hist[-1]]
+    t_l, _ = tg.autotune(rp, ci, ty, g.L, out_g, out_e, schedule="learned", model=model)
+    res["learned_autotuned_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="learned",
+                                             model=model, tuning=t_l)
+    res["learned_tuning"] = t_l.as_dict()
+    log(f"learned schedule, autotuned: {res['learned_autotuned_ms']:.1f} ms (training {res['mlp_train_ms']:.0f} ms)")
+    return res
+
+
+def batch_leg(tg, dev, steps=3):
+    """100,000 small typed graphs (n log-uniform in [10, 500], density
+    U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
+    import torch
+
+    import graphgen
+    b = graphgen.batch_gnp(100_000, 10, 500, 0.02, 0.3, 2, 8, 4)
+    key_off = tg.key_offsets(b.L)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
+    args = (t(b.node_off, np.int64), t(b.slot_off, np.int64), t(b.row_ptr, np.int32), t(b.col_idx, np.int32),
+            t(b.types, np.uint8), t(b.L, np.uint8), t(key_off, np.int64))
+    out = torch.empty(int(key_off[-1]), dtype=torch.uint64, device=dev)
+    tg.count_batch(*args, out=out)
+    tuning, _ = tg.autotune_batch(*args, out)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(steps):
+        tg.count_batch(*args, out=out, tuning=tuning)
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / steps
+    m = int(b.slot_off[-1]) // 2
+    log(f"batch: {b.G} graphs, {m} edges, {ms:.1f} ms")
+    return {"workload": "gnp-batch-100k", "graphs": b.G, "edges": m, "ms_per_call": ms,
+            "graphs_per_s": b.G / (ms * 1e-3), "edges_per_s": m / (ms * 1e-3), "tuning": tuning.as_dict()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +154,8 @@ def main():
     ap.add_argument("--schedule", default="degree", choices=["none", "degree", "learned"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (edges would shard by range, "
@@ -166,6 +237,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes": cb, "traffic": None},
     }
+    if not args.no_compare:
+        rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)
+    if not args.no_batch:
+        rec["batch"] = batch_leg(tg, dev)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle for ~{args.cpu_seconds:.0f} s on {threads} threads")

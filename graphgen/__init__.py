@@ -247,9 +247,42 @@ def chung_lu_1m(mean=None) -> Graph:
                                              types="zipf1.2+homophily0.7"))
 
 
+def bipartite_50m() -> Graph:
+    """Bipartite Chung-Lu user-item graph: 2M type-0 nodes (exponent 2.1,
+    mean 25, max expected degree 2e4) and 500k type-1 nodes (exponent 1.8,
+    mean 100, max expected degree 1e5), 50M expected edges, only between the
+    two sides; L=2 with the side as the type; seed 31."""
+    rp, ci, parts = kpartite_cl([2_000_000, 500_000], [2.1, 1.8], [2e4, 1e5], [25.0, 100.0], 50_000_000, 31)
+    return Graph("bip-50m", rp, ci, parts, 2, dict(model="bipartite-chung-lu", sizes=[2_000_000, 500_000],
+                                                  gamma=[2.1, 1.8], wmax=[2e4, 1e5], mean=[25, 100], seed=31))
+
+
+def tripartite_30m() -> Graph:
+    """3-partite Chung-Lu graph: parts of 1M, 1M and 200k nodes (types 0, 1,
+    2), power-law weights with exponent 2.1 and max expected degree 2e4 in
+    every part, 30M expected edges, only between different parts; seed 32."""
+    rp, ci, parts = kpartite_cl([1_000_000, 1_000_000, 200_000], [2.1, 2.1, 2.1], [2e4, 2e4, 2e4],
+                                [27.3, 27.3, 27.3], 30_000_000, 32)
+    return Graph("tri-30m", rp, ci, parts, 3, dict(model="3-partite-chung-lu", sizes=[1_000_000, 1_000_000, 200_000],
+                                                  gamma=2.1, wmax=2e4, seed=32))
+
+
+def chung_lu_20m() -> Graph:
+    """Chung-Lu, n=20M, exponent 2.0, max expected degree 5e5, mean 30
+    (about 3e8 edges before probability capping), L=8 types iid Zipf(1.0),
+    seed 5."""
+    rp, ci = chung_lu(20_000_000, 2.0, 5e5, 30.0, 5)
+    ty = types_zipf(20_000_000, 8, 1.0, 5)
+    return Graph("cl-20m", rp, ci, ty, 8, dict(model="chung-lu", gamma=2.0, wmax=5e5, mean=30.0, seed=5,
+                                              types="zipf1.0"))
+
+
 WORKLOADS = {
     "cl-2k": chung_lu_small,
     "cl-1m": chung_lu_1m,
+    "bip-50m": bipartite_50m,
+    "tri-30m": tripartite_30m,
+    "cl-20m": chung_lu_20m,
 }
 
 

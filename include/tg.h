@@ -83,7 +83,11 @@ typedef struct tg_cost_model tg_cost_model;
 /* Launch-shape choices (defaults from tg_tuning_default; tg_autotune picks
  * them by timing).  Counts never depend on them. */
 typedef struct {
+  int32_t light_max_degree;   /* tg_count: edges with |T_ij| <= 64 and min(d_i, d_j) <= this use a
+                                 16-lane team (L <= 8) */
   int32_t heavy_min_degree;   /* tg_count: edges with min(d_i, d_j) above this use one workgroup */
+  int32_t mid_log2_cost;      /* tg_count: edges whose log2 schedule cost exceeds this use at least
+                                 a full wavefront (64 = never) */
   int32_t heavy_log2_cost;    /* tg_count: edges whose log2 schedule cost exceeds this use one
                                  workgroup (64 = never) */
   int32_t combine_grid;       /* tg_count: workgroups of the one-wavefront-per-edge launch */
@@ -234,6 +238,24 @@ tg_status tg_cost_model_set_params(tg_cost_model* model, const float* params);
 /* Binary file with the parameters and statistics. */
 tg_status tg_cost_model_save(const tg_cost_model* model, const char* path);
 tg_status tg_cost_model_load(tg_cost_model* model, const char* path);
+
+/* ---- autotuning.  Both searches time real calls on the caller's data
+ * (counts are rewritten with identical values) and only change launch
+ * shapes. */
+
+/* Coordinate descent over tg_tuning's tg_count fields, timing the per-edge
+ * combine phase with HIP events; base supplies the schedule and model (NULL:
+ * defaults).  Outputs as in tg_count (edge_counts may be NULL). */
+tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
+                      const tg_options* base, tg_tuning* tuning, float* best_ms, hipStream_t stream);
+
+/* Chooses tg_tuning.batch_variant per size class by timing whole
+ * tg_count_batch calls; *tuning is the starting point and the result. */
+tg_status tg_autotune_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
+                            const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
+                            const int64_t* key_off, uint64_t* global_counts, tg_tuning* tuning, float* best_ms,
+                            hipStream_t stream);
 
 /* Human-readable name of a status code (static string). */
 const char* tg_status_string(tg_status s);

@@ -56,12 +56,15 @@ def declared_symbols():
 
 class Tuning(ctypes.Structure):
     """Launch-shape choices (tg_tuning); counts never depend on them."""
-    _fields_ = [("heavy_min_degree", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
+    _fields_ = [("light_max_degree", ctypes.c_int32), ("heavy_min_degree", ctypes.c_int32),
+                ("mid_log2_cost", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
                 ("combine_grid", ctypes.c_int32), ("batch_variant", ctypes.c_int32 * 9)]
+    SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid")
 
     def as_dict(self):
-        return {"heavy_min_degree": self.heavy_min_degree, "heavy_log2_cost": self.heavy_log2_cost,
-                "combine_grid": self.combine_grid, "batch_variant": list(self.batch_variant)}
+        d = {k: int(getattr(self, k)) for k in self.SCALARS}
+        d["batch_variant"] = list(self.batch_variant)
+        return d
 
     @classmethod
     def default(cls):
@@ -72,7 +75,7 @@ class Tuning(ctypes.Structure):
     @classmethod
     def from_dict(cls, d):
         t = cls.default()
-        for k in ("heavy_min_degree", "heavy_log2_cost", "combine_grid"):
+        for k in cls.SCALARS:
             if k in d:
                 setattr(t, k, int(d[k]))
         if "batch_variant" in d:
@@ -118,6 +121,12 @@ def lib():
     L.tg_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_tuning_default.restype = None
     L.tg_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
+    L.tg_autotune.restype = i32
+    L.tg_autotune.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, ctypes.POINTER(_Options), ctypes.POINTER(Tuning),
+                              ctypes.POINTER(ctypes.c_float), vp]
+    L.tg_autotune_batch.restype = i32
+    L.tg_autotune_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Tuning),
+                                    ctypes.POINTER(ctypes.c_float), vp]
     L.tg_cost_model_num_params.restype = sz
     L.tg_cost_model_num_params.argtypes = []
     L.tg_cost_model_create.restype = i32
@@ -347,3 +356,63 @@ def edge_work(row_ptr, col_idx, types, L, edges):
                               types.data_ptr(), L, edges.data_ptr(), edges.numel(), out.data_ptr(),
                               _stream_handle(torch, row_ptr.device)))
     return out
+
+
+def autotune(row_ptr, col_idx, types, L, out_global, out_edges=None, schedule="degree", model=None, start=None):
+    """Chooses tg_count launch shapes by timing (tg_autotune).  Returns
+    (Tuning, best combine-phase milliseconds)."""
+    import torch
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.schedule = SCHEDULES[schedule]
+    opt.model = model.handle if model is not None else None
+    opt.tuning = ctypes.cast(ctypes.pointer(start), ctypes.c_void_p) if start is not None else None
+    t = Tuning.default()
+    best = ctypes.c_float()
+    _check(lib().tg_autotune(row_ptr.numel() - 1, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(),
+                             types.data_ptr(), L, out_global.data_ptr(),
+                             out_edges.data_ptr() if out_edges is not None else None, ctypes.byref(opt),
+                             ctypes.byref(t), ctypes.byref(best), _stream_handle(torch, row_ptr.device)))
+    return t, float(best.value)
+
+
+def autotune_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_off, out, start=None):
+    """Chooses tg_count_batch kernel variants per size class by timing.
+    Returns (Tuning, best milliseconds)."""
+    import torch
+    t = start if start is not None else Tuning.default()
+    best = ctypes.c_float()
+    _check(lib().tg_autotune_batch(node_off.numel() - 1, node_off.data_ptr(), slot_off.data_ptr(), row_ptr.data_ptr(),
+                                   col_idx.data_ptr(), types.data_ptr(), L_per_graph.data_ptr(), key_off.data_ptr(),
+                                   out.data_ptr(), ctypes.byref(t), ctypes.byref(best),
+                                   _stream_handle(torch, node_off.device)))
+    return t, float(best.value)
+
+
+def tuning_cache_key(kind, **sig):
+    """Cache key of a tuning: device name, kind and a workload signature."""
+    import torch
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return name + "|" + kind + "|" + "|".join(f"{k}={sig[k]}" for k in sorted(sig))
+
+
+def load_tuning(path, key):
+    import json
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return Tuning.from_dict(d[key]) if key in d else None
+
+
+def save_tuning(path, key, tuning):
+    import json
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[key] = tuning.as_dict()
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)

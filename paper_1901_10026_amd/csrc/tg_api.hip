@@ -199,7 +199,7 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   TG_HIP(S.get(&W.C4, m * P));
   TG_HIP(S.get(&W.elist, m));
   TG_HIP(S.get(&W.nlist, n));
-  TG_HIP(S.get(&W.counters, 256));
+  TG_HIP(S.get(&W.counters, 512));
 
   // ---- prep
   if (timer) timer->mark(TG_PHASE_PREP);
@@ -216,8 +216,10 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
 
   // ---- typed triangles per edge, node tables
   if (timer) timer->mark(TG_PHASE_TAU);
-  k_tau<<<grid_for(m, 4), 256, 0, st>>>(m, nullptr, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
-  TG_LAUNCHED("k_tau");
+  k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  TG_LAUNCHED("k_tau<16>");
+  k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  TG_LAUNCHED("k_tau<64>");
   if (timer) timer->mark(TG_PHASE_TABLES);
   k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D, W.tau,
                                                                                      W.s2e, W.Pn, W.Un);
@@ -273,7 +275,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   tg_tuning tune;
   tg_tuning_default(&tune);
   if (opt.tuning) tune = *opt.tuning;
-  BinParams bp{mode, std::max(1, tune.heavy_min_degree), std::min(64, std::max(0, tune.heavy_log2_cost))};
+  BinParams bp{mode,
+               std::max(1, tune.light_max_degree),
+               std::max(1, tune.heavy_min_degree),
+               std::min(64, std::max(0, tune.mid_log2_cost)),
+               std::min(64, std::max(0, tune.heavy_log2_cost)),
+               L <= 8 ? 1 : 0};
   const float* pred = nullptr;
   if (mode == 2) {
     float* p;
@@ -282,45 +289,48 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     if (s != TG_OK) return s;
     pred = p;
   }
-  int32_t* cnt = W.counters;           // [0,128) edge bins, [128,132) node tiers, [132] max heavy |T|
-  TG_HIP(hipMemsetAsync(cnt, 0, 256 * sizeof(int32_t), st));
+  // counters: [0,192) edge bins (class * 64 + bucket), [256,260) node tiers,
+  // [264] max |T| of workgroup-class edges, [272] divisibility flag
+  int32_t* cnt = W.counters;
+  TG_HIP(hipMemsetAsync(cnt, 0, 512 * sizeof(int32_t), st));
   k_edge_bin_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
-                                                           (uint32_t*)(cnt + 132));
+                                                           (uint32_t*)(cnt + 264));
   TG_LAUNCHED("k_edge_bin_count");
-  k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128);
+  k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256);
   TG_LAUNCHED("k_node_tier_count");
-  int32_t h_cnt[256];
+  int32_t h_cnt[512];
   TG_HIP(hipMemcpyAsync(h_cnt, cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
   TG_HIP(hipStreamSynchronize(st));
-  int32_t cur[256];
+  int32_t cur[512];
   memset(cur, 0, sizeof(cur));
-  int64_t acc = 0;
-  for (int b = 0; b < 128; ++b) { cur[b] = (int32_t)acc; acc += h_cnt[b]; }
-  int64_t n_heavy = 0;
-  for (int b = 64; b < 128; ++b) n_heavy += h_cnt[b];
-  const int64_t n_light_edges = m - n_heavy;
+  int64_t acc = 0, class_begin[3], class_count[3];
+  for (int c = 0; c < 3; ++c) {
+    class_begin[c] = acc;
+    for (int b = 0; b < 64; ++b) { cur[c * 64 + b] = (int32_t)acc; acc += h_cnt[c * 64 + b]; }
+    class_count[c] = acc - class_begin[c];
+  }
   int64_t nacc = 0;
-  for (int t = 0; t < 4; ++t) { cur[128 + t] = (int32_t)nacc; nacc += h_cnt[128 + t]; }
-  const int64_t max_t_heavy = (uint32_t)h_cnt[132];
-  TG_HIP(hipMemcpyAsync(cnt, cur, sizeof(cur), hipMemcpyHostToDevice, st));
+  for (int t = 0; t < 4; ++t) { cur[256 + t] = (int32_t)nacc; nacc += h_cnt[256 + t]; }
+  const int64_t max_t_heavy = (uint32_t)h_cnt[264];
+  TG_HIP(hipMemcpyAsync(cnt, cur, 264 * sizeof(int32_t), hipMemcpyHostToDevice, st));
   k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
                                                              W.elist);
   TG_LAUNCHED("k_edge_bin_scatter");
-  k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 128, W.nlist);
+  k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256, W.nlist);
   TG_LAUNCHED("k_node_tier_scatter");
 
   // ---- non-induced typed 4-cycles per edge
   timer.mark(TG_PHASE_CYCLES);
   k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
   TG_LAUNCHED("k_fill_u64");
-  const int64_t n_t1 = h_cnt[129], n_t2 = h_cnt[130], n_t3 = h_cnt[131];
+  const int64_t n_t1 = h_cnt[257], n_t2 = h_cnt[258], n_t3 = h_cnt[259];
   if (n_t1 > 0) {
-    k_c4_hash<1, 8><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[129], rp, ci, W.deg, ty, L, W.s2e,
+    k_c4_hash<1, 8><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty, L, W.s2e,
                                                              W.C4);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (n_t2 > 0) {
-    k_c4_hash<4, 12><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[130], rp, ci, W.deg, ty, L, W.s2e,
+    k_c4_hash<4, 12><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg, ty, L, W.s2e,
                                                               W.C4);
     TG_LAUNCHED("k_c4_hash<4>");
   }
@@ -329,7 +339,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     std::vector<int32_t> hx(n_t3);
     std::vector<uint64_t> hw(n_t3);
     std::vector<int32_t> hd(n_t3);
-    TG_HIP(hipMemcpyAsync(hx.data(), W.nlist + cur[131], n_t3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipMemcpyAsync(hx.data(), W.nlist + cur[259], n_t3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     TG_HIP(hipStreamSynchronize(st));
     // gather W and degree of the listed nodes on the host side of the copy
     {
@@ -339,7 +349,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       TG_HIP(S.get(&d_idx, n_t3));
       TG_HIP(S.get(&d_w, n_t3));
       TG_HIP(S.get(&d_d, n_t3));
-      k_gather_node_info<<<grid_for(n_t3, 256, 8192), 256, 0, st>>>(n_t3, W.nlist + cur[131], W.wedge_work, W.deg,
+      k_gather_node_info<<<grid_for(n_t3, 256, 8192), 256, 0, st>>>(n_t3, W.nlist + cur[259], W.wedge_work, W.deg,
                                                                     d_w, d_d);
       TG_LAUNCHED("k_gather_node_info");
       TG_HIP(hipMemcpyAsync(hw.data(), d_w, n_t3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
@@ -400,29 +410,36 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
   A.work = nullptr;
   const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
-  if (n_light_edges > 0) {
-    const size_t lds = gbytes + 4 * 4 * LL * sizeof(uint64_t) + 4 * TG_T_WAVE_CAP * (sizeof(int32_t) + 1);
-    k_combine_wave<<<grid_for(n_light_edges, 4, std::max(1, tune.combine_grid)), 256, lds, st>>>(A, n_light_edges,
-                                                                                               W.elist, (int)K);
-    TG_LAUNCHED("k_combine_wave");
+  const int kl = A.gacc_in_lds ? (int)K : 0;
+  if (class_count[0] > 0) {
+    const size_t lds = combine_lds_bytes<16, uint32_t>(L, kl);
+    k_combine<16, uint32_t><<<grid_for(class_count[0], 16, std::max(1, tune.combine_grid)), 256, lds, st>>>(
+        A, class_count[0], W.elist + class_begin[0], (int)K, nullptr, 0);
+    TG_LAUNCHED("k_combine<16>");
   }
-  if (n_heavy > 0) {
-    const unsigned grid = grid_for(n_heavy, 1, 1024);
+  if (class_count[1] > 0) {
+    const size_t lds = combine_lds_bytes<64, uint32_t>(L, kl);
+    k_combine<64, uint32_t><<<grid_for(class_count[1], 4, std::max(1, tune.combine_grid)), 256, lds, st>>>(
+        A, class_count[1], W.elist + class_begin[1], (int)K, nullptr, 0);
+    TG_LAUNCHED("k_combine<64>");
+  }
+  if (class_count[2] > 0) {
+    const unsigned grid = grid_for(class_count[2], 1, 1024);
     int32_t* t_over = nullptr;
     int64_t t_cap = 0;
     if (max_t_heavy > TG_T_WG_CAP) {
       t_cap = max_t_heavy;
       TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
     }
-    const size_t lds = gbytes + 4 * LL * sizeof(uint64_t) + 4 * sizeof(int32_t) +
-                       TG_T_WG_CAP * (sizeof(int32_t) + 1);
-    k_combine_wg<<<grid, 256, lds, st>>>(A, n_heavy, W.elist + n_light_edges, (int)K, t_over, t_cap);
-    TG_LAUNCHED("k_combine_wg");
+    const size_t lds = combine_lds_bytes<256, uint64_t>(L, kl);
+    k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, class_count[2], W.elist + class_begin[2], (int)K, t_over,
+                                                     t_cap);
+    TG_LAUNCHED("k_combine<256>");
   }
 
   // ---- Eq. 17 and outputs
   timer.mark(TG_PHASE_FINALIZE);
-  int32_t* flag = cnt + 200;
+  int32_t* flag = cnt + 272;
   TG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
   k_finalize<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, L, flag);
   TG_LAUNCHED("k_finalize");
@@ -696,9 +713,9 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
     t_cap = h_tmax;
     TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
   }
-  const size_t lds = 4 * LL * sizeof(uint64_t) + 4 * sizeof(int32_t) + TG_T_WG_CAP * (sizeof(int32_t) + 1);
-  k_combine_wg<<<grid, 256, lds, st>>>(A, count, list, (int)K, t_over, t_cap);
-  TG_LAUNCHED("k_combine_wg");
+  const size_t lds = combine_lds_bytes<256, uint64_t>(L, 0);
+  k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, count, list, (int)K, t_over, t_cap);
+  TG_LAUNCHED("k_combine<256>");
   return TG_OK;
 }
 
@@ -842,7 +859,9 @@ void tg_options_default(tg_options* opt) {
 
 void tg_tuning_default(tg_tuning* t) {
   if (!t) return;
+  t->light_max_degree = 256;
   t->heavy_min_degree = 4096;
+  t->mid_log2_cost = 64;
   t->heavy_log2_cost = 64;
   t->combine_grid = 2048;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
@@ -1061,6 +1080,115 @@ tg_status tg_cost_model_gradient(const tg_cost_model* md, const float* X, const 
   TG_LAUNCHED("k_mlp_backward");
   k_mlp_reduce<<<grid_for(TG_MLP_NPARAM, 256, 64), 256, 0, stream>>>(nb, partial, ploss, grad, loss);
   TG_LAUNCHED("k_mlp_reduce");
+  return TG_OK;
+}
+
+tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
+                      const tg_options* base, tg_tuning* tuning, float* best_ms, hipStream_t stream) {
+  if (!tuning) return fail(TG_ERR_INVALID_ARG, "null tuning output");
+  tg_options opt;
+  tg_options_default(&opt);
+  if (base) opt = *base;
+  opt.edge_begin = 0;
+  opt.edge_end = -1;
+  tg_tuning cur;
+  tg_tuning_default(&cur);
+  if (base && base->tuning) cur = *base->tuning;
+  float ph[TG_NUM_PHASES];
+  opt.phase_ms = ph;
+  auto trial = [&](const tg_tuning& t, float* ms) -> tg_status {
+    opt.tuning = &t;
+    tg_status s = tg_count(n, nnz, row_ptr, col_idx, node_types, L, global_counts, edge_counts, nullptr, &opt,
+                           stream);
+    *ms = ph[TG_PHASE_COMBINE];
+    return s;
+  };
+  float best = 0.0f;
+  if (tg_status s = trial(cur, &best)) return s;   // warm-up of the pool and caches
+  if (tg_status s = trial(cur, &best)) return s;
+  const bool learned = opt.schedule == TG_SCHED_LEARNED;
+  // coordinate descent over one parameter at a time (counts never change)
+  std::vector<std::pair<int32_t*, std::vector<int32_t>>> axes;
+  tg_tuning t = cur;
+  axes.push_back({&t.light_max_degree, {16, 64, 256, 1024}});
+  axes.push_back({&t.heavy_min_degree, {1024, 4096, 16384}});
+  if (opt.schedule != TG_SCHED_NONE) {
+    if (learned) {
+      axes.push_back({&t.mid_log2_cost, {64, 10, 12, 14, 16}});
+      axes.push_back({&t.heavy_log2_cost, {64, 14, 16, 18, 20}});
+    } else {
+      axes.push_back({&t.mid_log2_cost, {64, 12, 14, 16, 18}});
+      axes.push_back({&t.heavy_log2_cost, {64, 18, 20, 22, 24}});
+    }
+  }
+  axes.push_back({&t.combine_grid, {1024, 2048, 4096, 8192}});
+  for (auto& ax : axes) {
+    int32_t best_v = *ax.first;
+    for (int32_t v : ax.second) {
+      if (v == best_v) continue;
+      *ax.first = v;
+      float ms = 0.0f;
+      if (tg_status s = trial(t, &ms)) return s;
+      if (ms < best) { best = ms; best_v = v; }
+    }
+    *ax.first = best_v;
+  }
+  *tuning = t;
+  if (best_ms) *best_ms = best;
+  return TG_OK;
+}
+
+tg_status tg_autotune_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
+                            const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
+                            const int64_t* key_off, uint64_t* global_counts, tg_tuning* tuning, float* best_ms,
+                            hipStream_t stream) {
+  if (!tuning) return fail(TG_ERR_INVALID_ARG, "null tuning output");
+  tg_tuning t = *tuning;
+  tg_options opt;
+  tg_options_default(&opt);
+  opt.check = 1;
+  hipEvent_t e0, e1;
+  TG_HIP(hipEventCreate(&e0));
+  TG_HIP(hipEventCreate(&e1));
+  auto trial = [&](const tg_tuning& tt, float* ms) -> tg_status {
+    opt.tuning = &tt;
+    tg_status s = TG_OK;
+    float best_of = 1e30f;
+    for (int rep = 0; rep < 2 && s == TG_OK; ++rep) {
+      if (hipEventRecord(e0, stream) != hipSuccess) return fail(TG_ERR_HIP, "hipEventRecord");
+      s = tg_count_batch(G, node_off, slot_off, row_ptr_local, col_idx_local, node_types, L_per_graph, key_off,
+                         global_counts, &opt, stream);
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(TG_ERR_HIP, "hipEvent timing");
+      float x = 0.0f;
+      (void)hipEventElapsedTime(&x, e0, e1);
+      best_of = std::min(best_of, x);
+    }
+    *ms = best_of;
+    return s;
+  };
+  float best = 0.0f;
+  tg_status st = trial(t, &best);
+  // variants able to hold each size class W (words per bit row)
+  const int wmax[6] = {1, 2, 2, 4, 4, 8};
+  for (int w = 8; w >= 1 && st == TG_OK; --w) {
+    int best_v = t.batch_variant[w];
+    for (int v = 0; v < 6 && st == TG_OK; ++v) {
+      if (wmax[v] < w || v == best_v) continue;
+      t.batch_variant[w] = v;
+      float ms = 0.0f;
+      st = trial(t, &ms);
+      if (st == TG_OK && ms < best) { best = ms; best_v = v; }
+    }
+    t.batch_variant[w] = best_v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TG_OK) return st;
+  t.batch_variant[0] = t.batch_variant[1];
+  *tuning = t;
+  if (best_ms) *best_ms = best;
   return TG_OK;
 }
 

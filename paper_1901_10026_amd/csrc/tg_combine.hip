@@ -1,0 +1,345 @@
+// ------------------------------------------------------------- combine --
+//
+// Per edge (i, j), with T = T_ij, S_i, S_j, I as in Section 4 and ordered
+// typed pair counts E(X^t, Y^u) = #{(k, r): k in X of type t, r in Y of type
+// u, k ~ r}:
+//   A_i[t][u] = sum_{k in T^t} tau_(i,k)[u],  A_j likewise,
+//   Q[t][u]   = sum_{k in T^t} D[k][u],
+//   Mu[t][u]  = edges {k, r} inside T with k preceding r, typed (phi_k, phi_r),
+//   M(t,u)    = Mu[t][u] + Mu[u][t] = E(T^t, T^u).
+// Every neighbour of k in T is i, j, or in T, S_i, S_j or I, and every
+// neighbour of k in S_i is i or in T, S_i, S_j or I.  Hence
+//   E(T^t, S_i^u) = A_i[t][u] - |T^t| [phi_j = u] - M(t,u)
+//   E(T^t, I^u)   = Q[t][u] - |T^t| ([phi_i=u] + [phi_j=u]) - M - E(T,S_i) - E(T,S_j)
+//   E(S_i^t, S_i^u) = U[i][t][u] - [phi_j=t] |T^u| - A_i[t][u] - E(T^u, S_i^t)
+//   E(S_i^t, I^u) = P[i][t][u] - [phi_j=t] D[j][u] - Q[t][u] - |S_i^t| [phi_i=u]
+//                   - E(T^u, S_i^t) - E(S_i^t, S_i^u) - E(S_i^t, S_j^u)
+// and the non-induced 4-cycle count through (i, j) is g6 + g10 + 2 g12.  With
+// sym(X){t,u} = X[t][u] + X[u][t] (t != u) or X[t][t], the explicit orbits of
+// Algorithms 2-3 are
+//   g12 = sym(Mu), g10 = sym(E(T,S_i) + E(T,S_j)), g8 = sym(E(T,I)),
+//   g7 = (sym(E(S_i,S_i)) + sym(E(S_j,S_j))) / 2, g6 = C4 - g10 - 2 g12,
+//   g3 = sym(E(S_i,I) + E(S_j,I)),
+// then g4, g5, g9, g11 follow from Eqs. 7-10 and the graphlets from Eqs. 11-16.
+//
+// One team of TSIZE lanes (16 or 64 lanes of a wavefront, or a 256-lane
+// workgroup) handles one edge at a time.  AccT is the width of the LDS
+// accumulators (32 bits suffices when |T_ij| is small).
+
+template <int TSIZE>
+__device__ __forceinline__ void tsync() {
+  if (TSIZE <= TG_WAVE) wave_sync();
+  else __syncthreads();
+}
+
+// lanes of this thread's team, as bits 0..TSIZE-1 (TSIZE <= 64)
+template <int TSIZE>
+__device__ __forceinline__ uint64_t team_bits(uint64_t mask) {
+  if (TSIZE >= TG_WAVE) return mask;
+  const int sh = (lane() / TSIZE) * TSIZE;
+  return (mask >> sh) & ((1ull << TSIZE) - 1ull);
+}
+
+__device__ __forceinline__ uint64_t bits_below(int tl) { return tl == 0 ? 0ull : (~0ull >> (64 - tl)); }
+
+// Exclusive prefix sum over the team; *total gets the team sum.  For
+// TSIZE == 256, scratch holds 4 + 256 ints of LDS.
+template <int TSIZE>
+__device__ __forceinline__ int32_t team_excl_scan(int32_t v, int32_t* total, int32_t* scratch, int tid) {
+  if (TSIZE <= TG_WAVE) {
+    const int tl = tid;
+    int32_t x = v;
+    for (int off = 1; off < TSIZE; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, TSIZE);
+      if (tl >= off) x += y;
+    }
+    *total = __shfl(x, TSIZE - 1, TSIZE);
+    return x - v;
+  } else {
+    const int ln = lane(), wv = tid / TG_WAVE;
+    int32_t x = v;
+    for (int off = 1; off < TG_WAVE; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, TG_WAVE);
+      if (ln >= off) x += y;
+    }
+    if (ln == TG_WAVE - 1) scratch[wv] = x;
+    __syncthreads();
+    int32_t before = 0, tot = 0;
+    for (int q = 0; q < TSIZE / TG_WAVE; ++q) {
+      const int32_t c = scratch[q];
+      if (q < wv) before += c;
+      tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + x - v;
+  }
+}
+
+template <int TSIZE, class AccT>
+__device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
+                                             AccT* __restrict__ acc, uint64_t* gacc, int32_t* scratch, int tid) {
+  const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
+  const int R = 2 * L + 6 * P;
+  AccT* Aa = acc;
+  AccT* Ab = acc + LL;
+  AccT* Q = acc + 2 * LL;
+  AccT* Mu = acc + 3 * LL;
+  for (int x = tid; x < 4 * LL; x += TSIZE) acc[x] = 0;
+  tsync<TSIZE>();
+  const int32_t i = A.ei[e], j = A.ej[e];
+  const int32_t di = A.deg[i], dj = A.deg[j];
+  const bool a_is_i = di <= dj;
+  const int32_t a = a_is_i ? i : j, b = a_is_i ? j : i;
+  const int32_t la = a_is_i ? di : dj, lb = a_is_i ? dj : di;
+  const int32_t ra = A.rp[a], rb = A.rp[b];
+  const int wv = tid / TG_WAVE;
+
+  // ---- T_ij with the sums of tau and D over its members
+  int32_t nT = 0;
+  for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
+    const int32_t idx = b0 + tid;
+    bool found = false;
+    int32_t k = 0, p = 0;
+    if (idx < la) {
+      k = A.ci[ra + idx];
+      p = lower_bound(A.ci + rb, lb, k);
+      found = p < lb && A.ci[rb + p] == k;
+    }
+    int t = 0;
+    if (found) {
+      t = A.ty[k];
+      const int64_t ea = A.s2e[ra + idx], eb = A.s2e[rb + p];
+      for (int u = 0; u < L; ++u) {
+        const uint32_t va = A.tau[ea * L + u];
+        if (va) atomicAdd(&Aa[t * L + u], (AccT)va);
+        const uint32_t vb = A.tau[eb * L + u];
+        if (vb) atomicAdd(&Ab[t * L + u], (AccT)vb);
+        const uint32_t vd = A.D[(int64_t)k * L + u];
+        if (vd) atomicAdd(&Q[t * L + u], (AccT)vd);
+      }
+    }
+    const uint64_t wmask = ballot(found);
+    int32_t before, total;
+    if (TSIZE <= TG_WAVE) {
+      const uint64_t tm = team_bits<TSIZE>(wmask);
+      before = __popcll(tm & bits_below(tid));
+      total = __popcll(tm);
+    } else {
+      if (lane() == 0) scratch[wv] = __popcll(wmask);
+      __syncthreads();
+      before = __popcll(wmask & bits_below(lane()));
+      total = 0;
+      for (int q = 0; q < TSIZE / TG_WAVE; ++q) {
+        const int32_t c = scratch[q];
+        if (q < wv) before += c;
+        total += c;
+      }
+      __syncthreads();
+    }
+    if (found) {
+      Tid[nT + before] = k;
+      Tty[nT + before] = (uint8_t)t;
+    }
+    nT += total;
+  }
+  tsync<TSIZE>();
+
+  uint64_t my_work = 0;
+  if (A.work && tid == 0)
+    my_work = (uint64_t)la * (uint64_t)(1 + (lb > 0 ? 32 - __clz(lb) : 0)) + (uint64_t)nT * 3u * (uint64_t)L +
+              (uint64_t)(P + L);
+
+  // ---- typed edges inside T (4-cliques through (i, j)), each found from its
+  // lower end's degree-ordered out-list; (member, out-slot) pairs are dealt
+  // to lanes through a team prefix sum
+  int32_t* s_excl = scratch + 8;  // TSIZE == 256 only
+  for (int32_t q0 = 0; q0 < nT; q0 += TSIZE) {
+    const int32_t q = q0 + tid;
+    int32_t ostart = 0, ocnt = 0, tk = 0;
+    if (q < nT) {
+      const int32_t k = Tid[q];
+      ostart = A.out_off[k];
+      ocnt = A.out_off[k + 1] - ostart;
+      tk = Tty[q];
+    }
+    int32_t tot;
+    const int32_t excl = team_excl_scan<TSIZE>(ocnt, &tot, scratch, tid);
+    if (A.work && tid == 0) my_work += (uint64_t)tot + (uint64_t)min(TSIZE, nT - q0);
+    if (TSIZE > TG_WAVE) {
+      s_excl[tid] = excl;
+      s_excl[TSIZE + tid] = ostart;
+      s_excl[2 * TSIZE + tid] = tk;
+      __syncthreads();
+    }
+    for (int32_t c0 = 0; c0 < tot; c0 += TSIZE) {
+      const int32_t v = c0 + tid;
+      int o = 0;
+      int32_t o_excl, o_start, o_tk;
+      if (TSIZE <= TG_WAVE) {
+        for (int step = TSIZE / 2; step > 0; step >>= 1) {
+          const int32_t ex = __shfl(excl, o + step, TSIZE);
+          if (ex <= v) o += step;
+        }
+        o_excl = __shfl(excl, o, TSIZE);
+        o_start = __shfl(ostart, o, TSIZE);
+        o_tk = __shfl(tk, o, TSIZE);
+      } else {
+        for (int step = TSIZE / 2; step > 0; step >>= 1)
+          if (s_excl[o + step] <= v) o += step;
+        o_excl = s_excl[o];
+        o_start = s_excl[TSIZE + o];
+        o_tk = s_excl[2 * TSIZE + o];
+      }
+      if (v < tot) {
+        const int32_t r = A.out_col[o_start + (v - o_excl)];
+        const int32_t pp = lower_bound(Tid, nT, r);
+        if (pp < nT && Tid[pp] == r) atomicAdd(&Mu[o_tk * L + Tty[pp]], (AccT)1);
+      }
+    }
+    if (TSIZE > TG_WAVE) __syncthreads();
+  }
+  if (A.work && tid == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
+  tsync<TSIZE>();
+
+  // ---- per type pair: every orbit, then every graphlet
+  const int pi = A.ty[i], pj = A.ty[j];
+  const AccT* Ai = a_is_i ? Aa : Ab;
+  const AccT* Aj = a_is_i ? Ab : Aa;
+  const uint32_t* tau_e = A.tau + (int64_t)e * L;
+  const uint32_t* Di = A.D + (int64_t)i * L;
+  const uint32_t* Dj = A.D + (int64_t)j * L;
+  const uint64_t* Ui = A.Un + (int64_t)i * LL;
+  const uint64_t* Uj = A.Un + (int64_t)j * LL;
+  const uint64_t* Pi = A.Pn + (int64_t)i * LL;
+  const uint64_t* Pj = A.Pn + (int64_t)j * LL;
+  uint64_t* row = (A.edge_counts && e >= A.edge_begin && e < A.edge_end)
+                      ? A.edge_counts + (int64_t)(e - A.edge_begin) * R : nullptr;
+  auto gadd = [&](int64_t key, int64_t v) {
+    if (v == 0) return;
+    if (gacc) atomicAdd((unsigned long long*)&gacc[key], (unsigned long long)v);
+    else atomicAdd((unsigned long long*)&A.global_sums[key], (unsigned long long)v);
+  };
+  auto Tn = [&](int x) -> int64_t { return (int64_t)tau_e[x]; };
+  auto Si = [&](int x) -> int64_t { return (int64_t)Di[x] - tau_e[x] - (pj == x ? 1 : 0); };
+  auto Sj = [&](int x) -> int64_t { return (int64_t)Dj[x] - tau_e[x] - (pi == x ? 1 : 0); };
+  for (int c = tid; c < L; c += TSIZE) {
+    const int64_t wedge = Si(c) + Sj(c), tri = Tn(c);
+    if (row) { row[c] = (uint64_t)wedge; row[L + c] = (uint64_t)tri; }
+    gadd(key_of(L, 0, pi, pj, c, 0), wedge);
+    gadd(key_of(L, 1, pi, pj, c, 0), tri);
+  }
+  for (int p = tid; p < P; p += TSIZE) {
+    int u = 0;
+    while ((u + 1) * (u + 2) / 2 <= p) ++u;
+    const int t = p - u * (u + 1) / 2;
+    auto sym = [&](auto f) -> int64_t { return t == u ? f(t, t) : f(t, u) + f(u, t); };
+    auto M = [&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y] + (int64_t)Mu[y * L + x]; };
+    auto ETSi = [&](int x, int y) -> int64_t { return (int64_t)Ai[x * L + y] - Tn(x) * (pj == y) - M(x, y); };
+    auto ETSj = [&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y] - Tn(x) * (pi == y) - M(x, y); };
+    auto ETI = [&](int x, int y) -> int64_t {
+      return (int64_t)Q[x * L + y] - Tn(x) * ((pi == y) + (pj == y)) - M(x, y) - ETSi(x, y) - ETSj(x, y);
+    };
+    const int64_t g12 = sym([&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y]; });
+    const int64_t g10 = sym(ETSi) + sym(ETSj);
+    const int64_t g8 = sym(ETI);
+    const int64_t sSiSi = sym([&](int x, int y) -> int64_t { return (int64_t)Ui[x * L + y]; })
+                        - sym([&](int x, int y) -> int64_t { return (pj == x) ? Tn(y) : 0; })
+                        - sym([&](int x, int y) -> int64_t { return (int64_t)Ai[x * L + y]; }) - sym(ETSi);
+    const int64_t sSjSj = sym([&](int x, int y) -> int64_t { return (int64_t)Uj[x * L + y]; })
+                        - sym([&](int x, int y) -> int64_t { return (pi == x) ? Tn(y) : 0; })
+                        - sym([&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y]; }) - sym(ETSj);
+    const int64_t g7 = (sSiSi + sSjSj) / 2;
+    const int64_t g6 = (int64_t)A.C4[(int64_t)e * P + p] - g10 - 2 * g12;
+    const int64_t g3 = sym([&](int x, int y) -> int64_t { return (int64_t)Pi[x * L + y]; })
+                     + sym([&](int x, int y) -> int64_t { return (int64_t)Pj[x * L + y]; })
+                     - sym([&](int x, int y) -> int64_t { return (pj == x) ? (int64_t)Dj[y] : 0; })
+                     - sym([&](int x, int y) -> int64_t { return (pi == x) ? (int64_t)Di[y] : 0; })
+                     - 2 * sym([&](int x, int y) -> int64_t { return (int64_t)Q[x * L + y]; })
+                     - sym([&](int x, int y) -> int64_t { return (pi == y) ? Si(x) : 0; })
+                     - sym([&](int x, int y) -> int64_t { return (pj == y) ? Sj(x) : 0; })
+                     - g10 - sSiSi - sSjSj - 2 * g6;
+    int64_t g4, g5, g9, g11;
+    if (t == u) {
+      g4 = Si(t) * Sj(t) - g6;                         // Eq. 7
+      g5 = c2(Si(t)) + c2(Sj(t)) - g7;                 // Eq. 8
+      g9 = Tn(t) * (Si(t) + Sj(t)) - g10;              // Eq. 9
+      g11 = c2(Tn(t)) - g12;                           // Eq. 10
+    } else {
+      g4 = Si(t) * Sj(u) + Si(u) * Sj(t) - g6;
+      g5 = Si(t) * Si(u) + Sj(t) * Sj(u) - g7;
+      g9 = Tn(t) * (Si(u) + Sj(u)) + Tn(u) * (Si(t) + Sj(t)) - g10;
+      g11 = Tn(t) * Tn(u) - g12;
+    }
+    const int64_t h[6] = {g3 + g4, g5, g6, g7 + g8 + g9, g10 + g11, g12};  // Eqs. 11-16
+    for (int s = 0; s < 6; ++s) {
+      if (row) row[2 * L + s * P + p] = (uint64_t)h[s];
+      gadd(key_of(L, 2 + s, pi, pj, t, u), h[s]);
+    }
+  }
+  tsync<TSIZE>();
+}
+
+// Capacity of T_ij kept in LDS per team.
+template <int TSIZE>
+struct TeamCap {
+  static constexpr int value = TSIZE == 16 ? 64 : (TSIZE == 64 ? 256 : TG_T_WG_CAP);
+};
+
+// One team per edge, grid-stride over a list.  LDS: [global key
+// accumulators] then per team [acc 4L^2 AccT][scan scratch][T ids][T types].
+// A T_ij larger than the team's capacity (workgroup teams only) is kept in
+// this workgroup's slice of a global scratch.
+template <int TSIZE, class AccT>
+__global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
+                                                 int nkeys, int32_t* __restrict__ t_over, int64_t t_over_cap) {
+  extern __shared__ uint64_t smem_comb[];
+  constexpr int TEAMS = 256 / TSIZE;
+  constexpr int TCAP = TeamCap<TSIZE>::value;
+  constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
+  const int LL = A.L * A.L;
+  uint64_t* gacc = A.gacc_in_lds ? smem_comb : nullptr;
+  const int koff = A.gacc_in_lds ? nkeys : 0;
+  const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
+  // per-team region, in bytes, rounded to 8
+  const int acc_bytes = 4 * LL * (int)sizeof(AccT);
+  const int region = ((acc_bytes + SCR * 4 + TCAP * 5) + 7) & ~7;
+  char* base = (char*)(smem_comb + koff) + (int64_t)team * region;
+  AccT* acc = (AccT*)base;
+  int32_t* scratch = (int32_t*)(base + acc_bytes);
+  int32_t* Tid_l = scratch + SCR;
+  uint8_t* Tty_l = (uint8_t*)(Tid_l + TCAP);
+  int32_t* Tid_g = t_over ? t_over + (int64_t)blockIdx.x * t_over_cap : nullptr;
+  uint8_t* Tty_g = t_over ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
+                          : nullptr;
+  if (gacc) {
+    for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
+  }
+  __syncthreads();
+  for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
+    const int32_t e = list[w];
+    bool big = false;
+    if (TSIZE > TG_WAVE) {
+      uint32_t tsum = 0;
+      for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
+      big = tsum > (uint32_t)TCAP;
+    }
+    combine_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc, gacc, scratch, tid);
+  }
+  __syncthreads();
+  if (gacc) {
+    for (int x = threadIdx.x; x < nkeys; x += blockDim.x)
+      if (gacc[x]) atomicAdd((unsigned long long*)&A.global_sums[x], (unsigned long long)gacc[x]);
+  }
+}
+
+// LDS bytes of k_combine<TSIZE, AccT>
+template <int TSIZE, class AccT>
+inline size_t combine_lds_bytes(int L, int nkeys_in_lds) {
+  constexpr int TCAP = TeamCap<TSIZE>::value;
+  constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
+  const int acc_bytes = 4 * L * L * (int)sizeof(AccT);
+  const int region = ((acc_bytes + SCR * 4 + TCAP * 5) + 7) & ~7;
+  return (size_t)nkeys_in_lds * 8 + (size_t)(256 / TSIZE) * region;
+}
+

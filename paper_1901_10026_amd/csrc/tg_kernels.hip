@@ -205,37 +205,45 @@ __global__ void k_fill_edges(int64_t n, const int32_t* __restrict__ rp, const in
 
 // -------------------------------------------------------------------- tau --
 
-// One wavefront per edge: tau_e[t] = |Gamma_i^t intersect Gamma_j^t| by
-// binary search of the shorter row's ids in the longer row.
-__global__ void k_tau(int64_t count, const int32_t* __restrict__ list, const int32_t* __restrict__ ei,
-                      const int32_t* __restrict__ ej, const int32_t* __restrict__ rp,
-                      const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
-                      const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau) {
-  const int64_t w = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
-  if (w >= count) return;
-  const int ln = lane();
-  const int32_t e = list ? list[w] : (int32_t)w;
-  const int32_t i = ei[e], j = ej[e];
-  const bool ia = deg[i] <= deg[j];
-  const int32_t a = ia ? i : j, b = ia ? j : i;
-  const int32_t la = deg[a], lb = deg[b];
-  const int32_t* pa = ci + rp[a];
-  const int32_t* pb = ci + rp[b];
-  uint32_t my_t = 0;
-  for (int32_t b0 = 0; b0 < la; b0 += TG_WAVE) {
-    const bool valid = b0 + ln < la;
-    int t = -1;
-    if (valid) {
-      const int32_t k = pa[b0 + ln];
-      const int32_t p = lower_bound(pb, lb, k);
-      if (p < lb && pb[p] == k) t = ty[k];
+// tau_e[t] = |Gamma_i^t intersect Gamma_j^t| by binary search of the shorter
+// row's ids in the longer row.  One team of TSIZE lanes (16 or 64) per edge;
+// a launch takes the edges whose shorter row length lies in (dlo, dhi], so
+// short rows do not leave most of a wavefront idle.
+template <int TSIZE>
+__global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi, const int32_t* __restrict__ ei,
+                                             const int32_t* __restrict__ ej, const int32_t* __restrict__ rp,
+                                             const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
+                                             const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau) {
+  constexpr int TEAMS = 256 / TSIZE;
+  const int team = threadIdx.x / TSIZE, tl = threadIdx.x % TSIZE;
+  for (int64_t e = (int64_t)blockIdx.x * TEAMS + team; e < m; e += (int64_t)gridDim.x * TEAMS) {
+    const int32_t i = ei[e], j = ej[e];
+    const int32_t di = deg[i], dj = deg[j];
+    const bool ia = di <= dj;
+    const int32_t la = ia ? di : dj, lb = ia ? dj : di;
+    if (la <= dlo || la > dhi) continue;
+    const int32_t* pa = ci + rp[ia ? i : j];
+    const int32_t* pb = ci + rp[ia ? j : i];
+    uint32_t my_t = 0;
+    for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
+      int t = -1;
+      if (b0 + tl < la) {
+        const int32_t k = pa[b0 + tl];
+        const int32_t p = lower_bound(pb, lb, k);
+        if (p < lb && pb[p] == k) t = ty[k];
+      }
+      const uint64_t wm = ballot(t >= 0);
+      const uint64_t tm = (TSIZE >= TG_WAVE) ? wm : ((wm >> ((lane() / TSIZE) * TSIZE)) & ((1ull << TSIZE) - 1ull));
+      if (tm) {
+        for (int tt = 0; tt < L; ++tt) {
+          const uint64_t b = ballot(t == tt);
+          const uint64_t bt = (TSIZE >= TG_WAVE) ? b : ((b >> ((lane() / TSIZE) * TSIZE)) & ((1ull << TSIZE) - 1ull));
+          if (tl == tt) my_t += (uint32_t)__popcll(bt);
+        }
+      }
     }
-    for (int tt = 0; tt < L; ++tt) {
-      uint32_t c = (uint32_t)__popcll(ballot(t == tt));
-      if (ln == tt) my_t += c;
-    }
+    if (tl < L) tau[e * L + tl] = my_t;   // TSIZE >= 16 >= L
   }
-  if (ln < L) tau[(int64_t)e * L + ln] = my_t;
 }
 
 // ----------------------------------------------------------------- tables --
@@ -487,282 +495,47 @@ __global__ void __launch_bounds__(256) k_c4_group(int phase, int G, const int32_
   }
 }
 
-// ------------------------------------------------------------- combine --
-//
-// Per edge (i, j), with T = T_ij, S_i, S_j, I as in Section 4 and ordered
-// typed pair counts E(X^t, Y^u) = #{(k, r): k in X of type t, r in Y of type
-// u, k ~ r}:
-//   A_i[t][u] = sum_{k in T^t} tau_(i,k)[u],  A_j likewise,
-//   Q[t][u]   = sum_{k in T^t} D[k][u],
-//   Mu[t][u]  = edges {k, r} inside T with k preceding r, typed (phi_k, phi_r),
-//   M(t,u)    = Mu[t][u] + Mu[u][t] = E(T^t, T^u).
-// Every neighbour of k in T is i, j, or in T, S_i, S_j or I, and every
-// neighbour of k in S_i is i or in T, S_i, S_j or I.  Hence
-//   E(T^t, S_i^u) = A_i[t][u] - |T^t| [phi_j = u] - M(t,u)
-//   E(T^t, I^u)   = Q[t][u] - |T^t| ([phi_i=u] + [phi_j=u]) - M - E(T,S_i) - E(T,S_j)
-//   E(S_i^t, S_i^u) = U[i][t][u] - [phi_j=t] |T^u| - A_i[t][u] - E(T^u, S_i^t)
-//   E(S_i^t, I^u) = P[i][t][u] - [phi_j=t] D[j][u] - Q[t][u] - |S_i^t| [phi_i=u]
-//                   - E(T^u, S_i^t) - E(S_i^t, S_i^u) - E(S_i^t, S_j^u)
-// and the non-induced 4-cycle count through (i, j) is g6 + g10 + 2 g12.  With
-// sym(X){t,u} = X[t][u] + X[u][t] (t != u) or X[t][t], the explicit orbits of
-// Algorithms 2-3 are
-//   g12 = sym(Mu), g10 = sym(E(T,S_i) + E(T,S_j)), g8 = sym(E(T,I)),
-//   g7 = (sym(E(S_i,S_i)) + sym(E(S_j,S_j))) / 2, g6 = C4 - g10 - 2 g12,
-//   g3 = sym(E(S_i,I) + E(S_j,I)),
-// then g4, g5, g9, g11 follow from Eqs. 7-10 and the graphlets from Eqs. 11-16.
-
-template <int NWAVES>
-__device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
-                                             uint64_t* __restrict__ acc, uint64_t* gacc, int32_t* s_cnt, int tid) {
-  const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
-  const int R = 2 * L + 6 * P;
-  uint64_t* Aa = acc;
-  uint64_t* Ab = acc + LL;
-  uint64_t* Q = acc + 2 * LL;
-  uint64_t* Mu = acc + 3 * LL;
-  for (int x = tid; x < 4 * LL; x += NWAVES * TG_WAVE) acc[x] = 0;
-  team_sync<NWAVES>();
-  const int32_t i = A.ei[e], j = A.ej[e];
-  const int32_t di = A.deg[i], dj = A.deg[j];
-  const bool a_is_i = di <= dj;
-  const int32_t a = a_is_i ? i : j, b = a_is_i ? j : i;
-  const int32_t la = a_is_i ? di : dj, lb = a_is_i ? dj : di;
-  const int32_t ra = A.rp[a], rb = A.rp[b];
-  const int wv = tid / TG_WAVE, ln = lane();
-
-  // T_ij with the sums of tau and D over its members
-  int32_t nT = 0;
-  for (int32_t b0 = 0; b0 < la; b0 += NWAVES * TG_WAVE) {
-    const int32_t idx = b0 + tid;
-    bool found = false;
-    int32_t k = 0, p = 0;
-    if (idx < la) {
-      k = A.ci[ra + idx];
-      p = lower_bound(A.ci + rb, lb, k);
-      found = p < lb && A.ci[rb + p] == k;
-    }
-    int t = 0;
-    if (found) {
-      t = A.ty[k];
-      const int64_t ea = A.s2e[ra + idx], eb = A.s2e[rb + p];
-      for (int u = 0; u < L; ++u) {
-        const uint32_t va = A.tau[ea * L + u];
-        if (va) atomicAdd((unsigned long long*)&Aa[t * L + u], (unsigned long long)va);
-        const uint32_t vb = A.tau[eb * L + u];
-        if (vb) atomicAdd((unsigned long long*)&Ab[t * L + u], (unsigned long long)vb);
-        const uint32_t vd = A.D[(int64_t)k * L + u];
-        if (vd) atomicAdd((unsigned long long*)&Q[t * L + u], (unsigned long long)vd);
-      }
-    }
-    const uint64_t mask = ballot(found);
-    int32_t before = 0, total = __popcll(mask);
-    if (NWAVES > 1) {
-      if (ln == 0) s_cnt[wv] = total;
-      __syncthreads();
-      total = 0;
-      for (int q = 0; q < NWAVES; ++q) {
-        const int32_t c = s_cnt[q];
-        if (q < wv) before += c;
-        total += c;
-      }
-      __syncthreads();
-    }
-    if (found) {
-      const int32_t pos = nT + before + lanes_below(mask);
-      Tid[pos] = k;
-      Tty[pos] = (uint8_t)t;
-    }
-    nT += total;
-  }
-  team_sync<NWAVES>();
-
-  // instrumented work: probes of the intersection, gathers per member of T,
-  // out-list elements scanned, epilogue entries
-  uint64_t my_work = 0;
-  if (A.work && wv == 0)
-    my_work = (uint64_t)la * (uint64_t)(1 + (lb > 0 ? 32 - __clz(lb) : 0)) + (uint64_t)nT * 3u * (uint64_t)L +
-              (uint64_t)(P + L);
-
-  // typed edges inside T (4-cliques through (i, j)), each from its lower end
-  for (int32_t q = wv; q < nT; q += NWAVES) {
-    const int32_t k = Tid[q];
-    const int tk = Tty[q];
-    const int32_t o0 = A.out_off[k], o1 = A.out_off[k + 1];
-    my_work += (uint64_t)(1 + o1 - o0);
-    for (int32_t c0 = o0; c0 < o1; c0 += TG_WAVE) {
-      if (c0 + ln < o1) {
-        const int32_t r = A.out_col[c0 + ln];
-        const int32_t pp = lower_bound(Tid, nT, r);
-        if (pp < nT && Tid[pp] == r) atomicAdd((unsigned long long*)&Mu[tk * L + Tty[pp]], 1ull);
-      }
-    }
-  }
-  if (A.work && ln == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
-  team_sync<NWAVES>();
-
-  // per type pair: every orbit, then every graphlet
-  const int pi = A.ty[i], pj = A.ty[j];
-  const uint64_t* Ai = a_is_i ? Aa : Ab;
-  const uint64_t* Aj = a_is_i ? Ab : Aa;
-  const uint32_t* tau_e = A.tau + (int64_t)e * L;
-  const uint32_t* Di = A.D + (int64_t)i * L;
-  const uint32_t* Dj = A.D + (int64_t)j * L;
-  const uint64_t* Ui = A.Un + (int64_t)i * LL;
-  const uint64_t* Uj = A.Un + (int64_t)j * LL;
-  const uint64_t* Pi = A.Pn + (int64_t)i * LL;
-  const uint64_t* Pj = A.Pn + (int64_t)j * LL;
-  uint64_t* row = (A.edge_counts && e >= A.edge_begin && e < A.edge_end)
-                      ? A.edge_counts + (int64_t)(e - A.edge_begin) * R : nullptr;
-  auto gadd = [&](int64_t key, int64_t v) {
-    if (v == 0) return;
-    if (gacc) atomicAdd((unsigned long long*)&gacc[key], (unsigned long long)v);
-    else atomicAdd((unsigned long long*)&A.global_sums[key], (unsigned long long)v);
-  };
-  auto Tn = [&](int x) -> int64_t { return (int64_t)tau_e[x]; };
-  auto Si = [&](int x) -> int64_t { return (int64_t)Di[x] - tau_e[x] - (pj == x ? 1 : 0); };
-  auto Sj = [&](int x) -> int64_t { return (int64_t)Dj[x] - tau_e[x] - (pi == x ? 1 : 0); };
-  for (int c = tid; c < L; c += NWAVES * TG_WAVE) {
-    const int64_t wedge = Si(c) + Sj(c), tri = Tn(c);
-    if (row) { row[c] = (uint64_t)wedge; row[L + c] = (uint64_t)tri; }
-    gadd(key_of(L, 0, pi, pj, c, 0), wedge);
-    gadd(key_of(L, 1, pi, pj, c, 0), tri);
-  }
-  for (int p = tid; p < P; p += NWAVES * TG_WAVE) {
-    int u = 0;
-    while ((u + 1) * (u + 2) / 2 <= p) ++u;
-    const int t = p - u * (u + 1) / 2;
-    auto sym = [&](auto f) -> int64_t { return t == u ? f(t, t) : f(t, u) + f(u, t); };
-    auto M = [&](int x, int y) -> int64_t { return (int64_t)(Mu[x * L + y] + Mu[y * L + x]); };
-    auto ETSi = [&](int x, int y) -> int64_t { return (int64_t)Ai[x * L + y] - Tn(x) * (pj == y) - M(x, y); };
-    auto ETSj = [&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y] - Tn(x) * (pi == y) - M(x, y); };
-    auto ETI = [&](int x, int y) -> int64_t {
-      return (int64_t)Q[x * L + y] - Tn(x) * ((pi == y) + (pj == y)) - M(x, y) - ETSi(x, y) - ETSj(x, y);
-    };
-    const int64_t g12 = sym([&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y]; });
-    const int64_t g10 = sym(ETSi) + sym(ETSj);
-    const int64_t g8 = sym(ETI);
-    const int64_t sSiSi = sym([&](int x, int y) -> int64_t { return (int64_t)Ui[x * L + y]; })
-                        - sym([&](int x, int y) -> int64_t { return (pj == x) ? Tn(y) : 0; })
-                        - sym([&](int x, int y) -> int64_t { return (int64_t)Ai[x * L + y]; }) - sym(ETSi);
-    const int64_t sSjSj = sym([&](int x, int y) -> int64_t { return (int64_t)Uj[x * L + y]; })
-                        - sym([&](int x, int y) -> int64_t { return (pi == x) ? Tn(y) : 0; })
-                        - sym([&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y]; }) - sym(ETSj);
-    const int64_t g7 = (sSiSi + sSjSj) / 2;
-    const int64_t g6 = (int64_t)A.C4[(int64_t)e * P + p] - g10 - 2 * g12;
-    const int64_t g3 = sym([&](int x, int y) -> int64_t { return (int64_t)Pi[x * L + y]; })
-                     + sym([&](int x, int y) -> int64_t { return (int64_t)Pj[x * L + y]; })
-                     - sym([&](int x, int y) -> int64_t { return (pj == x) ? (int64_t)Dj[y] : 0; })
-                     - sym([&](int x, int y) -> int64_t { return (pi == x) ? (int64_t)Di[y] : 0; })
-                     - 2 * sym([&](int x, int y) -> int64_t { return (int64_t)Q[x * L + y]; })
-                     - sym([&](int x, int y) -> int64_t { return (pi == y) ? Si(x) : 0; })
-                     - sym([&](int x, int y) -> int64_t { return (pj == y) ? Sj(x) : 0; })
-                     - g10 - sSiSi - sSjSj - 2 * g6;
-    int64_t g4, g5, g9, g11;
-    if (t == u) {
-      g4 = Si(t) * Sj(t) - g6;                         // Eq. 7
-      g5 = c2(Si(t)) + c2(Sj(t)) - g7;                 // Eq. 8
-      g9 = Tn(t) * (Si(t) + Sj(t)) - g10;              // Eq. 9
-      g11 = c2(Tn(t)) - g12;                           // Eq. 10
-    } else {
-      g4 = Si(t) * Sj(u) + Si(u) * Sj(t) - g6;
-      g5 = Si(t) * Si(u) + Sj(t) * Sj(u) - g7;
-      g9 = Tn(t) * (Si(u) + Sj(u)) + Tn(u) * (Si(t) + Sj(t)) - g10;
-      g11 = Tn(t) * Tn(u) - g12;
-    }
-    const int64_t h[6] = {g3 + g4, g5, g6, g7 + g8 + g9, g10 + g11, g12};  // Eqs. 11-16
-    for (int s = 0; s < 6; ++s) {
-      if (row) row[2 * L + s * P + p] = (uint64_t)h[s];
-      gadd(key_of(L, 2 + s, pi, pj, t, u), h[s]);
-    }
-  }
-  team_sync<NWAVES>();
-}
-
-// One wavefront per edge (|T_ij| <= TG_T_WAVE_CAP), grid-stride over a list.
-__global__ void __launch_bounds__(256) k_combine_wave(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
-                                                      int nkeys) {
-  extern __shared__ uint64_t smem_cw[];
-  const int LL = A.L * A.L;
-  uint64_t* gacc = A.gacc_in_lds ? smem_cw : nullptr;
-  const int koff = A.gacc_in_lds ? nkeys : 0;
-  const int wv = threadIdx.x / TG_WAVE;
-  uint64_t* acc = smem_cw + koff + (int64_t)wv * 4 * LL;
-  int32_t* Tid = (int32_t*)(smem_cw + koff + 4 * 4 * LL) + wv * TG_T_WAVE_CAP;
-  uint8_t* Tty = (uint8_t*)((int32_t*)(smem_cw + koff + 4 * 4 * LL) + 4 * TG_T_WAVE_CAP) + wv * TG_T_WAVE_CAP;
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
-  }
-  __syncthreads();
-  for (int64_t w = (int64_t)blockIdx.x * 4 + wv; w < count; w += (int64_t)gridDim.x * 4)
-    combine_edge<1>(A, list[w], Tid, Tty, acc, gacc, nullptr, threadIdx.x % TG_WAVE);
-  __syncthreads();
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x)
-      if (gacc[x]) atomicAdd((unsigned long long*)&A.global_sums[x], (unsigned long long)gacc[x]);
-  }
-}
-
-// One workgroup per edge, grid-stride over a list; T_ij in LDS when it fits,
-// else in this workgroup's slice of a global scratch.
-__global__ void __launch_bounds__(256) k_combine_wg(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
-                                                    int nkeys, int32_t* __restrict__ t_over, int64_t t_over_cap) {
-  extern __shared__ uint64_t smem_cg[];
-  const int LL = A.L * A.L;
-  uint64_t* gacc = A.gacc_in_lds ? smem_cg : nullptr;
-  const int koff = A.gacc_in_lds ? nkeys : 0;
-  uint64_t* acc = smem_cg + koff;
-  int32_t* s_cnt = (int32_t*)(smem_cg + koff + 4 * LL);
-  int32_t* Tid_l = s_cnt + 4;
-  uint8_t* Tty_l = (uint8_t*)(Tid_l + TG_T_WG_CAP);
-  int32_t* Tid_g = t_over ? t_over + (int64_t)blockIdx.x * t_over_cap : nullptr;
-  uint8_t* Tty_g = t_over ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
-                          : nullptr;
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
-  }
-  __syncthreads();
-  for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
-    const int32_t e = list[w];
-    uint32_t tsum = 0;
-    for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
-    const bool big = tsum > TG_T_WG_CAP;
-    combine_edge<4>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc, gacc, s_cnt, threadIdx.x);
-  }
-  __syncthreads();
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x)
-      if (gacc[x]) atomicAdd((unsigned long long*)&A.global_sums[x], (unsigned long long)gacc[x]);
-  }
-}
+#include "tg_combine.hip"
 
 // ------------------------------------------------------------- schedule --
 
 // Edge class (0: one wavefront, 1: one workgroup) and cost bucket (0 = most
 // expensive).  cost: 0 none, 1 degree product, 2 given per-edge cost.
 struct BinParams {
-  int mode;              // 0 none, 1 degree product, 2 predicted log2 cost
-  int heavy_min_degree;  // min(d_i, d_j) above this: workgroup
-  int heavy_log2_cost;   // floor(log2 cost) above this: workgroup
+  int mode;               // 0 none, 1 degree product, 2 predicted log2 cost
+  int light_max_degree;   // class 0 (16-lane team) needs min(d_i, d_j) <= this and |T| <= 64
+  int heavy_min_degree;   // min(d_i, d_j) above this: class 2 (workgroup)
+  int mid_log2_cost;      // floor(log2 cost) above this: at least class 1 (wavefront)
+  int heavy_log2_cost;    // floor(log2 cost) above this: class 2
+  int teams16;            // 0: class 0 is folded into class 1 (large L)
 };
 
+// Edge class (0: 16-lane team, 1: wavefront, 2: workgroup) and cost bucket
+// (0 = most expensive).
 __device__ __forceinline__ void edge_bin(int32_t e, const int32_t* ei, const int32_t* ej, const int32_t* deg,
                                          const uint32_t* tau, int L, BinParams bp, const float* pred, int* cls,
                                          int* bucket, uint32_t* tsum_out) {
   const int32_t i = ei[e], j = ej[e];
   const int32_t di = deg[i], dj = deg[j];
+  const int32_t dmin = min(di, dj);
   uint32_t tsum = 0;
   for (int t = 0; t < L; ++t) tsum += tau[(int64_t)e * L + t];
   *tsum_out = tsum;
-  int heavy = (tsum > TG_T_WAVE_CAP || min(di, dj) > bp.heavy_min_degree) ? 1 : 0;
-  if (bp.mode == 0) { *cls = heavy; *bucket = 0; return; }
-  double c;
-  if (bp.mode == 1) c = (double)di * (double)dj;
-  else c = exp2((double)pred[e]);
-  int lg = (int)floor(log2(c + 1.0));
-  lg = lg < 0 ? 0 : (lg > 63 ? 63 : lg);
-  if (lg > bp.heavy_log2_cost) heavy = 1;
-  *cls = heavy;
-  *bucket = 63 - lg;
+  int c = 0;
+  if (tsum > 256 || dmin > bp.heavy_min_degree) c = 2;
+  else if (tsum > 64 || dmin > bp.light_max_degree || !bp.teams16) c = 1;
+  int lg = 0;
+  if (bp.mode != 0) {
+    double cst;
+    if (bp.mode == 1) cst = (double)di * (double)dj;
+    else cst = exp2((double)pred[e]);
+    lg = (int)floor(log2(cst + 1.0));
+    lg = lg < 0 ? 0 : (lg > 63 ? 63 : lg);
+    if (lg > bp.heavy_log2_cost) c = 2;
+    else if (lg > bp.mid_log2_cost && c == 0) c = 1;
+  }
+  *cls = c;
+  *bucket = bp.mode == 0 ? 0 : 63 - lg;
 }
 
 // Bin counts and scatter use a per-workgroup LDS histogram so that global
@@ -773,9 +546,9 @@ __global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t
                                                         const uint32_t* __restrict__ tau, int L, BinParams bp,
                                                         const float* __restrict__ pred, int32_t* __restrict__ counts,
                                                         uint32_t* __restrict__ max_t_heavy) {
-  __shared__ int32_t h[128];
+  __shared__ int32_t h[192];
   __shared__ uint32_t tmax;
-  for (int q = threadIdx.x; q < 128; q += blockDim.x) h[q] = 0;
+  for (int q = threadIdx.x; q < 192; q += blockDim.x) h[q] = 0;
   if (threadIdx.x == 0) tmax = 0;
   __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
@@ -783,10 +556,10 @@ __global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t
     uint32_t tsum;
     edge_bin((int32_t)e, ei, ej, deg, tau, L, bp, pred, &cls, &bucket, &tsum);
     atomicAdd(&h[cls * 64 + bucket], 1);
-    if (cls == 1) atomicMax(&tmax, tsum);
+    if (cls == 2) atomicMax(&tmax, tsum);
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < 128; q += blockDim.x)
+  for (int q = threadIdx.x; q < 192; q += blockDim.x)
     if (h[q]) atomicAdd(&counts[q], h[q]);
   if (threadIdx.x == 0 && tmax) atomicMax(max_t_heavy, tmax);
 }
@@ -797,10 +570,10 @@ __global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32
                                                           const uint32_t* __restrict__ tau, int L, BinParams bp,
                                                           const float* __restrict__ pred,
                                                           int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
-  __shared__ int32_t h[128];
-  __shared__ int32_t base[128];
+  __shared__ int32_t h[192];
+  __shared__ int32_t base[192];
   for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < m; t0 += (int64_t)gridDim.x * blockDim.x) {
-    for (int q = threadIdx.x; q < 128; q += blockDim.x) h[q] = 0;
+    for (int q = threadIdx.x; q < 192; q += blockDim.x) h[q] = 0;
     __syncthreads();
     const int64_t e = t0 + threadIdx.x;
     int bin = -1, local = 0;
@@ -812,7 +585,7 @@ __global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32
       local = atomicAdd(&h[bin], 1);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < 128; q += blockDim.x)
+    for (int q = threadIdx.x; q < 192; q += blockDim.x)
       base[q] = h[q] ? atomicAdd(&cursor[q], h[q]) : 0;
     __syncthreads();
     if (bin >= 0) list[base[bin] + local] = (int32_t)e;

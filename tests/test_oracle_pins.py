@@ -350,3 +350,25 @@ def test_bf16_rounding_reference():
     assert r[4] == np.float32(-3.140625)
     assert r[6] == np.inf
     assert (r.view(np.uint32) & 0xFFFF == 0).all()
+
+
+def test_part_structure_forces_zero_keys():
+    # On k-partite graphs typed by part, a (shape, multiset) key that no
+    # placement can properly colour never occurs (brute force).
+    from test_gpu_partite import colourable
+    for sizes, seed in (([7, 6], 3), ([5, 4, 4], 4)):
+        k = len(sizes)
+        rp, ci, parts = graphgen.kpartite_cl(sizes, [2.5] * k, [6.0] * k, [4.0] * k, 3 * sum(sizes), seed)
+        rows, _, glob = oracle.brute(rp, ci, parts, k)
+        seen = 0
+        for key in range(oracle.num_keys(k)):
+            shape = next(h for h in range(8) if key < (oracle.shape_offset(k, h + 1) if h < 7
+                                                        else oracle.num_keys(k)))
+            types = None
+            for ms in itertools.combinations_with_replacement(range(k), 3 if shape < 2 else 4):
+                if oracle.key(k, shape, ms) == key:
+                    types = ms
+            if not colourable(shape, types):
+                assert glob[key] == 0
+            seen += int(glob[key] > 0)
+        assert seen > 0
