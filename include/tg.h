@@ -90,7 +90,9 @@ typedef struct {
                                  a full wavefront (64 = never) */
   int32_t heavy_log2_cost;    /* tg_count: edges whose log2 schedule cost exceeds this use one
                                  workgroup (64 = never) */
-  int32_t combine_grid;       /* tg_count: workgroups of the one-wavefront-per-edge launch */
+  int32_t combine_grid;       /* tg_count: workgroup count cap of the small-team combine launches */
+  int32_t c4_footprint_mb;    /* tg_count: heavy nodes of the 4-cycle pass are processed in groups
+                                 whose count arrays touch about this many MiB */
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */
@@ -243,8 +245,8 @@ tg_status tg_cost_model_load(tg_cost_model* model, const char* path);
  * (counts are rewritten with identical values) and only change launch
  * shapes. */
 
-/* Coordinate descent over tg_tuning's tg_count fields, timing the per-edge
- * combine phase with HIP events; base supplies the schedule and model (NULL:
+/* Coordinate descent over tg_tuning's tg_count fields, timing the 4-cycle
+ * and per-edge combine phases with HIP events; base supplies the schedule and model (NULL:
  * defaults).  Outputs as in tg_count (edge_counts may be NULL). */
 tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                       const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,

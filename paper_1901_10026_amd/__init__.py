@@ -58,8 +58,10 @@ class Tuning(ctypes.Structure):
     """Launch-shape choices (tg_tuning); counts never depend on them."""
     _fields_ = [("light_max_degree", ctypes.c_int32), ("heavy_min_degree", ctypes.c_int32),
                 ("mid_log2_cost", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
-                ("combine_grid", ctypes.c_int32), ("batch_variant", ctypes.c_int32 * 9)]
-    SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid")
+                ("combine_grid", ctypes.c_int32), ("c4_footprint_mb", ctypes.c_int32),
+                ("batch_variant", ctypes.c_int32 * 9)]
+    SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
+               "c4_footprint_mb")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

@@ -298,6 +298,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   TG_LAUNCHED("k_edge_bin_count");
   k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256);
   TG_LAUNCHED("k_node_tier_count");
+  k_max_degree<<<grid_for(n, 256, 1024), 256, 0, st>>>(n, W.deg, cnt + 268);
+  TG_LAUNCHED("k_max_degree");
   int32_t h_cnt[512];
   TG_HIP(hipMemcpyAsync(h_cnt, cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st));
   TG_HIP(hipStreamSynchronize(st));
@@ -312,6 +314,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   int64_t nacc = 0;
   for (int t = 0; t < 4; ++t) { cur[256 + t] = (int32_t)nacc; nacc += h_cnt[256 + t]; }
   const int64_t max_t_heavy = (uint32_t)h_cnt[264];
+  const int64_t max_deg = h_cnt[268];
+  // 32-bit 4-cycle counters when (d_i - 1)(d_j - 1) < 2^32 on every edge
+  const bool c4_wide = (max_deg - 1) * (max_deg - 1) >= (1ll << 32);
+  const int stage_xu = (!c4_wide && L <= 8) ? 1 : 0;
   TG_HIP(hipMemcpyAsync(cnt, cur, 264 * sizeof(int32_t), hipMemcpyHostToDevice, st));
   k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
                                                              W.elist);
@@ -324,14 +330,23 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
   TG_LAUNCHED("k_fill_u64");
   const int64_t n_t1 = h_cnt[257], n_t2 = h_cnt[258], n_t3 = h_cnt[259];
+  uint32_t* C4n = reinterpret_cast<uint32_t*>(W.C4);
   if (n_t1 > 0) {
-    k_c4_hash<1, 8><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty, L, W.s2e,
-                                                             W.C4);
+    if (c4_wide)
+      k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
+                                                                         L, W.s2e, W.C4);
+    else
+      k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
+                                                                         L, W.s2e, C4n);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (n_t2 > 0) {
-    k_c4_hash<4, 12><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg, ty, L, W.s2e,
-                                                              W.C4);
+    if (c4_wide)
+      k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
+                                                                          ty, L, W.s2e, W.C4);
+    else
+      k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
+                                                                          ty, L, W.s2e, C4n);
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -363,41 +378,74 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     });
     const int CS = L <= 8 ? 8 : 16;
     const int64_t stride = n * CS;
-    int64_t G = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
-    G = std::max<int64_t>(1, std::min<int64_t>(G, std::min<int64_t>(256, n_t3)));
-    const int64_t ngroups = (n_t3 + G - 1) / G;
+    int64_t Gmax = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
+    Gmax = std::max<int64_t>(1, std::min<int64_t>(Gmax, std::min<int64_t>(256, n_t3)));
+    // groups of consecutive nodes (heaviest first) whose dense arrays together
+    // touch about c4_footprint_mb of rows, so that a group's working set can
+    // stay in the last-level cache; at most Gmax nodes per group
+    const int64_t foot = (int64_t)std::max(1, tune.c4_footprint_mb) << 20;
+    std::vector<int64_t> gstart, gcount;
+    {
+      int64_t q = 0;
+      while (q < n_t3) {
+        int64_t c = 0, bytes = 0;
+        while (q + c < n_t3 && c < Gmax) {
+          const int64_t touched = std::min<int64_t>((int64_t)hw[order[q + c]], n) * CS * (int64_t)sizeof(uint32_t);
+          if (c > 0 && bytes + touched > foot) break;
+          bytes += touched;
+          ++c;
+        }
+        gstart.push_back(q);
+        gcount.push_back(c);
+        q += c;
+      }
+    }
+    const int64_t ngroups = (int64_t)gstart.size();
+    const int64_t G = Gmax;
     std::vector<int32_t> gx(n_t3);
-    std::vector<int64_t> gp(ngroups * (G + 1), 0);
+    std::vector<int64_t> gp(n_t3 + ngroups, 0);
     for (int64_t g = 0; g < ngroups; ++g) {
       int64_t acc2 = 0;
-      for (int64_t q = 0; q < G; ++q) {
-        int64_t idx = g * G + q;
-        gp[g * (G + 1) + q] = acc2;
-        if (idx < n_t3) {
-          gx[idx] = hx[order[idx]];
-          acc2 += hd[order[idx]];
-        }
+      for (int64_t q = 0; q < gcount[g]; ++q) {
+        const int64_t idx = gstart[g] + q;
+        gp[gstart[g] + g + q] = acc2;
+        gx[idx] = hx[order[idx]];
+        acc2 += hd[order[idx]];
       }
-      gp[g * (G + 1) + G] = acc2;
+      gp[gstart[g] + g + gcount[g]] = acc2;
     }
     int32_t* d_gx;
     int64_t* d_gp;
     uint32_t* dense;
     TG_HIP(S.get(&d_gx, n_t3));
-    TG_HIP(S.get(&d_gp, ngroups * (G + 1)));
+    TG_HIP(S.get(&d_gp, n_t3 + ngroups));
     TG_HIP(S.get(&dense, G * stride));
     TG_HIP(hipMemcpyAsync(d_gx, gx.data(), n_t3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
     TG_HIP(hipMemcpyAsync(d_gp, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
     k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
     TG_LAUNCHED("k_fill_u32");
     for (int64_t g = 0; g < ngroups; ++g) {
-      const int Gg = (int)std::min<int64_t>(G, n_t3 - g * G);
-      const int64_t slots = gp[g * (G + 1) + Gg];
-      for (int phase = 0; phase < 3; ++phase) {
-        k_c4_group<<<grid_for(slots, 4 * TG_WAVE), 256, 0, st>>>(phase, Gg, d_gx + g * G, d_gp + g * (G + 1), dense,
-                                                                stride, CS, rp, ci, W.deg, ty, L, W.s2e, W.C4);
-        TG_LAUNCHED("k_c4_group");
+      const int Gg = (int)gcount[g];
+      const int64_t slots = gp[gstart[g] + g + Gg];
+      const unsigned grid = grid_for(slots, 4 * TG_WAVE);
+      const int32_t* gxg = d_gx + gstart[g];
+      const int64_t* gpg = d_gp + gstart[g] + g;
+      if (c4_wide) {
+        k_c4_group<0, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      W.C4, 0);
+        k_c4_group<1, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      W.C4, 0);
+        k_c4_group<2, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      W.C4, 0);
+      } else {
+        k_c4_group<0, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      C4n, stage_xu);
+        k_c4_group<1, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      C4n, stage_xu);
+        k_c4_group<2, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
+                                                      C4n, stage_xu);
       }
+      TG_LAUNCHED("k_c4_group");
     }
   }
 
@@ -406,9 +454,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.C4n = C4n;
+  A.c4_wide = c4_wide ? 1 : 0;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
   A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
   A.work = nullptr;
+  A.thash_ok = n < (1ll << 27) ? 1 : 0;
   const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
   const int kl = A.gacc_in_lds ? (int)K : 0;
   if (class_count[0] > 0) {
@@ -703,9 +754,12 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
+  A.c4_wide = 1;
   A.edge_counts = nullptr; A.edge_begin = 0; A.edge_end = 0; A.global_sums = gsink;
   A.gacc_in_lds = 0;
   A.work = work_by_edge;
+  A.thash_ok = n < (1ll << 27) ? 1 : 0;
   const unsigned grid = grid_for(count, 1, 1024);
   int32_t* t_over = nullptr;
   int64_t t_cap = 0;
@@ -864,6 +918,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->mid_log2_cost = 64;
   t->heavy_log2_cost = 64;
   t->combine_grid = 2048;
+  t->c4_footprint_mb = 4096;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }
@@ -1101,7 +1156,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
     opt.tuning = &t;
     tg_status s = tg_count(n, nnz, row_ptr, col_idx, node_types, L, global_counts, edge_counts, nullptr, &opt,
                            stream);
-    *ms = ph[TG_PHASE_COMBINE];
+    *ms = ph[TG_PHASE_CYCLES] + ph[TG_PHASE_COMBINE];
     return s;
   };
   float best = 0.0f;
@@ -1123,6 +1178,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
     }
   }
   axes.push_back({&t.combine_grid, {1024, 2048, 4096, 8192}});
+  axes.push_back({&t.c4_footprint_mb, {256, 1024, 4096}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

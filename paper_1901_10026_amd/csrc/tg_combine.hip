@@ -76,9 +76,16 @@ __device__ __forceinline__ int32_t team_excl_scan(int32_t v, int32_t* total, int
   }
 }
 
+// LDS hash of T_ij for workgroup teams: slot = (node id << 4) | type, -1 empty.
+#define TG_THASH_LOG2 12
+__device__ __forceinline__ uint32_t thash_home(int32_t k) {
+  return ((uint32_t)k * 2654435761u) >> (32 - TG_THASH_LOG2);
+}
+
 template <int TSIZE, class AccT>
 __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
-                                             AccT* __restrict__ acc, uint64_t* gacc, int32_t* scratch, int tid) {
+                                             AccT* __restrict__ acc, uint64_t* gacc, int32_t* scratch, int tid,
+                                             int32_t* Th) {
   const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
   const int R = 2 * L + 6 * P;
   AccT* Aa = acc;
@@ -86,6 +93,8 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
   AccT* Q = acc + 2 * LL;
   AccT* Mu = acc + 3 * LL;
   for (int x = tid; x < 4 * LL; x += TSIZE) acc[x] = 0;
+  if (Th)
+    for (int x = tid; x < (1 << TG_THASH_LOG2); x += TSIZE) Th[x] = -1;
   tsync<TSIZE>();
   const int32_t i = A.ei[e], j = A.ej[e];
   const int32_t di = A.deg[i], dj = A.deg[j];
@@ -140,6 +149,10 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
     if (found) {
       Tid[nT + before] = k;
       Tty[nT + before] = (uint8_t)t;
+      if (Th) {
+        uint32_t h = thash_home(k);
+        while (atomicCAS(&Th[h], -1, (k << 4) | t) != -1) h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+      }
     }
     nT += total;
   }
@@ -154,6 +167,7 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
   // lower end's degree-ordered out-list; (member, out-slot) pairs are dealt
   // to lanes through a team prefix sum
   int32_t* s_excl = scratch + 8;  // TSIZE == 256 only
+  const uint64_t tmask = TSIZE >= TG_WAVE ? ~0ull : (((1ull << TSIZE) - 1ull) << ((lane() / TSIZE) * TSIZE));
   for (int32_t q0 = 0; q0 < nT; q0 += TSIZE) {
     const int32_t q = q0 + tid;
     int32_t ostart = 0, ocnt = 0, tk = 0;
@@ -191,10 +205,30 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
         o_start = s_excl[TSIZE + o];
         o_tk = s_excl[2 * TSIZE + o];
       }
+      int cell = -1;
       if (v < tot) {
         const int32_t r = A.out_col[o_start + (v - o_excl)];
-        const int32_t pp = lower_bound(Tid, nT, r);
-        if (pp < nT && Tid[pp] == r) atomicAdd(&Mu[o_tk * L + Tty[pp]], (AccT)1);
+        if (Th) {
+          uint32_t h = thash_home(r);
+          for (;;) {
+            const int32_t sv = Th[h];
+            if (sv == -1) break;
+            if ((sv >> 4) == r) { cell = o_tk * L + (sv & 15); break; }
+            h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+          }
+        } else {
+          const int32_t pp = lower_bound(Tid, nT, r);
+          if (pp < nT && Tid[pp] == r) cell = o_tk * L + Tty[pp];
+        }
+      }
+      // hits on one typed cell: one LDS atomic per distinct cell and wavefront
+      uint64_t pending = ballot(cell >= 0) & tmask;
+      while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int lc = __shfl(cell, leader, TG_WAVE);
+        const uint64_t same = ballot(cell == lc) & tmask;
+        if (lane() == leader) atomicAdd(&Mu[lc], (AccT)__popcll(same));
+        pending &= ~same;
       }
     }
     if (TSIZE > TG_WAVE) __syncthreads();
@@ -250,7 +284,8 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
                         - sym([&](int x, int y) -> int64_t { return (pi == x) ? Tn(y) : 0; })
                         - sym([&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y]; }) - sym(ETSj);
     const int64_t g7 = (sSiSi + sSjSj) / 2;
-    const int64_t g6 = (int64_t)A.C4[(int64_t)e * P + p] - g10 - 2 * g12;
+    const int64_t c4 = A.c4_wide ? (int64_t)A.C4[(int64_t)e * P + p] : (int64_t)A.C4n[(int64_t)e * P + p];
+    const int64_t g6 = c4 - g10 - 2 * g12;
     const int64_t g3 = sym([&](int x, int y) -> int64_t { return (int64_t)Pi[x * L + y]; })
                      + sym([&](int x, int y) -> int64_t { return (int64_t)Pj[x * L + y]; })
                      - sym([&](int x, int y) -> int64_t { return (pj == x) ? (int64_t)Dj[y] : 0; })
@@ -302,12 +337,14 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   const int koff = A.gacc_in_lds ? nkeys : 0;
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
   // per-team region, in bytes, rounded to 8
+  constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
   const int acc_bytes = 4 * LL * (int)sizeof(AccT);
-  const int region = ((acc_bytes + SCR * 4 + TCAP * 5) + 7) & ~7;
+  const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   char* base = (char*)(smem_comb + koff) + (int64_t)team * region;
   AccT* acc = (AccT*)base;
   int32_t* scratch = (int32_t*)(base + acc_bytes);
-  int32_t* Tid_l = scratch + SCR;
+  int32_t* Th = (HBYTES && A.thash_ok) ? scratch + SCR : nullptr;
+  int32_t* Tid_l = scratch + SCR + HBYTES / 4;
   uint8_t* Tty_l = (uint8_t*)(Tid_l + TCAP);
   int32_t* Tid_g = t_over ? t_over + (int64_t)blockIdx.x * t_over_cap : nullptr;
   uint8_t* Tty_g = t_over ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
@@ -324,7 +361,8 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
       for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
       big = tsum > (uint32_t)TCAP;
     }
-    combine_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc, gacc, scratch, tid);
+    combine_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc, gacc, scratch, tid,
+                              big ? nullptr : Th);
   }
   __syncthreads();
   if (gacc) {
@@ -338,8 +376,9 @@ template <int TSIZE, class AccT>
 inline size_t combine_lds_bytes(int L, int nkeys_in_lds) {
   constexpr int TCAP = TeamCap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
+  constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
   const int acc_bytes = 4 * L * L * (int)sizeof(AccT);
-  const int region = ((acc_bytes + SCR * 4 + TCAP * 5) + 7) & ~7;
+  const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   return (size_t)nkeys_in_lds * 8 + (size_t)(256 / TSIZE) * region;
 }
 

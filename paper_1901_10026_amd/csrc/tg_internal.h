@@ -20,7 +20,7 @@
 #define TG_C4_MED_W 2048      // wedge work handled by one workgroup with an LDS hash
 #define TG_C4_MED_CAP 4096
 #define TG_T_WAVE_CAP 128     // |T_ij| handled by one wavefront
-#define TG_T_WG_CAP 4096      // |T_ij| kept in LDS by a workgroup (larger: global scratch)
+#define TG_T_WG_CAP 2048      // |T_ij| kept in LDS by a workgroup (larger: global scratch)
 #define TG_GACC_MAX_KEYS 5120 // global keys accumulated in LDS per workgroup
 
 namespace tg {
@@ -51,7 +51,7 @@ struct Work {
   uint32_t* tau;         // m*L
   uint64_t* Pn;          // n*L*L
   uint64_t* Un;          // n*L*L
-  uint64_t* C4;          // m*P
+  uint64_t* C4;          // m*P (32-bit counters when they suffice: see c4_wide)
   int32_t* elist;        // m     edge ids grouped by class and bucket
   int32_t* nlist;        // n     node ids grouped by tier
   int32_t* counters;     // small
@@ -72,13 +72,16 @@ struct EdgeArgs {
   const uint32_t* tau;
   const uint64_t* Pn;
   const uint64_t* Un;
-  const uint64_t* C4;
+  const uint64_t* C4;     // 64-bit 4-cycle counters (c4_wide), or
+  const uint32_t* C4n;    // 32-bit ones
+  int c4_wide;
   int L;
   uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or null
   int64_t edge_begin, edge_end;
   uint64_t* global_sums;  // K(L)
   int gacc_in_lds;
   uint64_t* work;         // null, or per-edge element-visit counts (added atomically, by edge id)
+  int thash_ok;           // node ids fit the packed (id << 4 | type) hash slots
 };
 
 }  // namespace tg

@@ -329,23 +329,31 @@ __device__ __forceinline__ void team_sync() {
 
 // Credits the cycles through wedge x-u-w (slots sxu of x's row and suw of
 // u's row) given the typed middle counts between x and w.
-__device__ __forceinline__ void credit_wedge(uint64_t* __restrict__ C4, int L, int P, int32_t e_xu, int32_t e_uw,
+// Per-edge 4-cycle counters are 32 bits when every count fits (the count on
+// edge (i, j) is at most (d_i - 1)(d_j - 1)), else 64 bits.
+__device__ __forceinline__ void c4_add(uint32_t* C4, int64_t idx, uint64_t v) { atomicAdd(&C4[idx], (uint32_t)v); }
+__device__ __forceinline__ void c4_add(uint64_t* C4, int64_t idx, uint64_t v) {
+  atomicAdd((unsigned long long*)&C4[idx], (unsigned long long)v);
+}
+
+template <class C4T>
+__device__ __forceinline__ void credit_wedge(C4T* __restrict__ C4, int L, int P, int32_t e_xu, int32_t e_uw,
                                              int phx, int phu, int phw, int t, uint32_t cnt_t) {
   const int64_t c = (int64_t)cnt_t - (t == phu ? 1 : 0);
   if (c > 0) {
-    atomicAdd((unsigned long long*)&C4[(int64_t)e_xu * P + pair_index(phw, t)], (unsigned long long)c);
-    atomicAdd((unsigned long long*)&C4[(int64_t)e_uw * P + pair_index(phx, t)], (unsigned long long)c);
+    c4_add(C4, (int64_t)e_xu * P + pair_index(phw, t), (uint64_t)c);
+    c4_add(C4, (int64_t)e_uw * P + pair_index(phx, t), (uint64_t)c);
   }
 }
 
 // One team (NWAVES wavefronts) per node x, middle counts in LDS hash tables:
 // kw/tw keyed by w (totals), kt/ct keyed by w*L+t (typed counts).
-template <int NWAVES, int LOG2CAP>
+template <int NWAVES, int LOG2CAP, class C4T>
 __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* __restrict__ list,
                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  int L, const int32_t* __restrict__ s2e,
-                                                 uint64_t* __restrict__ C4) {
+                                                 C4T* __restrict__ C4) {
   constexpr int CAP = 1 << LOG2CAP;
   constexpr int TEAMS = 4 / NWAVES;
   __shared__ int32_t kw_all[TEAMS][CAP];
@@ -419,18 +427,29 @@ __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int32_t* total) {
   return x - v;
 }
 
-__global__ void __launch_bounds__(256) k_c4_group(int phase, int G, const int32_t* __restrict__ gx,
+template <int PHASE, class C4T>
+__global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restrict__ gx,
                                                   const int64_t* __restrict__ gpref, uint32_t* __restrict__ dense,
                                                   int64_t stride, int CS, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
-                                                  const int32_t* __restrict__ s2e, uint64_t* __restrict__ C4) {
-  const int64_t wq = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
+                                                  const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
+                                                  int stage_xu) {
+  // credits to the edges (x, u) of this wavefront's 64 slots are summed in
+  // LDS first (stage_xu: L <= 8 and every sum fits 32 bits)
+  __shared__ uint32_t xu_acc[4][TG_WAVE * 36];
+  const int wib = threadIdx.x / TG_WAVE;
+  const int64_t wq = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib;
   const int64_t total_slots = gpref[G];
   const int64_t s0 = wq * TG_WAVE;
   if (s0 >= total_slots) return;
   const int ln = lane();
   const int P = L * (L + 1) / 2;
+  uint32_t* xacc = xu_acc[wib];
+  if (PHASE == 1 && stage_xu) {
+    for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) xacc[q] = 0u;
+    wave_sync();
+  }
   // this lane's (node, slot) pair
   const int64_t sl = s0 + ln;
   int g = 0;
@@ -479,18 +498,33 @@ __global__ void __launch_bounds__(256) k_c4_group(int phase, int G, const int32_
     const int32_t w = ci[suw];
     if (!precedes(deg[w], w, o_dx, o_x)) continue;
     uint32_t* row = dense + (int64_t)o_g * stride + (int64_t)w * CS;
-    if (phase == 0) {
+    if (PHASE == 0) {
       atomicAdd(&row[o_phu], 1u);
-    } else if (phase == 1) {
+    } else if (PHASE == 1) {
       uint32_t c[16];
       uint32_t sum = 0;
       for (int t = 0; t < L; ++t) { c[t] = row[t]; sum += c[t]; }
       if (sum < 2) continue;
       const int32_t e_uw = s2e[suw];
       const int phw = ty[w];
-      for (int t = 0; t < L; ++t) credit_wedge(C4, L, P, o_exu, e_uw, o_phx, o_phu, phw, t, c[t]);
+      for (int t = 0; t < L; ++t) {
+        const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
+        if (cc <= 0) continue;
+        c4_add(C4, (int64_t)e_uw * P + pair_index(o_phx, t), (uint64_t)cc);
+        if (stage_xu) atomicAdd(&xacc[o * P + pair_index(phw, t)], (uint32_t)cc);
+        else c4_add(C4, (int64_t)o_exu * P + pair_index(phw, t), (uint64_t)cc);
+      }
     } else {
       for (int t = 0; t < L; ++t) row[t] = 0u;
+    }
+  }
+  if (PHASE == 1 && stage_xu) {
+    wave_sync();
+    for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) {
+      const uint32_t val = xacc[q];
+      const int s = q / P;
+      const int32_t es = __shfl(e_xu, s, TG_WAVE);
+      if (val) c4_add(C4, (int64_t)es * P + (q % P), (uint64_t)val);
     }
   }
 }
@@ -597,6 +631,19 @@ __global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32
 // 2 workgroup, 3 grouped dense.
 __device__ __forceinline__ int node_tier(uint64_t W) {
   return W == 0 ? 0 : (W <= TG_C4_LIGHT_W ? 1 : (W <= TG_C4_MED_W ? 2 : 3));
+}
+
+__global__ void __launch_bounds__(256) k_max_degree(int64_t n, const int32_t* __restrict__ deg,
+                                                    int32_t* __restrict__ out) {
+  __shared__ int32_t mx;
+  if (threadIdx.x == 0) mx = 0;
+  __syncthreads();
+  int32_t local = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    local = max(local, deg[v]);
+  atomicMax(&mx, local);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, mx);
 }
 
 __global__ void __launch_bounds__(256) k_node_tier_count(int64_t n, const uint64_t* __restrict__ W,
