@@ -92,7 +92,9 @@ typedef struct {
                                  workgroup (64 = never) */
   int32_t combine_grid;       /* tg_count: workgroup count cap of the small-team combine launches */
   int32_t c4_footprint_mb;    /* tg_count: heavy nodes of the 4-cycle pass are processed in groups
-                                 whose count arrays touch about this many MiB */
+                                 whose count rows touch at most about this many MiB ... */
+  int32_t c4_group_kwedges;   /* ... and that close once they hold this many thousand wedges */
+  int32_t c4_chunk;           /* tg_count: wedges per wavefront in the heavy 4-cycle pass (>= 64) */
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */

@@ -134,18 +134,41 @@ int64_t dense_budget_bytes() {
 }
 
 // Exclusive scan of in[0, n) into out[0, n], out[n] = total.
-tg_status scan(Scratch& S, hipStream_t st, int64_t n, const int32_t* in, int32_t* out) {
+template <class T>
+tg_status scan(Scratch& S, hipStream_t st, int64_t n, const T* in, T* out) {
   const int64_t nb = (n + 1023) / 1024;
-  int32_t* sums;
+  T* sums;
   TG_HIP(S.get(&sums, nb + 1));
   if (nb > 0) {
-    k_scan_blocks<<<(unsigned)nb, 256, 0, st>>>(n, in, out, sums);
+    k_scan_blocks<T><<<(unsigned)nb, 256, 0, st>>>(n, in, out, sums);
     TG_LAUNCHED("k_scan_blocks");
   }
-  k_scan_sums<<<1, 64, 0, st>>>(nb, sums, sums + nb);
+  k_scan_sums<T><<<1, 256, 0, st>>>(nb, sums, sums + nb);
   TG_LAUNCHED("k_scan_sums");
-  k_scan_add<<<grid_for(n + 1, 256, 8192), 256, 0, st>>>(n, out, sums, sums + nb);
+  k_scan_add<T><<<grid_for(n + 1, 256, 8192), 256, 0, st>>>(n, out, sums, sums + nb);
   TG_LAUNCHED("k_scan_add");
+  return TG_OK;
+}
+
+// Gather and row kernels over list[0, count) of one edge class, in batches
+// whose accumulators fit ea (ea_budget bytes).
+template <int TSIZE, class AccT>
+tg_status combine_class(hipStream_t st, const EdgeArgs& A, int64_t count, const int32_t* list, unsigned grid,
+                        int32_t* t_over, int64_t t_cap, int64_t K, void* ea, int64_t ea_budget,
+                        unsigned rows_grid) {
+  const int64_t per = 4ll * A.L * A.L * (int64_t)sizeof(AccT);
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ea_budget / per));
+  const size_t lds = combine_lds_bytes<TSIZE, AccT>(A.L);
+  const size_t rlds = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
+  for (int64_t c0 = 0; c0 < count; c0 += chunk) {
+    const int64_t c = std::min(chunk, count - c0);
+    const unsigned g = std::min(grid, grid_for(c, 256 / TSIZE));
+    k_combine<TSIZE, AccT><<<g, 256, lds, st>>>(A, c, list + c0, reinterpret_cast<AccT*>(ea), t_over, t_cap);
+    TG_LAUNCHED("k_combine");
+    k_combine_rows<AccT><<<grid_for(c, 16, rows_grid), 256, rlds, st>>>(A, c, list + c0,
+                                                                         reinterpret_cast<const AccT*>(ea), (int)K);
+    TG_LAUNCHED("k_combine_rows");
+  }
   return TG_OK;
 }
 
@@ -376,23 +399,32 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
       return hw[a] != hw[b] ? hw[a] > hw[b] : hx[a] < hx[b];
     });
+    // dense rows: 16-bit counts (two per word) when no count can exceed
+    // 65535 (a count is at most d_x), else 32-bit
+    const bool half = max_deg < 65536;
     const int CS = L <= 8 ? 8 : 16;
-    const int64_t stride = n * CS;
+    const int RW = half ? CS / 2 : CS;
+    const int64_t stride = n * RW;
     int64_t Gmax = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
     Gmax = std::max<int64_t>(1, std::min<int64_t>(Gmax, std::min<int64_t>(256, n_t3)));
-    // groups of consecutive nodes (heaviest first) whose dense arrays together
-    // touch about c4_footprint_mb of rows, so that a group's working set can
-    // stay in the last-level cache; at most Gmax nodes per group
+    // groups of consecutive nodes (heaviest first): a group closes once its
+    // wedges fill the chip (c4_group_kwedges thousand) or its count rows
+    // would touch more than c4_footprint_mb, so that they can stay in the
+    // last-level cache; at most Gmax nodes per group
     const int64_t foot = (int64_t)std::max(1, tune.c4_footprint_mb) << 20;
+    const int64_t wtarget = (int64_t)std::max(1, tune.c4_group_kwedges) * 1000;
+    const int CH = std::max(64, tune.c4_chunk);
     std::vector<int64_t> gstart, gcount;
     {
       int64_t q = 0;
       while (q < n_t3) {
-        int64_t c = 0, bytes = 0;
+        int64_t c = 0, bytes = 0, wsum = 0;
         while (q + c < n_t3 && c < Gmax) {
-          const int64_t touched = std::min<int64_t>((int64_t)hw[order[q + c]], n) * CS * (int64_t)sizeof(uint32_t);
-          if (c > 0 && bytes + touched > foot) break;
+          const uint64_t wq = hw[order[q + c]];
+          const int64_t touched = std::min<int64_t>((int64_t)wq, n) * RW * (int64_t)sizeof(uint32_t);
+          if (c > 0 && (bytes + touched > foot || wsum >= wtarget)) break;
           bytes += touched;
+          wsum += (int64_t)wq;
           ++c;
         }
         gstart.push_back(q);
@@ -401,50 +433,70 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       }
     }
     const int64_t ngroups = (int64_t)gstart.size();
-    const int64_t G = Gmax;
+    int64_t G = 0;
+    for (int64_t g = 0; g < ngroups; ++g) G = std::max(G, gcount[g]);
+    // heavy nodes in processing order, prefix of their degrees (slots),
+    // and prefix of their wedge counts (W(x), summed over the node's slots)
     std::vector<int32_t> gx(n_t3);
-    std::vector<int64_t> gp(n_t3 + ngroups, 0);
-    for (int64_t g = 0; g < ngroups; ++g) {
-      int64_t acc2 = 0;
-      for (int64_t q = 0; q < gcount[g]; ++q) {
-        const int64_t idx = gstart[g] + q;
-        gp[gstart[g] + g + q] = acc2;
-        gx[idx] = hx[order[idx]];
-        acc2 += hd[order[idx]];
-      }
-      gp[gstart[g] + g + gcount[g]] = acc2;
+    std::vector<int64_t> hs(n_t3 + 1, 0), hwp(n_t3 + 1, 0);
+    for (int64_t q = 0; q < n_t3; ++q) {
+      gx[q] = hx[order[q]];
+      hs[q + 1] = hs[q] + hd[order[q]];
+      hwp[q + 1] = hwp[q] + (int64_t)hw[order[q]];
     }
+    const int64_t nslots = hs[n_t3];
     int32_t* d_gx;
-    int64_t* d_gp;
+    int64_t *d_hs, *d_sc, *d_wp;
     uint32_t* dense;
     TG_HIP(S.get(&d_gx, n_t3));
-    TG_HIP(S.get(&d_gp, n_t3 + ngroups));
+    TG_HIP(S.get(&d_hs, n_t3 + 1));
+    TG_HIP(S.get(&d_sc, nslots));
+    TG_HIP(S.get(&d_wp, nslots + 1));
     TG_HIP(S.get(&dense, G * stride));
     TG_HIP(hipMemcpyAsync(d_gx, gx.data(), n_t3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    TG_HIP(hipMemcpyAsync(d_gp, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    TG_HIP(hipMemcpyAsync(d_hs, hs.data(), (n_t3 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    k_c4_slot_wedges<<<grid_for(nslots, 256, 16384), 256, 0, st>>>(nslots, n_t3, d_gx, d_hs, rp, ci, W.deg, d_sc);
+    TG_LAUNCHED("k_c4_slot_wedges");
+    if (tg_status s2 = scan(S, st, nslots, (const int64_t*)d_sc, d_wp)) return s2;
     k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
     TG_LAUNCHED("k_fill_u32");
     for (int64_t g = 0; g < ngroups; ++g) {
       const int Gg = (int)gcount[g];
-      const int64_t slots = gp[gstart[g] + g + Gg];
-      const unsigned grid = grid_for(slots, 4 * TG_WAVE);
-      const int32_t* gxg = d_gx + gstart[g];
-      const int64_t* gpg = d_gp + gstart[g] + g;
+      const int64_t q0 = gstart[g];
+      const int64_t W0 = hwp[q0], Wn = hwp[q0 + Gg] - W0;
+      if (Wn == 0) continue;
+      int64_t ch = CH;
+      while ((Wn + ch - 1) / ch > (1ll << 24)) ch *= 2;
+      const unsigned grid = grid_for((Wn + ch - 1) / ch, 4);
+      // the group's nodes, slot prefix (global base) and wedge prefix
+      const int32_t* gxg = d_gx + q0;
+      const int64_t* gsl = d_hs + q0;
+      const int64_t* wpg = d_wp + hs[q0];
+      // clearing by a fill of the group's rows when that is cheaper than a
+      // second walk over its wedges
+      const bool fill_clear = Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 32;
+      const size_t xu_lds = (size_t)4 * TG_WAVE * P * sizeof(uint32_t);
+#define TG_C4_GROUP(PH, T, HF, C4P, STG)                                                                           \
+  k_c4_group<PH, T, HF><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(Gg, gxg, gsl, wpg, W0, Wn, (int)ch, dense, stride, RW, rp, ci, W.deg, ty, \
+                                              L, W.s2e, C4P, STG)
+#define TG_C4_PHASES(T, HF, C4P, STG)                                                   \
+  do {                                                                                  \
+    TG_C4_GROUP(0, T, HF, C4P, STG);                                                    \
+    TG_C4_GROUP(1, T, HF, C4P, STG);                                                    \
+    if (fill_clear)                                                                     \
+      k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0); \
+    else                                                                                \
+      TG_C4_GROUP(2, T, HF, C4P, STG);                                                  \
+  } while (0)
       if (c4_wide) {
-        k_c4_group<0, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      W.C4, 0);
-        k_c4_group<1, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      W.C4, 0);
-        k_c4_group<2, uint64_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      W.C4, 0);
+        if (half) TG_C4_PHASES(uint64_t, true, W.C4, 0);
+        else TG_C4_PHASES(uint64_t, false, W.C4, 0);
       } else {
-        k_c4_group<0, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      C4n, stage_xu);
-        k_c4_group<1, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      C4n, stage_xu);
-        k_c4_group<2, uint32_t><<<grid, 256, 0, st>>>(Gg, gxg, gpg, dense, stride, CS, rp, ci, W.deg, ty, L, W.s2e,
-                                                      C4n, stage_xu);
+        if (half) TG_C4_PHASES(uint32_t, true, C4n, stage_xu);
+        else TG_C4_PHASES(uint32_t, false, C4n, stage_xu);
       }
+#undef TG_C4_PHASES
+#undef TG_C4_GROUP
       TG_LAUNCHED("k_c4_group");
     }
   }
@@ -460,20 +512,28 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
   A.work = nullptr;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
-  const size_t gbytes = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
-  const int kl = A.gacc_in_lds ? (int)K : 0;
-  if (class_count[0] > 0) {
-    const size_t lds = combine_lds_bytes<16, uint32_t>(L, kl);
-    k_combine<16, uint32_t><<<grid_for(class_count[0], 16, std::max(1, tune.combine_grid)), 256, lds, st>>>(
-        A, class_count[0], W.elist + class_begin[0], (int)K, nullptr, 0);
-    TG_LAUNCHED("k_combine<16>");
+  // gathered accumulators of one batch of edges (reused by every class and
+  // batch: all launches are ordered on st)
+  const int64_t ea_budget = 4ll << 30;
+  void* ea = nullptr;
+  {
+    int64_t need = 0;
+    for (int c = 0; c < 3; ++c)
+      need = std::max<int64_t>(need, class_count[c] * 4 * LL * (c == 2 ? 8 : 4));
+    need = std::min(need, ea_budget);
+    if (need > 0) TG_HIP(S.get(reinterpret_cast<uint64_t**>(&ea), (need + 7) / 8));
   }
-  if (class_count[1] > 0) {
-    const size_t lds = combine_lds_bytes<64, uint32_t>(L, kl);
-    k_combine<64, uint32_t><<<grid_for(class_count[1], 4, std::max(1, tune.combine_grid)), 256, lds, st>>>(
-        A, class_count[1], W.elist + class_begin[1], (int)K, nullptr, 0);
-    TG_LAUNCHED("k_combine<64>");
-  }
+  const unsigned rows_grid = (unsigned)std::max(1, tune.combine_grid);
+  if (class_count[0] > 0)
+    if (tg_status s2 = combine_class<16, uint32_t>(st, A, class_count[0], W.elist + class_begin[0],
+                                                   grid_for(class_count[0], 16, std::max(1, tune.combine_grid)),
+                                                   nullptr, 0, K, ea, ea_budget, rows_grid))
+      return s2;
+  if (class_count[1] > 0)
+    if (tg_status s2 = combine_class<64, uint32_t>(st, A, class_count[1], W.elist + class_begin[1],
+                                                   grid_for(class_count[1], 4, std::max(1, tune.combine_grid)),
+                                                   nullptr, 0, K, ea, ea_budget, rows_grid))
+      return s2;
   if (class_count[2] > 0) {
     const unsigned grid = grid_for(class_count[2], 1, 1024);
     int32_t* t_over = nullptr;
@@ -482,10 +542,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       t_cap = max_t_heavy;
       TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
     }
-    const size_t lds = combine_lds_bytes<256, uint64_t>(L, kl);
-    k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, class_count[2], W.elist + class_begin[2], (int)K, t_over,
-                                                     t_cap);
-    TG_LAUNCHED("k_combine<256>");
+    if (tg_status s2 = combine_class<256, uint64_t>(st, A, class_count[2], W.elist + class_begin[2], grid, t_over,
+                                                    t_cap, K, ea, ea_budget, rows_grid))
+      return s2;
   }
 
   // ---- Eq. 17 and outputs
@@ -738,8 +797,6 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   uint32_t* tmax;
   TG_HIP(S.get(&gsink, K));
   TG_HIP(S.get(&tmax, 1));
-  k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
-  TG_LAUNCHED("k_fill_u64");
   k_fill_u64<<<grid_for(m, 256, 8192), 256, 0, st>>>(work_by_edge, m, 0);
   TG_LAUNCHED("k_fill_u64");
   k_fill_u64<<<1, 64, 0, st>>>(gsink, K, 0);
@@ -767,8 +824,8 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
     t_cap = h_tmax;
     TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
   }
-  const size_t lds = combine_lds_bytes<256, uint64_t>(L, 0);
-  k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, count, list, (int)K, t_over, t_cap);
+  const size_t lds = combine_lds_bytes<256, uint64_t>(L);
+  k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, count, list, nullptr, t_over, t_cap);
   TG_LAUNCHED("k_combine<256>");
   return TG_OK;
 }
@@ -918,7 +975,9 @@ void tg_tuning_default(tg_tuning* t) {
   t->mid_log2_cost = 64;
   t->heavy_log2_cost = 64;
   t->combine_grid = 2048;
-  t->c4_footprint_mb = 4096;
+  t->c4_footprint_mb = 192;
+  t->c4_group_kwedges = 4096;
+  t->c4_chunk = 1024;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }
@@ -1178,7 +1237,9 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
     }
   }
   axes.push_back({&t.combine_grid, {1024, 2048, 4096, 8192}});
-  axes.push_back({&t.c4_footprint_mb, {256, 1024, 4096}});
+  axes.push_back({&t.c4_footprint_mb, {64, 192, 1024}});
+  axes.push_back({&t.c4_group_kwedges, {1024, 4096, 16384}});
+  axes.push_back({&t.c4_chunk, {256, 1024, 4096}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

@@ -22,9 +22,13 @@
 //   g3 = sym(E(S_i,I) + E(S_j,I)),
 // then g4, g5, g9, g11 follow from Eqs. 7-10 and the graphlets from Eqs. 11-16.
 //
-// One team of TSIZE lanes (16 or 64 lanes of a wavefront, or a 256-lane
-// workgroup) handles one edge at a time.  AccT is the width of the LDS
-// accumulators (32 bits suffices when |T_ij| is small).
+// Two kernels per batch of edges.  The gather kernel builds T_ij and the
+// accumulators A_i, A_j, Q, Mu (one team of TSIZE lanes per edge: 16 or 64
+// lanes of a wavefront, or a 256-lane workgroup; AccT is their width, 32
+// bits when |T_ij| is small) and stores them per edge; the row kernel turns
+// them into orbits, graphlets and global key sums.  Keeping the identities
+// out of the gather kernel keeps its register count, and so its occupancy,
+// set by the intersection and 4-clique loops alone.
 
 template <int TSIZE>
 __device__ __forceinline__ void tsync() {
@@ -83,9 +87,9 @@ __device__ __forceinline__ uint32_t thash_home(int32_t k) {
 }
 
 template <int TSIZE, class AccT>
-__device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
-                                             AccT* __restrict__ acc, uint64_t* gacc, int32_t* scratch, int tid,
-                                             int32_t* Th) {
+__device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
+                                            AccT* __restrict__ acc, AccT* __restrict__ out, int32_t* scratch,
+                                            int tid, int32_t* Th) {
   const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
   const int R = 2 * L + 6 * P;
   AccT* Aa = acc;
@@ -186,56 +190,86 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
       s_excl[2 * TSIZE + tid] = tk;
       __syncthreads();
     }
-    for (int32_t c0 = 0; c0 < tot; c0 += TSIZE) {
-      const int32_t v = c0 + tid;
-      int o = 0;
-      int32_t o_excl, o_start, o_tk;
-      if (TSIZE <= TG_WAVE) {
-        for (int step = TSIZE / 2; step > 0; step >>= 1) {
-          const int32_t ex = __shfl(excl, o + step, TSIZE);
-          if (ex <= v) o += step;
-        }
-        o_excl = __shfl(excl, o, TSIZE);
-        o_start = __shfl(ostart, o, TSIZE);
-        o_tk = __shfl(tk, o, TSIZE);
-      } else {
-        for (int step = TSIZE / 2; step > 0; step >>= 1)
-          if (s_excl[o + step] <= v) o += step;
-        o_excl = s_excl[o];
-        o_start = s_excl[TSIZE + o];
-        o_tk = s_excl[2 * TSIZE + o];
-      }
-      int cell = -1;
-      if (v < tot) {
-        const int32_t r = A.out_col[o_start + (v - o_excl)];
-        if (Th) {
-          uint32_t h = thash_home(r);
-          for (;;) {
-            const int32_t sv = Th[h];
-            if (sv == -1) break;
-            if ((sv >> 4) == r) { cell = o_tk * L + (sv & 15); break; }
-            h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+    // U (member, out-slot) pairs per lane at a time, so that U independent
+    // out-list loads are in flight before their lookups
+    constexpr int U = 4;
+    for (int32_t c0 = 0; c0 < tot; c0 += TSIZE * U) {
+      int32_t r[U];
+      int rtk[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int32_t v = c0 + k * TSIZE + tid;
+        int o = 0;
+        int32_t o_excl, o_start, o_tk;
+        if (TSIZE <= TG_WAVE) {
+          for (int step = TSIZE / 2; step > 0; step >>= 1) {
+            const int32_t ex = __shfl(excl, o + step, TSIZE);
+            if (ex <= v) o += step;
           }
+          o_excl = __shfl(excl, o, TSIZE);
+          o_start = __shfl(ostart, o, TSIZE);
+          o_tk = __shfl(tk, o, TSIZE);
         } else {
-          const int32_t pp = lower_bound(Tid, nT, r);
-          if (pp < nT && Tid[pp] == r) cell = o_tk * L + Tty[pp];
+          for (int step = TSIZE / 2; step > 0; step >>= 1)
+            if (s_excl[o + step] <= v) o += step;
+          o_excl = s_excl[o];
+          o_start = s_excl[TSIZE + o];
+          o_tk = s_excl[2 * TSIZE + o];
         }
+        r[k] = v < tot ? A.out_col[o_start + (v - o_excl)] : -1;
+        rtk[k] = o_tk;
       }
-      // hits on one typed cell: one LDS atomic per distinct cell and wavefront
-      uint64_t pending = ballot(cell >= 0) & tmask;
-      while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int lc = __shfl(cell, leader, TG_WAVE);
-        const uint64_t same = ballot(cell == lc) & tmask;
-        if (lane() == leader) atomicAdd(&Mu[lc], (AccT)__popcll(same));
-        pending &= ~same;
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        int cell = -1;
+        if (r[k] >= 0) {
+          if (Th) {
+            uint32_t h = thash_home(r[k]);
+            for (;;) {
+              const int32_t sv = Th[h];
+              if (sv == -1) break;
+              if ((sv >> 4) == r[k]) { cell = rtk[k] * L + (sv & 15); break; }
+              h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+            }
+          } else {
+            const int32_t pp = lower_bound(Tid, nT, r[k]);
+            if (pp < nT && Tid[pp] == r[k]) cell = rtk[k] * L + Tty[pp];
+          }
+        }
+        // hits on one typed cell: one LDS atomic per distinct cell and wavefront
+        uint64_t pending = ballot(cell >= 0) & tmask;
+        while (pending) {
+          const int leader = __builtin_ctzll(pending);
+          const int lc = __shfl(cell, leader, TG_WAVE);
+          const uint64_t same = ballot(cell == lc) & tmask;
+          if (lane() == leader) atomicAdd(&Mu[lc], (AccT)__popcll(same));
+          pending &= ~same;
+        }
       }
     }
     if (TSIZE > TG_WAVE) __syncthreads();
   }
   if (A.work && tid == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
   tsync<TSIZE>();
+  if (out)
+    for (int x = tid; x < 4 * LL; x += TSIZE) out[x] = acc[x];
+  tsync<TSIZE>();
+}
 
+// Orbits, graphlets (per-edge row) and global key sums of edge e from its
+// gathered accumulators ea = [A_a | A_b | Q | Mu] (a = the endpoint with the
+// shorter row).  One team of TSIZE lanes per edge.
+template <int TSIZE, class AccT>
+__device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const AccT* __restrict__ ea,
+                                          uint64_t* gacc, int tid) {
+  const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
+  const int R = 2 * L + 6 * P;
+  const int32_t i = A.ei[e], j = A.ej[e];
+  const bool a_is_i = A.deg[i] <= A.deg[j];
+  const AccT* Aa = ea;
+  const AccT* Ab = ea + LL;
+  const AccT* Q = ea + 2 * LL;
+  const AccT* Mu = ea + 3 * LL;
   // ---- per type pair: every orbit, then every graphlet
   const int pi = A.ty[i], pj = A.ty[j];
   const AccT* Ai = a_is_i ? Aa : Ab;
@@ -312,7 +346,6 @@ __device__ __forceinline__ void combine_edge(const EdgeArgs& A, int32_t e, int32
       gadd(key_of(L, 2 + s, pi, pj, t, u), h[s]);
     }
   }
-  tsync<TSIZE>();
 }
 
 // Capacity of T_ij kept in LDS per team.
@@ -321,26 +354,27 @@ struct TeamCap {
   static constexpr int value = TSIZE == 16 ? 64 : (TSIZE == 64 ? 256 : TG_T_WG_CAP);
 };
 
-// One team per edge, grid-stride over a list.  LDS: [global key
-// accumulators] then per team [acc 4L^2 AccT][scan scratch][T ids][T types].
-// A T_ij larger than the team's capacity (workgroup teams only) is kept in
-// this workgroup's slice of a global scratch.
+// Gather kernel: one team per edge, grid-stride over list[0, count); the
+// accumulators of list[w] go to ea[w * 4L^2 ...] (or nowhere when ea is
+// null: work measurement only).  LDS per team: [acc 4L^2 AccT][scan
+// scratch][T hash (workgroup teams)][T ids][T types].  A T_ij larger than
+// the team's capacity (workgroup teams only) is kept in this workgroup's
+// slice of a global scratch.
 template <int TSIZE, class AccT>
 __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
-                                                 int nkeys, int32_t* __restrict__ t_over, int64_t t_over_cap) {
+                                                 AccT* __restrict__ ea, int32_t* __restrict__ t_over,
+                                                 int64_t t_over_cap) {
   extern __shared__ uint64_t smem_comb[];
   constexpr int TEAMS = 256 / TSIZE;
   constexpr int TCAP = TeamCap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
   const int LL = A.L * A.L;
-  uint64_t* gacc = A.gacc_in_lds ? smem_comb : nullptr;
-  const int koff = A.gacc_in_lds ? nkeys : 0;
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
   // per-team region, in bytes, rounded to 8
   constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
   const int acc_bytes = 4 * LL * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
-  char* base = (char*)(smem_comb + koff) + (int64_t)team * region;
+  char* base = (char*)smem_comb + (int64_t)team * region;
   AccT* acc = (AccT*)base;
   int32_t* scratch = (int32_t*)(base + acc_bytes);
   int32_t* Th = (HBYTES && A.thash_ok) ? scratch + SCR : nullptr;
@@ -349,10 +383,6 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   int32_t* Tid_g = t_over ? t_over + (int64_t)blockIdx.x * t_over_cap : nullptr;
   uint8_t* Tty_g = t_over ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
                           : nullptr;
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
-  }
-  __syncthreads();
   for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
     const int32_t e = list[w];
     bool big = false;
@@ -361,24 +391,40 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
       for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
       big = tsum > (uint32_t)TCAP;
     }
-    combine_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc, gacc, scratch, tid,
-                              big ? nullptr : Th);
-  }
-  __syncthreads();
-  if (gacc) {
-    for (int x = threadIdx.x; x < nkeys; x += blockDim.x)
-      if (gacc[x]) atomicAdd((unsigned long long*)&A.global_sums[x], (unsigned long long)gacc[x]);
+    gather_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
+                             ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? nullptr : Th);
   }
 }
 
 // LDS bytes of k_combine<TSIZE, AccT>
 template <int TSIZE, class AccT>
-inline size_t combine_lds_bytes(int L, int nkeys_in_lds) {
+inline size_t combine_lds_bytes(int L) {
   constexpr int TCAP = TeamCap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
   constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
   const int acc_bytes = 4 * L * L * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
-  return (size_t)nkeys_in_lds * 8 + (size_t)(256 / TSIZE) * region;
+  return (size_t)(256 / TSIZE) * region;
 }
 
+// Row kernel: one 16-lane team per edge of list[0, count), accumulators
+// from ea (as written by the gather kernel over the same list); global key
+// sums are gathered in LDS first when gacc_in_lds.
+template <class AccT>
+__global__ void __launch_bounds__(256) k_combine_rows(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
+                                                      const AccT* __restrict__ ea, int nkeys) {
+  extern __shared__ uint64_t smem_rows[];
+  constexpr int TS = 16, TEAMS = 256 / TS;
+  const int LL = A.L * A.L;
+  uint64_t* gacc = A.gacc_in_lds ? smem_rows : nullptr;
+  if (gacc)
+    for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
+  __syncthreads();
+  const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
+  for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS)
+    edge_rows<TS, AccT>(A, list[w], ea + w * 4 * LL, gacc, tid);
+  __syncthreads();
+  if (gacc)
+    for (int x = threadIdx.x; x < nkeys; x += blockDim.x)
+      if (gacc[x]) atomicAdd((unsigned long long*)&A.global_sums[x], (unsigned long long)gacc[x]);
+}

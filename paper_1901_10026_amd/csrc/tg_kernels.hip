@@ -125,42 +125,63 @@ __global__ void k_node_stats(int64_t n, const int32_t* __restrict__ rp, const in
   }
 }
 
-// Exclusive scan of int32 counts into int32 offsets (offsets[n] = total), in
-// three passes over blocks of 1024.
-__global__ void k_scan_blocks(int64_t n, const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                              int32_t* __restrict__ block_sums) {
-  __shared__ int32_t s[1024];
+// Exclusive scan of counts into offsets (offsets[n] = total), in three
+// passes over blocks of 1024; T is int32_t or int64_t.
+template <class T>
+__global__ void __launch_bounds__(256) k_scan_blocks(int64_t n, const T* __restrict__ in, T* __restrict__ out,
+                                                     T* __restrict__ block_sums) {
+  __shared__ T s[1024];
   const int64_t base = (int64_t)blockIdx.x * 1024;
-  for (int q = threadIdx.x; q < 1024; q += blockDim.x) s[q] = (base + q < n) ? in[base + q] : 0;
+  for (int q = threadIdx.x; q < 1024; q += blockDim.x) s[q] = (base + q < n) ? in[base + q] : (T)0;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    int32_t add[4];
+    T add[4];
     for (int r = 0; r < 4; ++r) {
       int q = threadIdx.x + r * 256;
-      add[r] = (q >= off) ? s[q - off] : 0;
+      add[r] = (q >= off) ? s[q - off] : (T)0;
     }
     __syncthreads();
     for (int r = 0; r < 4; ++r) s[threadIdx.x + r * 256] += add[r];
     __syncthreads();
   }
   for (int q = threadIdx.x; q < 1024; q += blockDim.x)
-    if (base + q < n) out[base + q] = (q > 0) ? s[q - 1] : 0;
+    if (base + q < n) out[base + q] = (q > 0) ? s[q - 1] : (T)0;
   if (threadIdx.x == 0) block_sums[blockIdx.x] = s[1023];
 }
 
-__global__ void k_scan_sums(int64_t nblocks, int32_t* __restrict__ block_sums, int32_t* __restrict__ total) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t acc = 0;
-  for (int64_t b = 0; b < nblocks; ++b) {
-    int32_t x = block_sums[b];
-    block_sums[b] = acc;
-    acc += x;
+// Exclusive scan of the block sums in place (one workgroup of 256), total
+// into *total.
+template <class T>
+__global__ void __launch_bounds__(256) k_scan_sums(int64_t nblocks, T* __restrict__ block_sums,
+                                                   T* __restrict__ total) {
+  __shared__ T part[256];
+  const int64_t per = (nblocks + 255) / 256;
+  const int64_t b0 = min((int64_t)threadIdx.x * per, nblocks), b1 = min(b0 + per, nblocks);
+  T acc = 0;
+  for (int64_t b = b0; b < b1; ++b) acc += block_sums[b];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int q = 0; q < 256; ++q) {
+      const T v = part[q];
+      part[q] = run;
+      run += v;
+    }
+    *total = run;
   }
-  *total = acc;
+  __syncthreads();
+  T run = part[threadIdx.x];
+  for (int64_t b = b0; b < b1; ++b) {
+    const T v = block_sums[b];
+    block_sums[b] = run;
+    run += v;
+  }
 }
 
-__global__ void k_scan_add(int64_t n, int32_t* __restrict__ out, const int32_t* __restrict__ block_sums,
-                           const int32_t* __restrict__ total) {
+template <class T>
+__global__ void k_scan_add(int64_t n, T* __restrict__ out, const T* __restrict__ block_sums,
+                           const T* __restrict__ total) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += (int64_t)gridDim.x * blockDim.x) {
     if (x == n) out[n] = *total;
     else out[x] += block_sums[x / 1024];
@@ -408,14 +429,19 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
 }
 
 // Nodes with large wedge work: a group of nodes at a time, each with a dense
-// per-node array of typed middle counts cnt[w * CS + t] (CS = 8 for L <= 8,
-// else 16: one aligned row per far end w) in global memory.  Phase 0 counts,
-// phase 1 credits, phase 2 clears; kernel boundaries order the phases.
+// per-node array of typed middle counts in global memory, one row of RW
+// 32-bit words per far end w (RW = CS words of 32-bit counts, or CS / 2
+// words holding two 16-bit counts when no count can exceed 65535, i.e. the
+// maximum degree is below 65536).  Phase 0 counts, phase 1 credits, phase 2
+// clears; kernel boundaries order the phases.
 //
-// Work mapping: wavefront q takes 64 consecutive (node, slot) pairs of the
-// group's rows; the pairs whose middle u precedes x contribute d_u wedges,
-// and the wavefront's wedges are dealt to lanes 64 at a time through a
-// wavefront prefix sum, so that lanes stay busy whatever the degrees.
+// Work mapping: the group's wedges x-u-w, in (node, slot of x's row,
+// position in u's row) order, are numbered through wp, the prefix over the
+// group's slots of their wedge counts (d_u when u precedes x, else 0).
+// Wavefront c takes wedges [c * CH, (c + 1) * CH) whatever the degrees, and
+// walks them 64 slots at a time: lane l owns one slot, its clipped wedge
+// count goes through a wavefront prefix sum, and the window's wedges are
+// dealt to lanes 64 at a time.
 __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int32_t* total) {
   const int ln = lane();
   int32_t x = v;
@@ -427,105 +453,173 @@ __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int32_t* total) {
   return x - v;
 }
 
-template <int PHASE, class C4T>
+// Wedge count of each slot of the heavy nodes (listed in processing order,
+// hs = prefix of their degrees): d_u when the middle u precedes x.
+__global__ void k_c4_slot_wedges(int64_t nslots, int64_t nnodes, const int32_t* __restrict__ hx,
+                                 const int64_t* __restrict__ hs, const int32_t* __restrict__ rp,
+                                 const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
+                                 int64_t* __restrict__ cnt) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnodes;  // largest q with hs[q] <= s
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hs[mid] <= s) lo = mid; else hi = mid;
+    }
+    const int32_t x = hx[lo];
+    const int32_t u = ci[rp[x] + (s - hs[lo])];
+    const int32_t du = deg[u];
+    cnt[s] = precedes(du, u, deg[x], x) ? (int64_t)du : 0;
+  }
+}
+
+template <int PHASE, class C4T, bool HALF>
 __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restrict__ gx,
-                                                  const int64_t* __restrict__ gpref, uint32_t* __restrict__ dense,
-                                                  int64_t stride, int CS, const int32_t* __restrict__ rp,
+                                                  const int64_t* __restrict__ gslot, const int64_t* __restrict__ wp,
+                                                  int64_t W0, int64_t Wn, int CH, uint32_t* __restrict__ dense,
+                                                  int64_t stride, int RW, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
                                                   int stage_xu) {
-  // credits to the edges (x, u) of this wavefront's 64 slots are summed in
-  // LDS first (stage_xu: L <= 8 and every sum fits 32 bits)
-  __shared__ uint32_t xu_acc[4][TG_WAVE * 36];
+  // credits to the edges (x, u) of the window's 64 slots are summed in LDS
+  // first (stage_xu: L <= 8 and every sum fits 32 bits); dynamic LDS of
+  // 4 * 64 * P words in phase 1 with stage_xu, else none
+  extern __shared__ uint32_t xu_acc[];
   const int wib = threadIdx.x / TG_WAVE;
-  const int64_t wq = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib;
-  const int64_t total_slots = gpref[G];
-  const int64_t s0 = wq * TG_WAVE;
-  if (s0 >= total_slots) return;
+  const int64_t wbeg = ((int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib) * CH;
+  if (wbeg >= Wn) return;
+  const int64_t wend = min(wbeg + (int64_t)CH, Wn);
   const int ln = lane();
   const int P = L * (L + 1) / 2;
-  uint32_t* xacc = xu_acc[wib];
-  if (PHASE == 1 && stage_xu) {
-    for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) xacc[q] = 0u;
-    wave_sync();
-  }
-  // this lane's (node, slot) pair
-  const int64_t sl = s0 + ln;
-  int g = 0;
-  int32_t x = 0, dx = 0, u = 0, bu = 0, cu = 0, e_xu = 0;
-  int phx = 0, phu = 0;
-  if (sl < total_slots) {
-    int lo = 0, hi = G;  // largest g with gpref[g] <= sl
+  // gslot holds the group's slot prefix with an arbitrary base
+  const int64_t sbase = gslot[0];
+  const int64_t S = gslot[G] - sbase;
+  uint32_t* xacc = xu_acc + wib * TG_WAVE * P;
+  // first slot: the largest s < S with wp[s] - W0 <= wbeg
+  int64_t sa;
+  {
+    int64_t lo = 0, hi = S;
     while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (gpref[mid] <= sl) lo = mid; else hi = mid;
+      const int64_t mid = (lo + hi) >> 1;
+      if (wp[mid] - W0 <= wbeg) lo = mid; else hi = mid;
     }
-    g = lo;
-    x = gx[g];
-    dx = deg[x];
-    const int32_t sx = rp[x] + (int32_t)(sl - gpref[g]);
-    u = ci[sx];
-    const int32_t du = deg[u];
-    if (precedes(du, u, dx, x)) {
-      cu = du;
-      bu = rp[u];
-      phx = ty[x];
-      phu = ty[u];
-      e_xu = s2e[sx];
-    }
+    sa = lo;
   }
-  int32_t tot = 0;
-  const int32_t excl = wave_excl_scan(cu, &tot);
-  for (int32_t c0 = 0; c0 < tot; c0 += TG_WAVE) {
-    const int32_t v = c0 + ln;
-    // owner lane: the largest l with excl[l] <= v (excl is non-decreasing)
-    int o = 0;
-    for (int step = 32; step > 0; step >>= 1) {
-      const int32_t ex = __shfl(excl, o + step, TG_WAVE);
-      if (o + step < TG_WAVE && ex <= v) o += step;
+  for (;;) {
+    if (PHASE == 1 && stage_xu) {
+      for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) xacc[q] = 0u;
+      wave_sync();
     }
-    const int32_t o_excl = __shfl(excl, o, TG_WAVE);
-    const int32_t o_bu = __shfl(bu, o, TG_WAVE);
-    const int32_t o_x = __shfl(x, o, TG_WAVE);
-    const int32_t o_dx = __shfl(dx, o, TG_WAVE);
-    const int o_g = __shfl(g, o, TG_WAVE);
-    const int o_phx = __shfl(phx, o, TG_WAVE);
-    const int o_phu = __shfl(phu, o, TG_WAVE);
-    const int32_t o_exu = __shfl(e_xu, o, TG_WAVE);
-    if (v >= tot) continue;
-    const int32_t suw = o_bu + (v - o_excl);
-    const int32_t w = ci[suw];
-    if (!precedes(deg[w], w, o_dx, o_x)) continue;
-    uint32_t* row = dense + (int64_t)o_g * stride + (int64_t)w * CS;
-    if (PHASE == 0) {
-      atomicAdd(&row[o_phu], 1u);
-    } else if (PHASE == 1) {
-      uint32_t c[16];
-      uint32_t sum = 0;
-      for (int t = 0; t < L; ++t) { c[t] = row[t]; sum += c[t]; }
-      if (sum < 2) continue;
-      const int32_t e_uw = s2e[suw];
-      const int phw = ty[w];
-      for (int t = 0; t < L; ++t) {
-        const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
-        if (cc <= 0) continue;
-        c4_add(C4, (int64_t)e_uw * P + pair_index(o_phx, t), (uint64_t)cc);
-        if (stage_xu) atomicAdd(&xacc[o * P + pair_index(phw, t)], (uint32_t)cc);
-        else c4_add(C4, (int64_t)o_exu * P + pair_index(phw, t), (uint64_t)cc);
+    // this lane's slot and the part of its wedges inside [wbeg, wend)
+    const int64_t sl = sa + ln;
+    int32_t x = 0, dx = 0, bu = 0, cu = 0, off = 0, e_xu = 0, gi = 0;
+    int phx = 0, phu = 0;
+    if (sl < S) {
+      const int64_t ws = wp[sl] - W0, we = wp[sl + 1] - W0;
+      const int64_t lo = max(ws, wbeg), hi = min(we, wend);
+      if (hi > lo) {
+        int a = 0, b = G;  // largest g with gslot[g] <= sl
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (gslot[mid] - sbase <= sl) a = mid; else b = mid;
+        }
+        gi = a;
+        x = gx[a];
+        dx = deg[x];
+        const int32_t sx = rp[x] + (int32_t)(sl - (gslot[a] - sbase));
+        const int32_t u = ci[sx];
+        cu = (int32_t)(hi - lo);
+        off = (int32_t)(lo - ws);
+        bu = rp[u];
+        phx = ty[x];
+        phu = ty[u];
+        e_xu = s2e[sx];
       }
-    } else {
-      for (int t = 0; t < L; ++t) row[t] = 0u;
     }
-  }
-  if (PHASE == 1 && stage_xu) {
-    wave_sync();
-    for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) {
-      const uint32_t val = xacc[q];
-      const int s = q / P;
-      const int32_t es = __shfl(e_xu, s, TG_WAVE);
-      if (val) c4_add(C4, (int64_t)es * P + (q % P), (uint64_t)val);
+    int32_t tot = 0;
+    const int32_t excl = wave_excl_scan(cu, &tot);
+    // U batches of 64 wedges per step: their row and degree loads are
+    // issued before any of them is used
+    constexpr int U = 2;
+    for (int32_t c0 = 0; c0 < tot; c0 += TG_WAVE * U) {
+      int32_t wv[U], sv[U], ov[U];
+      bool ok[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int32_t v = c0 + k * TG_WAVE + ln;
+        // owner lane: the largest l with excl[l] <= v (excl is non-decreasing)
+        int o = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+          const int32_t ex = __shfl(excl, o + step, TG_WAVE);
+          if (o + step < TG_WAVE && ex <= v) o += step;
+        }
+        const int32_t o_excl = __shfl(excl, o, TG_WAVE);
+        const int32_t o_bu = __shfl(bu, o, TG_WAVE);
+        const int32_t o_off = __shfl(off, o, TG_WAVE);
+        ov[k] = o;
+        ok[k] = v < tot;
+        sv[k] = o_bu + o_off + (v - o_excl);
+        wv[k] = ok[k] ? ci[sv[k]] : 0;
+      }
+      int32_t dw[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) dw[k] = ok[k] ? deg[wv[k]] : 0;
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int o = ov[k];
+        const int32_t o_x = __shfl(x, o, TG_WAVE);
+        const int32_t o_dx = __shfl(dx, o, TG_WAVE);
+        const int32_t o_gi = __shfl(gi, o, TG_WAVE);
+        const int o_phx = __shfl(phx, o, TG_WAVE);
+        const int o_phu = __shfl(phu, o, TG_WAVE);
+        const int32_t o_exu = __shfl(e_xu, o, TG_WAVE);
+        const int32_t w = wv[k], suw = sv[k];
+        if (!ok[k] || !precedes(dw[k], w, o_dx, o_x)) continue;
+        uint32_t* row = dense + (int64_t)o_gi * stride + (int64_t)w * RW;
+        if (PHASE == 0) {
+          if (HALF) atomicAdd(&row[o_phu >> 1], 1u << ((o_phu & 1) << 4));
+          else atomicAdd(&row[o_phu], 1u);
+        } else if (PHASE == 1) {
+          uint32_t c[16];
+          uint32_t sum = 0;
+          if (HALF) {
+            for (int q = 0; q < RW; ++q) {
+              const uint32_t wd = row[q];
+              c[2 * q] = wd & 0xffffu;
+              c[2 * q + 1] = wd >> 16;
+            }
+          } else {
+            for (int t = 0; t < L; ++t) c[t] = row[t];
+          }
+          for (int t = 0; t < L; ++t) sum += c[t];
+          if (sum < 2) continue;
+          const int32_t e_uw = s2e[suw];
+          const int phw = ty[w];
+          for (int t = 0; t < L; ++t) {
+            const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
+            if (cc <= 0) continue;
+            c4_add(C4, (int64_t)e_uw * P + pair_index(o_phx, t), (uint64_t)cc);
+            if (stage_xu) atomicAdd(&xacc[o * P + pair_index(phw, t)], (uint32_t)cc);
+            else c4_add(C4, (int64_t)o_exu * P + pair_index(phw, t), (uint64_t)cc);
+          }
+        } else {
+          for (int q = 0; q < RW; ++q) row[q] = 0u;
+        }
+      }
     }
+    if (PHASE == 1 && stage_xu) {
+      wave_sync();
+      for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) {
+        const uint32_t val = xacc[q];
+        const int s = q / P;
+        const int32_t es = __shfl(e_xu, s, TG_WAVE);
+        if (val) c4_add(C4, (int64_t)es * P + (q % P), (uint64_t)val);
+      }
+      wave_sync();
+    }
+    // next window, unless it starts at or past this wavefront's last wedge
+    sa += TG_WAVE;
+    if (sa >= S || wp[sa] - W0 >= wend) break;
   }
 }
 
