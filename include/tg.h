@@ -95,6 +95,9 @@ typedef struct {
                                  whose count rows touch at most about this many MiB ... */
   int32_t c4_group_kwedges;   /* ... and that close once they hold this many thousand wedges */
   int32_t c4_chunk;           /* tg_count: wedges per wavefront in the heavy 4-cycle pass (>= 64) */
+  int32_t c4_hash_ratio;      /* tg_count: a heavy node uses a hash table of its far ends instead of a
+                                 dense array when the table is at least this many times smaller
+                                 (0 = never) */
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */

@@ -405,36 +405,69 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     const int CS = L <= 8 ? 8 : 16;
     const int RW = half ? CS / 2 : CS;
     const int64_t stride = n * RW;
+    // Nodes whose far ends are few compared with n (a table of 2^k >= 2
+    // min(W, n) rows is at least c4_hash_ratio times smaller than a dense
+    // array) use hash tables; the rest (the heaviest, a prefix of the
+    // order) use dense arrays.
+    auto hash_log2 = [&](uint64_t wq) {
+      const int64_t want = 2 * std::min<int64_t>((int64_t)wq, n);
+      int lg = 6;
+      while ((1ll << lg) < want) ++lg;
+      return lg;
+    };
+    const int hash_ratio = std::max(0, tune.c4_hash_ratio);
+    int64_t qd = n_t3;  // nodes [0, qd) dense, [qd, n_t3) hashed
+    if (hash_ratio > 0) {
+      qd = 0;
+      while (qd < n_t3 && ((1ll << hash_log2(hw[order[qd]])) * (1 + RW)) * hash_ratio > stride) ++qd;
+    }
     int64_t Gmax = dense_budget_bytes() / (stride * (int64_t)sizeof(uint32_t));
     Gmax = std::max<int64_t>(1, std::min<int64_t>(Gmax, std::min<int64_t>(256, n_t3)));
     // groups of consecutive nodes (heaviest first): a group closes once its
     // wedges fill the chip (c4_group_kwedges thousand) or its count rows
     // would touch more than c4_footprint_mb, so that they can stay in the
-    // last-level cache; at most Gmax nodes per group
+    // last-level cache; at most Gmax nodes per dense group
     const int64_t foot = (int64_t)std::max(1, tune.c4_footprint_mb) << 20;
     const int64_t wtarget = (int64_t)std::max(1, tune.c4_group_kwedges) * 1000;
     const int CH = std::max(64, tune.c4_chunk);
     std::vector<int64_t> gstart, gcount;
+    std::vector<int64_t> hoff(n_t3, 0);
+    std::vector<uint8_t> hlog(n_t3, 0);
+    std::vector<int64_t> grows;  // hash rows of each group (0 for dense groups)
+    int64_t G = 0, max_hrows = 0;
     {
       int64_t q = 0;
       while (q < n_t3) {
-        int64_t c = 0, bytes = 0, wsum = 0;
-        while (q + c < n_t3 && c < Gmax) {
+        const bool hashed = q >= qd;
+        const int64_t qend = hashed ? n_t3 : qd;
+        int64_t c = 0, bytes = 0, wsum = 0, rows = 0;
+        while (q + c < qend && (hashed ? c < (1 << 20) : c < Gmax)) {
           const uint64_t wq = hw[order[q + c]];
-          const int64_t touched = std::min<int64_t>((int64_t)wq, n) * RW * (int64_t)sizeof(uint32_t);
-          if (c > 0 && (bytes + touched > foot || wsum >= wtarget)) break;
+          int64_t touched;
+          if (hashed) {
+            const int lg = hash_log2(wq);
+            touched = (1ll << lg) * (1 + RW) * (int64_t)sizeof(uint32_t);
+            if (c > 0 && (bytes + touched > foot || wsum >= wtarget)) break;
+            hoff[q + c] = rows;
+            hlog[q + c] = (uint8_t)lg;
+            rows += 1ll << lg;
+          } else {
+            touched = std::min<int64_t>((int64_t)wq, n) * RW * (int64_t)sizeof(uint32_t);
+            if (c > 0 && (bytes + touched > foot || wsum >= wtarget)) break;
+          }
           bytes += touched;
           wsum += (int64_t)wq;
           ++c;
         }
         gstart.push_back(q);
         gcount.push_back(c);
+        grows.push_back(rows);
+        if (hashed) max_hrows = std::max(max_hrows, rows);
+        else G = std::max(G, c);
         q += c;
       }
     }
     const int64_t ngroups = (int64_t)gstart.size();
-    int64_t G = 0;
-    for (int64_t g = 0; g < ngroups; ++g) G = std::max(G, gcount[g]);
     // heavy nodes in processing order, prefix of their degrees (slots),
     // and prefix of their wedge counts (W(x), summed over the node's slots)
     std::vector<int32_t> gx(n_t3);
@@ -446,55 +479,90 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     }
     const int64_t nslots = hs[n_t3];
     int32_t* d_gx;
-    int64_t *d_hs, *d_sc, *d_wp;
-    uint32_t* dense;
+    int64_t *d_hs, *d_sc, *d_wp, *d_hoff = nullptr;
+    uint8_t* d_hlog = nullptr;
+    int32_t* hkeys = nullptr;
+    uint32_t* dense = nullptr;
+    uint32_t* hcnt = nullptr;
     TG_HIP(S.get(&d_gx, n_t3));
     TG_HIP(S.get(&d_hs, n_t3 + 1));
     TG_HIP(S.get(&d_sc, nslots));
     TG_HIP(S.get(&d_wp, nslots + 1));
-    TG_HIP(S.get(&dense, G * stride));
     TG_HIP(hipMemcpyAsync(d_gx, gx.data(), n_t3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
     TG_HIP(hipMemcpyAsync(d_hs, hs.data(), (n_t3 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    if (G > 0) {
+      TG_HIP(S.get(&dense, G * stride));
+      k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
+      TG_LAUNCHED("k_fill_u32");
+    }
+    if (max_hrows > 0) {
+      TG_HIP(S.get(&d_hoff, n_t3));
+      TG_HIP(S.get(&d_hlog, n_t3));
+      TG_HIP(S.get(&hkeys, max_hrows));
+      TG_HIP(S.get(&hcnt, max_hrows * RW));
+      TG_HIP(hipMemcpyAsync(d_hoff, hoff.data(), n_t3 * sizeof(int64_t), hipMemcpyHostToDevice, st));
+      TG_HIP(hipMemcpyAsync(d_hlog, hlog.data(), n_t3 * sizeof(uint8_t), hipMemcpyHostToDevice, st));
+      k_fill_u32<<<grid_for(max_hrows, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(hkeys), max_hrows,
+                                                                  0xffffffffu);
+      k_fill_u32<<<grid_for(max_hrows * RW, 256, 16384), 256, 0, st>>>(hcnt, max_hrows * RW, 0);
+      TG_LAUNCHED("k_fill_u32");
+    }
     k_c4_slot_wedges<<<grid_for(nslots, 256, 16384), 256, 0, st>>>(nslots, n_t3, d_gx, d_hs, rp, ci, W.deg, d_sc);
     TG_LAUNCHED("k_c4_slot_wedges");
     if (tg_status s2 = scan(S, st, nslots, (const int64_t*)d_sc, d_wp)) return s2;
-    k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
-    TG_LAUNCHED("k_fill_u32");
+    const size_t xu_lds = (size_t)4 * TG_WAVE * P * sizeof(uint32_t);
     for (int64_t g = 0; g < ngroups; ++g) {
       const int Gg = (int)gcount[g];
       const int64_t q0 = gstart[g];
+      const bool hashed = q0 >= qd;
       const int64_t W0 = hwp[q0], Wn = hwp[q0 + Gg] - W0;
       if (Wn == 0) continue;
       int64_t ch = CH;
       while ((Wn + ch - 1) / ch > (1ll << 24)) ch *= 2;
       const unsigned grid = grid_for((Wn + ch - 1) / ch, 4);
-      // the group's nodes, slot prefix (global base) and wedge prefix
+      // the group's nodes, slot prefix (global base), wedge prefix and
+      // (hashed groups) table offsets and sizes
       const int32_t* gxg = d_gx + q0;
       const int64_t* gsl = d_hs + q0;
       const int64_t* wpg = d_wp + hs[q0];
-      // clearing by a fill of the group's rows when that is cheaper than a
-      // second walk over its wedges
-      const bool fill_clear = Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 32;
-      const size_t xu_lds = (size_t)4 * TG_WAVE * P * sizeof(uint32_t);
-#define TG_C4_GROUP(PH, T, HF, C4P, STG)                                                                           \
-  k_c4_group<PH, T, HF><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(Gg, gxg, gsl, wpg, W0, Wn, (int)ch, dense, stride, RW, rp, ci, W.deg, ty, \
-                                              L, W.s2e, C4P, STG)
-#define TG_C4_PHASES(T, HF, C4P, STG)                                                   \
-  do {                                                                                  \
-    TG_C4_GROUP(0, T, HF, C4P, STG);                                                    \
-    TG_C4_GROUP(1, T, HF, C4P, STG);                                                    \
-    if (fill_clear)                                                                     \
-      k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0); \
-    else                                                                                \
-      TG_C4_GROUP(2, T, HF, C4P, STG);                                                  \
+      const int64_t* hog = hashed ? d_hoff + q0 : nullptr;
+      const uint8_t* hlg = hashed ? d_hlog + q0 : nullptr;
+      uint32_t* cnt_base = hashed ? hcnt : dense;
+      const int64_t rows = grows[g];
+      // dense groups are cleared by a fill when that is cheaper than a second
+      // walk over their wedges; hashed groups always by a fill of their rows
+      const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 32;
+#define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
+  k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
+      Gg, gxg, gsl, wpg, W0, Wn, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, W.s2e, C4P, \
+      STG)
+#define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
+  do {                                                                                                             \
+    TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
+    TG_C4_GROUP(1, T, HF, HS, C4P, STG);                                                                           \
+    if (HS) {                                                                                                      \
+      k_fill_u32<<<grid_for(rows, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(hkeys), rows,             \
+                                                             0xffffffffu);                                         \
+      k_fill_u32<<<grid_for(rows * RW, 256, 16384), 256, 0, st>>>(hcnt, rows * RW, 0);                             \
+    } else if (fill_clear) {                                                                                       \
+      k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0);                        \
+    } else {                                                                                                       \
+      TG_C4_GROUP(2, T, HF, HS, C4P, STG);                                                                         \
+    }                                                                                                              \
   } while (0)
-      if (c4_wide) {
-        if (half) TG_C4_PHASES(uint64_t, true, W.C4, 0);
-        else TG_C4_PHASES(uint64_t, false, W.C4, 0);
-      } else {
-        if (half) TG_C4_PHASES(uint32_t, true, C4n, stage_xu);
-        else TG_C4_PHASES(uint32_t, false, C4n, stage_xu);
-      }
+#define TG_C4_ALL(HS)                                                  \
+  do {                                                                 \
+    if (c4_wide) {                                                     \
+      if (half) TG_C4_PHASES(uint64_t, true, HS, W.C4, 0);             \
+      else TG_C4_PHASES(uint64_t, false, HS, W.C4, 0);                 \
+    } else {                                                           \
+      if (half) TG_C4_PHASES(uint32_t, true, HS, C4n, stage_xu);       \
+      else TG_C4_PHASES(uint32_t, false, HS, C4n, stage_xu);           \
+    }                                                                  \
+  } while (0)
+      if (hashed) TG_C4_ALL(true);
+      else TG_C4_ALL(false);
+#undef TG_C4_ALL
 #undef TG_C4_PHASES
 #undef TG_C4_GROUP
       TG_LAUNCHED("k_c4_group");
@@ -978,6 +1046,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_footprint_mb = 192;
   t->c4_group_kwedges = 4096;
   t->c4_chunk = 1024;
+  t->c4_hash_ratio = 0;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }
@@ -1240,6 +1309,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
   axes.push_back({&t.c4_footprint_mb, {64, 192, 1024}});
   axes.push_back({&t.c4_group_kwedges, {1024, 4096, 16384}});
   axes.push_back({&t.c4_chunk, {256, 1024, 4096}});
+  axes.push_back({&t.c4_hash_ratio, {0, 4, 16}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

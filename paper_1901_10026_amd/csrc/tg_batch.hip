@@ -190,30 +190,31 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
         acc_add(acc, key_of(L, 1, pi, pj, u, 0), 2 * (int64_t)nT[u]);
 #pragma unroll
         for (int t = 0; t <= u; ++t) {
-          const int64_t Sit = nSi[t], Siu = nSi[u], Sjt = nSj[t], Sju = nSj[u], Tt = nT[t], Tu = nT[u];
-          int64_t p4, p5, p9, p11;
+          // every per-edge quantity of a graph of at most 512 nodes fits 32 bits
+          const int32_t Sit = nSi[t], Siu = nSi[u], Sjt = nSj[t], Sju = nSj[u], Tt = nT[t], Tu = nT[u];
+          int32_t p4, p5, p9, p11;
           if (t == u) {
             p4 = Sit * Sjt;
-            p5 = c2(Sit) + c2(Sjt);
+            p5 = Sit * (Sit - 1) / 2 + Sjt * (Sjt - 1) / 2;
             p9 = Tt * (Sit + Sjt);
-            p11 = c2(Tt);
+            p11 = Tt * (Tt - 1) / 2;
           } else {
             p4 = Sit * Sju + Siu * Sjt;
             p5 = Sit * Siu + Sjt * Sju;
             p9 = Tt * (Siu + Sju) + Tu * (Sit + Sjt);
             p11 = Tt * Tu;
           }
-          acc_add(acc, key_of(L, 2, pi, pj, t, u), 2 * p4);
-          acc_add(acc, key_of(L, 3, pi, pj, t, u), 2 * p5);
-          acc_add(acc, key_of(L, 5, pi, pj, t, u), 2 * p9);
-          acc_add(acc, key_of(L, 6, pi, pj, t, u), 2 * p11);
+          acc_add(acc, key_of(L, 2, pi, pj, t, u), 2 * (int64_t)p4);
+          acc_add(acc, key_of(L, 3, pi, pj, t, u), 2 * (int64_t)p5);
+          acc_add(acc, key_of(L, 5, pi, pj, t, u), 2 * (int64_t)p9);
+          acc_add(acc, key_of(L, 6, pi, pj, t, u), 2 * (int64_t)p11);
         }
       }
       // explicit orbits, one type t of k at a time
 #pragma unroll
       for (int t = 0; t < TG_BATCH_LMAX; ++t) {
         if (t >= L) continue;
-        int64_t r3[TG_BATCH_LMAX], r6[TG_BATCH_LMAX], r7[TG_BATCH_LMAX], r8[TG_BATCH_LMAX], r10[TG_BATCH_LMAX],
+        int32_t r3[TG_BATCH_LMAX], r6[TG_BATCH_LMAX], r7[TG_BATCH_LMAX], r8[TG_BATCH_LMAX], r10[TG_BATCH_LMAX],
             r12[TG_BATCH_LMAX];
 #pragma unroll
         for (int u = 0; u < TG_BATCH_LMAX; ++u) r3[u] = r6[u] = r7[u] = r8[u] = r10[u] = r12[u] = 0;
@@ -242,18 +243,18 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
             typed_popc<W_MAX>(xSj, S.seg, W, L, cSj);
 #pragma unroll
             for (int u = 0; u < TG_BATCH_LMAX; ++u) {
-              const int64_t dku = S.deg_t[k][u];
+              const int32_t dku = S.deg_t[k][u];
               if (cls == 0) {
-                const int64_t cI = dku - (pi == u) - (pj == u) - cT[u] - cSi[u] - cSj[u];
+                const int32_t cI = dku - (pi == u) - (pj == u) - cT[u] - cSi[u] - cSj[u];
                 r12[u] += cT[u];
                 r10[u] += cSi[u] + cSj[u];
                 r8[u] += cI;
               } else if (cls == 1) {
-                const int64_t cI = dku - (pi == u) - cT[u] - cSi[u] - cSj[u];
+                const int32_t cI = dku - (pi == u) - cT[u] - cSi[u] - cSj[u];
                 r7[u] += cSi[u];
                 r3[u] += cI;
               } else {
-                const int64_t cI = dku - (pj == u) - cT[u] - cSi[u] - cSj[u];
+                const int32_t cI = dku - (pj == u) - cT[u] - cSi[u] - cSj[u];
                 r7[u] += cSj[u];
                 r6[u] += cSi[u];
                 r3[u] += cI;
@@ -268,12 +269,12 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
           if (u >= L) continue;
           // h3 = g3 + g4, g4 = p4 - g6; h4 = g5 = p5 - g7; h5 = g6;
           // h6 = g7 + g8 + g9, g9 = p9 - g10; h7 = g10 + g11, g11 = p11 - g12; h8 = g12
-          acc_add(acc, key_of(L, 2, pi, pj, t, u), 2 * (r3[u] - r6[u]));
-          acc_add(acc, key_of(L, 3, pi, pj, t, u), -r7[u]);
-          acc_add(acc, key_of(L, 4, pi, pj, t, u), 2 * r6[u]);
-          acc_add(acc, key_of(L, 5, pi, pj, t, u), r7[u] + 2 * (r8[u] - r10[u]));
-          acc_add(acc, key_of(L, 6, pi, pj, t, u), 2 * r10[u] - r12[u]);
-          acc_add(acc, key_of(L, 7, pi, pj, t, u), r12[u]);
+          acc_add(acc, key_of(L, 2, pi, pj, t, u), 2 * (int64_t)(r3[u] - r6[u]));
+          acc_add(acc, key_of(L, 3, pi, pj, t, u), -(int64_t)r7[u]);
+          acc_add(acc, key_of(L, 4, pi, pj, t, u), 2 * (int64_t)r6[u]);
+          acc_add(acc, key_of(L, 5, pi, pj, t, u), (int64_t)r7[u] + 2 * (int64_t)(r8[u] - r10[u]));
+          acc_add(acc, key_of(L, 6, pi, pj, t, u), 2 * (int64_t)r10[u] - r12[u]);
+          acc_add(acc, key_of(L, 7, pi, pj, t, u), (int64_t)r12[u]);
         }
       }
     }

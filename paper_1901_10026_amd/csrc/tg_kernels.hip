@@ -472,11 +472,16 @@ __global__ void k_c4_slot_wedges(int64_t nslots, int64_t nnodes, const int32_t* 
   }
 }
 
-template <int PHASE, class C4T, bool HALF>
+// HASH: instead of a dense array per node, node gi of the group has an
+// open-addressing table of 2^hlog[gi] rows starting at row hoff[gi], keyed by
+// w in hkeys (-1 = empty), for nodes whose far ends are few compared with n.
+template <int PHASE, class C4T, bool HALF, bool HASH>
 __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restrict__ gx,
                                                   const int64_t* __restrict__ gslot, const int64_t* __restrict__ wp,
                                                   int64_t W0, int64_t Wn, int CH, uint32_t* __restrict__ dense,
-                                                  int64_t stride, int RW, const int32_t* __restrict__ rp,
+                                                  int64_t stride, int RW, const int64_t* __restrict__ hoff,
+                                                  const uint8_t* __restrict__ hlog, int32_t* __restrict__ hkeys,
+                                                  const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
@@ -575,7 +580,28 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         const int32_t o_exu = __shfl(e_xu, o, TG_WAVE);
         const int32_t w = wv[k], suw = sv[k];
         if (!ok[k] || !precedes(dw[k], w, o_dx, o_x)) continue;
-        uint32_t* row = dense + (int64_t)o_gi * stride + (int64_t)w * RW;
+        uint32_t* row;
+        if (HASH) {
+          const int64_t hb = hoff[o_gi];
+          const int hl = hlog[o_gi];
+          int32_t* keys = hkeys + hb;
+          const uint32_t mask = (1u << hl) - 1u;
+          uint32_t h = ((uint32_t)w * 2654435761u) >> (32 - hl);
+          if (PHASE == 0) {
+            for (;;) {
+              const int32_t old = atomicCAS(&keys[h], -1, w);
+              if (old == -1 || old == w) break;
+              h = (h + 1) & mask;
+            }
+          } else {
+            int32_t kk;
+            while ((kk = keys[h]) != w && kk != -1) h = (h + 1) & mask;
+            if (kk != w) continue;  // not reached: phase 0 inserted every far end
+          }
+          row = dense + (hb + h) * RW;
+        } else {
+          row = dense + (int64_t)o_gi * stride + (int64_t)w * RW;
+        }
         if (PHASE == 0) {
           if (HALF) atomicAdd(&row[o_phu >> 1], 1u << ((o_phu & 1) << 4));
           else atomicAdd(&row[o_phu], 1u);
