@@ -117,6 +117,11 @@ typedef struct {
   float* phase_ms;             /* host, TG_NUM_PHASES floats, or NULL: when set, the call records
                                   HIP events on `stream` around each phase, synchronises at the end
                                   and stores each phase's elapsed milliseconds */
+  const int64_t* edge_ids;     /* device, strictly increasing canonical edge ids in [0, m), or NULL.
+                                  When set, rows (and endpoints) are written for these edges only,
+                                  entry q for edge edge_ids[q], and edge_begin/edge_end are ignored:
+                                  a sample of a graph whose rows would not fit in memory */
+  int64_t num_edge_ids;        /* length of edge_ids */
 } tg_options;
 
 /* Phases timed through tg_options.phase_ms. */
@@ -161,12 +166,21 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
  *   col_idx         device, int32[nnz]
  *   node_types      device, uint8[n]
  *   L               number of node types, 1..16
- *   global_counts   device, uint64[tg_num_keys(L)]; always written
- *   edge_counts     device, uint64[(edge_end-edge_begin) * R(L)], or NULL for
- *                   global counts only
- *   edge_endpoints  device, int32[(edge_end-edge_begin) * 2] receiving (i, j)
- *                   with i < j of each canonical edge in range, or NULL
+ *   global_counts   device, uint64[tg_num_keys(L)], or NULL when edge_counts
+ *                   is given: then only the edges whose rows are asked for
+ *                   go through the per-edge step (the 4-cycle pass still
+ *                   covers the whole graph), for graphs too large to count
+ *                   in full
+ *   edge_counts     device, uint64[E * R(L)], or NULL for global counts only;
+ *                   E = edge_end - edge_begin, or num_edge_ids when
+ *                   opt->edge_ids is set
+ *   edge_endpoints  device, int32[E * 2] receiving (i, j) with i < j of each
+ *                   canonical edge in range (or listed), or NULL
  *   opt             host, or NULL for defaults
+ * Canonical edge ids number the edges (i, j), i < j, in (i, j) order.
+ * Errors: TG_ERR_INVALID_ARG for a bad edge range, an edge_ids array that
+ * is not strictly increasing inside [0, m), or neither output given (nothing
+ * written).
  */
 tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,

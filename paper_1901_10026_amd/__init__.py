@@ -92,7 +92,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("model", ctypes.c_void_p), ("tuning", ctypes.c_void_p),
                 ("validate", ctypes.c_int),
                 ("check", ctypes.c_int), ("edge_begin", ctypes.c_int64), ("edge_end", ctypes.c_int64),
-                ("phase_ms", ctypes.c_void_p)]
+                ("phase_ms", ctypes.c_void_p), ("edge_ids", ctypes.c_void_p), ("num_edge_ids", ctypes.c_int64)]
 
 
 PHASES = ("prep", "tau", "tables", "schedule", "cycles", "combine", "finalize")
@@ -200,13 +200,18 @@ def _stream_handle(torch, device):
 
 
 def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedule="degree", validate=False,
-          check=True, edge_range=None, model=None, out_global=None, out_edges=None, phase_ms=None, tuning=None):
+          check=True, edge_range=None, edge_ids=None, global_counts=True, model=None, out_global=None, out_edges=None,
+          phase_ms=None, tuning=None):
     """Counts every typed 3/4-node graphlet of one graph with tg_count.
 
     row_ptr, col_idx (int32) and types (uint8) are CUDA (HIP) tensors on the
     same device.  Returns (global uint64 [K(L)], per-edge uint64 [E, R(L)] or
     None, endpoints int32 [E, 2] or None) as torch tensors; uint64 results are
-    stored in torch.uint64 tensors.
+    stored in torch.uint64 tensors.  Rows cover the canonical edges in
+    edge_range (default all), or, when edge_ids (a strictly increasing int64
+    device tensor of canonical edge ids) is given, exactly those edges.
+    With global_counts=False (rows only) the global result is None and only
+    those edges go through the per-edge step.
     """
     import torch
     dev = row_ptr.device
@@ -219,11 +224,19 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     nnz = col_idx.numel()
     m = nnz // 2
     e0, e1 = (0, m) if edge_range is None else (int(edge_range[0]), int(edge_range[1]))
+    if edge_ids is not None:
+        if edge_ids.dtype != torch.int64 or not edge_ids.is_contiguous() or edge_ids.device != dev:
+            raise ValueError("edge_ids must be a contiguous int64 tensor on the inputs' device")
+        e0, e1 = 0, edge_ids.numel()
     K = num_keys(L)
     R = edge_row_width(L)
     if K == 0:
         raise TGError(4, "L must be in [1, 16]")
-    g = out_global if out_global is not None else torch.empty(K, dtype=torch.uint64, device=dev)
+    if not global_counts and not per_edge:
+        raise ValueError("rows-only counting needs per_edge=True")
+    g = None
+    if global_counts:
+        g = out_global if out_global is not None else torch.empty(K, dtype=torch.uint64, device=dev)
     rows = None
     if per_edge:
         rows = out_edges if out_edges is not None else torch.empty((max(e1 - e0, 0), R), dtype=torch.uint64,
@@ -240,8 +253,13 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     opt.edge_end = e1
     times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
     opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    if edge_ids is not None:
+        opt.edge_ids = edge_ids.data_ptr() if edge_ids.numel() else None
+        opt.num_edge_ids = edge_ids.numel()
+        if not edge_ids.numel():
+            opt.edge_begin, opt.edge_end = 0, 0
     st = lib().tg_count(n, nnz, row_ptr.data_ptr(), col_idx.data_ptr() if nnz else None,
-                        types.data_ptr() if n else None, L, g.data_ptr(),
+                        types.data_ptr() if n else None, L, g.data_ptr() if g is not None else None,
                         rows.data_ptr() if rows is not None and rows.numel() else None,
                         ends.data_ptr() if ends is not None and ends.numel() else None,
                         ctypes.byref(opt), _stream_handle(torch, dev))

@@ -261,7 +261,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31))
     return fail(TG_ERR_INVALID_ARG, "n and nnz must be in [0, 2^31)");
   if (n * (int64_t)L >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "n * L must be below 2^31");
-  if (!rp || !global_counts || (nnz > 0 && !ci) || (n > 0 && !ty))
+  if (!rp || (!global_counts && !edge_counts) || (nnz > 0 && !ci) || (n > 0 && !ty))
     return fail(TG_ERR_INVALID_ARG, "null input or output pointer");
   if (nnz % 2) return fail(TG_ERR_INVALID_GRAPH, "nnz is odd: some edge is stored in one direction only");
   if (opt.schedule < TG_SCHED_NONE || opt.schedule > TG_SCHED_LEARNED)
@@ -272,12 +272,33 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   const int64_t eb = opt.edge_begin, ee = opt.edge_end < 0 ? m : opt.edge_end;
   if (eb < 0 || eb > ee || ee > m) return fail(TG_ERR_INVALID_ARG, "edge range outside [0, m]");
   const int64_t K = nkeys(L), P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
+  if (opt.edge_ids && opt.num_edge_ids < 0) return fail(TG_ERR_INVALID_ARG, "negative num_edge_ids");
+  const int64_t* ids = (opt.edge_ids && opt.num_edge_ids > 0) ? opt.edge_ids : nullptr;
+  const int64_t nids = ids ? opt.num_edge_ids : 0;
   keep_pool_cached();
   Scratch S(st);
+  if (ids) {
+    int32_t* bad;
+    TG_HIP(S.get(&bad, 1));
+    TG_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    k_check_ids<<<grid_for(nids, 256, 4096), 256, 0, st>>>(ids, nids, m, bad);
+    TG_LAUNCHED("k_check_ids");
+    int32_t hb = 0;
+    TG_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (hb) return fail(TG_ERR_INVALID_ARG, "edge_ids must be strictly increasing canonical edge ids in [0, m)");
+  }
   PhaseTimer timer(st, opt.phase_ms);
 
-  k_fill_u64<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, K, 0);
-  TG_LAUNCHED("k_fill_u64");
+  if (global_counts) {
+    k_fill_u64<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, K, 0);
+    TG_LAUNCHED("k_fill_u64");
+  }
+  // without global counts only the edges whose rows are asked for go through
+  // the per-edge combine (the 4-cycle pass still covers the whole graph)
+  const int64_t* sel = global_counts ? nullptr : ids;
+  const int64_t sel_e0 = (global_counts || ids) ? 0 : eb;
+  const int64_t sel_count = global_counts ? m : (ids ? nids : ee - eb);
   if (opt.validate && n > 0) {
     tg_status vs = validate_graph(S, st, n, nnz, rp, ci, ty, L);
     if (vs != TG_OK) return vs;
@@ -316,8 +337,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // [264] max |T| of workgroup-class edges, [272] divisibility flag
   int32_t* cnt = W.counters;
   TG_HIP(hipMemsetAsync(cnt, 0, 512 * sizeof(int32_t), st));
-  k_edge_bin_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
-                                                           (uint32_t*)(cnt + 264));
+  k_edge_bin_count<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
+                                                                   W.tau, L, bp, pred, cnt, (uint32_t*)(cnt + 264));
   TG_LAUNCHED("k_edge_bin_count");
   k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256);
   TG_LAUNCHED("k_node_tier_count");
@@ -342,8 +363,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   const bool c4_wide = (max_deg - 1) * (max_deg - 1) >= (1ll << 32);
   const int stage_xu = (!c4_wide && L <= 8) ? 1 : 0;
   TG_HIP(hipMemcpyAsync(cnt, cur, 264 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  k_edge_bin_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.tau, L, bp, pred, cnt,
-                                                             W.elist);
+  k_edge_bin_scatter<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
+                                                                     W.tau, L, bp, pred, cnt, W.elist);
   TG_LAUNCHED("k_edge_bin_scatter");
   k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256, W.nlist);
   TG_LAUNCHED("k_node_tier_scatter");
@@ -577,7 +598,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
-  A.gacc_in_lds = K <= TG_GACC_MAX_KEYS ? 1 : 0;
+  A.edge_ids = ids; A.n_edge_ids = nids;
+  A.gacc_in_lds = (global_counts && K <= TG_GACC_MAX_KEYS) ? 1 : 0;
   A.work = nullptr;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
   // gathered accumulators of one batch of edges (reused by every class and
@@ -619,9 +641,14 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   timer.mark(TG_PHASE_FINALIZE);
   int32_t* flag = cnt + 272;
   TG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-  k_finalize<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, L, flag);
-  TG_LAUNCHED("k_finalize");
-  if (edge_endpoints && ee > eb) {
+  if (global_counts) {
+    k_finalize<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, L, flag);
+    TG_LAUNCHED("k_finalize");
+  }
+  if (edge_endpoints && ids) {
+    k_copy_endpoints_ids<<<grid_for(nids, 256, 8192), 256, 0, st>>>(ids, nids, W.ei, W.ej, edge_endpoints);
+    TG_LAUNCHED("k_copy_endpoints_ids");
+  } else if (edge_endpoints && ee > eb) {
     k_copy_endpoints<<<grid_for(ee - eb, 256, 8192), 256, 0, st>>>(eb, ee, W.ei, W.ej, edge_endpoints);
     TG_LAUNCHED("k_copy_endpoints");
   }
@@ -882,6 +909,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
   A.c4_wide = 1;
   A.edge_counts = nullptr; A.edge_begin = 0; A.edge_end = 0; A.global_sums = gsink;
+  A.edge_ids = nullptr; A.n_edge_ids = 0;
   A.gacc_in_lds = 0;
   A.work = work_by_edge;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
@@ -1034,6 +1062,8 @@ void tg_options_default(tg_options* opt) {
   opt->edge_begin = 0;
   opt->edge_end = -1;
   opt->phase_ms = nullptr;
+  opt->edge_ids = nullptr;
+  opt->num_edge_ids = 0;
 }
 
 void tg_tuning_default(tg_tuning* t) {
@@ -1046,7 +1076,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_footprint_mb = 192;
   t->c4_group_kwedges = 4096;
   t->c4_chunk = 1024;
-  t->c4_hash_ratio = 0;
+  t->c4_hash_ratio = 2;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }

@@ -281,12 +281,23 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
   const uint64_t* Uj = A.Un + (int64_t)j * LL;
   const uint64_t* Pi = A.Pn + (int64_t)i * LL;
   const uint64_t* Pj = A.Pn + (int64_t)j * LL;
-  uint64_t* row = (A.edge_counts && e >= A.edge_begin && e < A.edge_end)
-                      ? A.edge_counts + (int64_t)(e - A.edge_begin) * R : nullptr;
+  uint64_t* row = nullptr;
+  if (A.edge_counts) {
+    if (A.edge_ids) {
+      int64_t lo = 0, hi = A.n_edge_ids;  // first id >= e
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (A.edge_ids[mid] < e) lo = mid + 1; else hi = mid;
+      }
+      if (lo < A.n_edge_ids && A.edge_ids[lo] == e) row = A.edge_counts + lo * R;
+    } else if (e >= A.edge_begin && e < A.edge_end) {
+      row = A.edge_counts + (int64_t)(e - A.edge_begin) * R;
+    }
+  }
   auto gadd = [&](int64_t key, int64_t v) {
     if (v == 0) return;
     if (gacc) atomicAdd((unsigned long long*)&gacc[key], (unsigned long long)v);
-    else atomicAdd((unsigned long long*)&A.global_sums[key], (unsigned long long)v);
+    else if (A.global_sums) atomicAdd((unsigned long long*)&A.global_sums[key], (unsigned long long)v);
   };
   auto Tn = [&](int x) -> int64_t { return (int64_t)tau_e[x]; };
   auto Si = [&](int x) -> int64_t { return (int64_t)Di[x] - tau_e[x] - (pj == x ? 1 : 0); };

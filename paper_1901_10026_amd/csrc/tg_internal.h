@@ -76,8 +76,10 @@ struct EdgeArgs {
   const uint32_t* C4n;    // 32-bit ones
   int c4_wide;
   int L;
-  uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or null
+  uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or for edge_ids, or null
   int64_t edge_begin, edge_end;
+  const int64_t* edge_ids;  // sorted sample of edges whose rows are written, or null
+  int64_t n_edge_ids;
   uint64_t* global_sums;  // K(L)
   int gacc_in_lds;
   uint64_t* work;         // null, or per-edge element-visit counts (added atomically, by edge id)

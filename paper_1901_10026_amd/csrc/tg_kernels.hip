@@ -694,7 +694,9 @@ __device__ __forceinline__ void edge_bin(int32_t e, const int32_t* ei, const int
 
 // Bin counts and scatter use a per-workgroup LDS histogram so that global
 // atomics are one per (workgroup tile, bin) rather than one per item.
-__global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t* __restrict__ ei,
+// Both passes bin the edges e = sel[q] (sel given) or e = e0 + q, q < count.
+__global__ void __launch_bounds__(256) k_edge_bin_count(int64_t count, const int64_t* __restrict__ sel, int64_t e0,
+                                                        const int32_t* __restrict__ ei,
                                                         const int32_t* __restrict__ ej,
                                                         const int32_t* __restrict__ deg,
                                                         const uint32_t* __restrict__ tau, int L, BinParams bp,
@@ -705,7 +707,8 @@ __global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t
   for (int q = threadIdx.x; q < 192; q += blockDim.x) h[q] = 0;
   if (threadIdx.x == 0) tmax = 0;
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = sel ? sel[q] : e0 + q;
     int cls, bucket;
     uint32_t tsum;
     edge_bin((int32_t)e, ei, ej, deg, tau, L, bp, pred, &cls, &bucket, &tsum);
@@ -718,7 +721,8 @@ __global__ void __launch_bounds__(256) k_edge_bin_count(int64_t m, const int32_t
   if (threadIdx.x == 0 && tmax) atomicMax(max_t_heavy, tmax);
 }
 
-__global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32_t* __restrict__ ei,
+__global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t count, const int64_t* __restrict__ sel,
+                                                          int64_t e0, const int32_t* __restrict__ ei,
                                                           const int32_t* __restrict__ ej,
                                                           const int32_t* __restrict__ deg,
                                                           const uint32_t* __restrict__ tau, int L, BinParams bp,
@@ -726,12 +730,13 @@ __global__ void __launch_bounds__(256) k_edge_bin_scatter(int64_t m, const int32
                                                           int32_t* __restrict__ cursor, int32_t* __restrict__ list) {
   __shared__ int32_t h[192];
   __shared__ int32_t base[192];
-  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < m; t0 += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < count; t0 += (int64_t)gridDim.x * blockDim.x) {
     for (int q = threadIdx.x; q < 192; q += blockDim.x) h[q] = 0;
     __syncthreads();
-    const int64_t e = t0 + threadIdx.x;
+    const int64_t qe = t0 + threadIdx.x;
+    const int64_t e = qe < count ? (sel ? sel[qe] : e0 + qe) : 0;
     int bin = -1, local = 0;
-    if (e < m) {
+    if (qe < count) {
       int cls, bucket;
       uint32_t tsum;
       edge_bin((int32_t)e, ei, ej, deg, tau, L, bp, pred, &cls, &bucket, &tsum);
@@ -819,6 +824,22 @@ __global__ void k_finalize(uint64_t* __restrict__ g, int L, int32_t* __restrict_
     const uint64_t v = g[k];
     if (v % d) atomicOr(flag, 1);
     g[k] = v / d;
+  }
+}
+
+// Listed edges: strictly increasing ids inside [0, m), else *bad = 1.
+__global__ void k_check_ids(const int64_t* __restrict__ ids, int64_t k, int64_t m, int32_t* __restrict__ bad) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < k; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = ids[q];
+    if (e < 0 || e >= m || (q > 0 && ids[q - 1] >= e)) *bad = 1;
+  }
+}
+
+__global__ void k_copy_endpoints_ids(const int64_t* __restrict__ ids, int64_t k, const int32_t* __restrict__ ei,
+                                     const int32_t* __restrict__ ej, int32_t* __restrict__ out) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < k; q += (int64_t)gridDim.x * blockDim.x) {
+    out[2 * q] = ei[ids[q]];
+    out[2 * q + 1] = ej[ids[q]];
   }
 }
 

@@ -27,7 +27,7 @@ def gpu_count(row_ptr, col_idx, types, L, per_edge=True, **kw):
     rp, ci, ty = to_dev(row_ptr, col_idx, types)
     g, rows, ends = tg.count(rp, ci, ty, L, per_edge=per_edge, **kw)
     torch.cuda.synchronize()
-    g = g.cpu().numpy().view(np.uint64)
+    g = g.cpu().numpy().view(np.uint64) if g is not None else None
     rows = rows.cpu().numpy().view(np.uint64) if rows is not None else None
     ends = ends.cpu().numpy() if ends is not None else None
     return g, rows, ends

@@ -1,0 +1,62 @@
+"""Skewed giant graph (Chung-Lu, 20M nodes, about 274M edges, maximum degree
+about 294k, L=8 Zipf types).  Its per-edge rows do not fit in memory and a
+full count needs about 1.1e14 4-clique probes, so the call counts rows only
+for a stratified edge sample (global_counts=False): the 4-cycle pass covers
+the whole graph, the per-edge step only the sample, and every sampled row
+must equal the oracle's."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from _gpu import note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_edges(d, s, ei, ej, per_decile=6, heaviest=3, budget=4e8, seed=11):
+    """Stratified by degree-product decile, uniform within each decile among
+    edges whose oracle cost (s_i + s_j) fits the budget, plus the heaviest
+    such edges."""
+    cost = d[ei] * d[ej]
+    ocost = s[ei] + s[ej]
+    order = np.argsort(cost, kind="stable")
+    rng = np.random.default_rng(seed)
+    picks = []
+    for part in np.array_split(order, 10):
+        ok = part[ocost[part] <= budget]
+        picks.extend(rng.choice(ok, size=min(per_decile, len(ok)), replace=False))
+    ok = order[ocost[order] <= budget]
+    picks.extend(ok[-heaviest:])
+    return np.unique(np.array(picks, dtype=np.int64))
+
+
+def test_giant_sampled_rows():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.workload("cl-20m")
+    d = np.diff(g.row_ptr).astype(np.int64)
+    note(f"cl-20m n={g.n} m={g.m} L={g.L} max_deg={d.max()}")
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    cs = np.concatenate([[0], np.cumsum(d[g.col_idx])])
+    s = cs[g.row_ptr[1:]] - cs[g.row_ptr[:-1]]  # neighbour degree sums
+    del cs
+    ids = sample_edges(d, s, ei, ej)
+    note(f"sampled {len(ids)} edges")
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    dev_ids = torch.from_numpy(ids).to(rp.device)
+    ph = {}
+    glob, rows, ends = tg.count(rp, ci, ty, g.L, per_edge=True, edge_ids=dev_ids, global_counts=False,
+                                endpoints=True, phase_ms=ph)
+    torch.cuda.synchronize()
+    note("tg_count done: " + " ".join(f"{k}={v:.0f}ms" for k, v in ph.items()))
+    assert glob is None
+    del rp, ci, ty
+    ends = ends.cpu().numpy()
+    assert np.array_equal(ends[:, 0], ei[ids]) and np.array_equal(ends[:, 1], ej[ids])
+    got = rows.cpu().numpy().view(np.uint64)
+    want, _ = oracle.count_edges(g.row_ptr, g.col_idx, g.types, g.L, ei[ids], ej[ids], nthreads=16)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} of {len(ids)} sampled rows differ, first edge {ids[bad[0]]}"
+    note(f"{len(ids)} sampled rows match the oracle")

@@ -65,6 +65,39 @@ def test_edge_ranges_and_global_only():
     assert r3 is None and np.array_equal(g3, gg)
 
 
+def test_edge_id_sample():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    gg, rr, ee = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, endpoints=True)
+    rng = np.random.default_rng(5)
+    ids = np.unique(np.concatenate([[0, g.m - 1], rng.choice(g.m, 300, replace=False)]))
+    dev_ids = torch.from_numpy(ids.astype(np.int64)).to("cuda:0")
+    g2, r2, e2 = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, edge_ids=dev_ids, endpoints=True)
+    assert np.array_equal(g2, gg)
+    assert np.array_equal(r2, rr[ids])
+    assert np.array_equal(e2, ee[ids])
+    for bad in ([5, 5], [7, 3], [-1], [g.m]):
+        with pytest.raises(tg.TGError, match="INVALID_ARG"):
+            gpu_count(g.row_ptr, g.col_idx, g.types, g.L, edge_ids=torch.tensor(bad, dtype=torch.int64,
+                                                                               device="cuda:0"))
+
+
+def test_rows_only_counting():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    ids = np.arange(3, g.m, 37, dtype=np.int64)
+    dev_ids = torch.from_numpy(ids).to("cuda:0")
+    g2, r2, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, edge_ids=dev_ids, global_counts=False)
+    assert g2 is None and np.array_equal(r2, rr[ids])
+    g3, r3, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, edge_range=(100, 1500), global_counts=False)
+    assert g3 is None and np.array_equal(r3, rr[100:1500])
+
+
 @pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5)])
 def test_complete_graphs_hit_heavy_paths(n, L):
     # |T_ij| = n - 2 exceeds one wavefront's capacity for n >= 131, and the
