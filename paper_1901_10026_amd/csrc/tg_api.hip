@@ -361,7 +361,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   const int64_t max_deg = h_cnt[268];
   // 32-bit 4-cycle counters when (d_i - 1)(d_j - 1) < 2^32 on every edge
   const bool c4_wide = (max_deg - 1) * (max_deg - 1) >= (1ll << 32);
-  const int stage_xu = (!c4_wide && L <= 8) ? 1 : 0;
+  // the heavy pass sums the credits of one window's x-side edges in 32-bit
+  // LDS counters (a window holds at most one chunk of wedges, each credit at
+  // most the maximum degree)
   TG_HIP(hipMemcpyAsync(cnt, cur, 264 * sizeof(int32_t), hipMemcpyHostToDevice, st));
   k_edge_bin_scatter<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
                                                                      W.tau, L, bp, pred, cnt, W.elist);
@@ -551,8 +553,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       uint32_t* cnt_base = hashed ? hcnt : dense;
       const int64_t rows = grows[g];
       // dense groups are cleared by a fill when that is cheaper than a second
-      // walk over their wedges; hashed groups always by a fill of their rows
-      const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 32;
+      // walk over their wedges (a streamed byte costs about 1/256 of a walked
+      // wedge); hashed groups always by a fill of their rows
+      const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 256;
+      const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
       Gg, gxg, gsl, wpg, W0, Wn, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, W.s2e, C4P, \
@@ -574,8 +578,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_ALL(HS)                                                  \
   do {                                                                 \
     if (c4_wide) {                                                     \
-      if (half) TG_C4_PHASES(uint64_t, true, HS, W.C4, 0);             \
-      else TG_C4_PHASES(uint64_t, false, HS, W.C4, 0);                 \
+      if (half) TG_C4_PHASES(uint64_t, true, HS, W.C4, stage_xu);      \
+      else TG_C4_PHASES(uint64_t, false, HS, W.C4, stage_xu);          \
     } else {                                                           \
       if (half) TG_C4_PHASES(uint32_t, true, HS, C4n, stage_xu);       \
       else TG_C4_PHASES(uint32_t, false, HS, C4n, stage_xu);           \
