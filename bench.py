@@ -146,6 +146,8 @@ def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=3):
     counts are the same in every case."""
     import torch
     res = {}
+    res["none_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="none")
+    log(f"no cost order: {res['none_ms']:.1f} ms")
     res["degree_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="degree")
     log(f"degree schedule: {res['degree_ms']:.1f} ms")
     t_deg, _ = tg.autotune(rp, ci, ty, g.L, out_g, out_e, schedule="degree")

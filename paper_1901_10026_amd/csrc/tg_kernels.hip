@@ -678,18 +678,21 @@ __device__ __forceinline__ void edge_bin(int32_t e, const int32_t* ei, const int
   int c = 0;
   if (tsum > 256 || dmin > bp.heavy_min_degree) c = 2;
   else if (tsum > 64 || dmin > bp.light_max_degree || !bp.teams16) c = 1;
-  int lg = 0;
+  int fine = 0;
   if (bp.mode != 0) {
-    double cst;
-    if (bp.mode == 1) cst = (double)di * (double)dj;
-    else cst = exp2((double)pred[e]);
-    lg = (int)floor(log2(cst + 1.0));
-    lg = lg < 0 ? 0 : (lg > 63 ? 63 : lg);
+    double l2;
+    if (bp.mode == 1) l2 = log2((double)di * (double)dj + 1.0);
+    else l2 = log2(exp2((double)pred[e]) + 1.0);
+    l2 = l2 < 0.0 ? 0.0 : l2;
+    const int lg = (int)fmin(floor(l2), 63.0);
     if (lg > bp.heavy_log2_cost) c = 2;
     else if (lg > bp.mid_log2_cost && c == 0) c = 1;
+    // buckets of half an octave of cost, so that edges of alike cost share
+    // wavefronts (teams of 16 lanes run four to a wavefront in lockstep)
+    fine = (int)fmin(floor(2.0 * l2), 63.0);
   }
   *cls = c;
-  *bucket = bp.mode == 0 ? 0 : 63 - lg;
+  *bucket = bp.mode == 0 ? 0 : 63 - fine;
 }
 
 // Bin counts and scatter use a per-workgroup LDS histogram so that global

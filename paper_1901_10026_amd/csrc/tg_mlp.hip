@@ -5,11 +5,13 @@
 //
 // Parameter layout (fp32 master copy, NPARAM floats):
 //   W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3[1]
-// Features per edge (i, j), d_lo <= d_hi the endpoint degrees, h[t] the
-// combined neighbour type histogram (D[i][t] + D[j][t]) / (d_i + d_j):
+// Features per edge (i, j), d_lo <= d_hi the endpoint degrees, c[t] the type
+// histogram of the common neighbours (tau_e[t] / |T_ij|, known before any
+// per-edge counting) and h[t] the combined neighbour type histogram
+// (D[i][t] + D[j][t]) / (d_i + d_j), types >= 8 folded onto t mod 8:
 //   0 log2(1+d_lo)  1 log2(1+d_hi)  2 log2(1+d_lo*d_hi)  3 [phi_i == phi_j]
-//   4..11 h[0..7] (types >= 8 folded onto t mod 8)  12 entropy of h (bits)
-//   13 h[phi_i]  14 h[phi_j]  15 log2(1 + max_t (D[i][t] + D[j][t]))
+//   4..11 c[0..7]  12 log2(1 + |T_ij|)  13 entropy of h (bits)
+//   14 h[phi_i]  15 h[phi_j]
 // Features are standardised with the training sample's mean and deviation.
 // Target: log2(1 + work), work = the instrumented element-visit count of the
 // per-edge counting kernel for that edge.
@@ -42,43 +44,46 @@ __device__ __host__ __forceinline__ float bf16_round(float x) {
 
 // ------------------------------------------------------------- features --
 
-__device__ __forceinline__ void edge_features(int32_t i, int32_t j, const int32_t* deg, const uint32_t* D,
-                                              const uint8_t* ty, int L, float f[TG_MLP_IN]) {
+__device__ __forceinline__ void edge_features(int32_t e, int32_t i, int32_t j, const int32_t* deg,
+                                              const uint32_t* D, const uint32_t* tau, const uint8_t* ty, int L,
+                                              float f[TG_MLP_IN]) {
   const float di = (float)deg[i], dj = (float)deg[j];
   const float lo = fminf(di, dj), hi = fmaxf(di, dj);
-  float h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  float mx = 0.0f;
+  float h[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  float nT = 0.0f;
   const float tot = di + dj;
   for (int t = 0; t < L; ++t) {
-    const float c = (float)(D[(int64_t)i * L + t] + D[(int64_t)j * L + t]);
-    h[t & 7] += c;
-    mx = fmaxf(mx, c);
+    h[t & 7] += (float)(D[(int64_t)i * L + t] + D[(int64_t)j * L + t]);
+    const float ct = (float)tau[(int64_t)e * L + t];
+    c[t & 7] += ct;
+    nT += ct;
   }
   float ent = 0.0f;
   for (int t = 0; t < 8; ++t) {
     h[t] = tot > 0 ? h[t] / tot : 0.0f;
+    c[t] = nT > 0 ? c[t] / nT : 0.0f;
     if (h[t] > 0) ent -= h[t] * log2f(h[t]);
   }
   f[0] = log2f(1.0f + lo);
   f[1] = log2f(1.0f + hi);
   f[2] = log2f(1.0f + lo * hi);
   f[3] = ty[i] == ty[j] ? 1.0f : 0.0f;
-  for (int t = 0; t < 8; ++t) f[4 + t] = h[t];
-  f[12] = ent;
-  f[13] = h[ty[i] & 7];
-  f[14] = h[ty[j] & 7];
-  f[15] = log2f(1.0f + mx);
+  for (int t = 0; t < 8; ++t) f[4 + t] = c[t];
+  f[12] = log2f(1.0f + nT);
+  f[13] = ent;
+  f[14] = h[ty[i] & 7];
+  f[15] = h[ty[j] & 7];
 }
 
 // Features of the listed edges (list null: edges 0..count-1).
 __global__ void k_mlp_features(int64_t count, const int32_t* __restrict__ list, const int32_t* __restrict__ ei,
                                const int32_t* __restrict__ ej, const int32_t* __restrict__ deg,
-                               const uint32_t* __restrict__ D, const uint8_t* __restrict__ ty, int L,
-                               float* __restrict__ X) {
+                               const uint32_t* __restrict__ D, const uint32_t* __restrict__ tau,
+                               const uint8_t* __restrict__ ty, int L, float* __restrict__ X) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
     const int32_t e = list ? list[q] : (int32_t)q;
     float f[TG_MLP_IN];
-    edge_features(ei[e], ej[e], deg, D, ty, L, f);
+    edge_features(e, ei[e], ej[e], deg, D, tau, ty, L, f);
     for (int c = 0; c < TG_MLP_IN; ++c) X[q * TG_MLP_IN + c] = f[c];
   }
 }
@@ -137,27 +142,101 @@ __device__ __forceinline__ void load_params_bf16(const uint16_t* __restrict__ Pb
   }
 }
 
-// Predicted log2 cost of the listed rows of X (or of edges when X is null:
-// features are then computed from the graph).
+// Predicted log2 cost of the rows of X (or of edges 0..count-1 when X is
+// null: features are then computed from the graph), on bf16 matrix cores.
+// One wavefront takes 16 rows at a time: layer 1 is [16 x 16] x [16 x 64]
+// (four 16x16x16 MFMAs), layer 2 [16 x 64] x [64 x 64] (sixteen), with the
+// standardised inputs and the first hidden layer rounded to bf16 (weights are
+// bf16 already) and fp32 accumulation; layer 3 is a dot product on the vector
+// ALUs.  Operand layouts of v_mfma_f32_16x16x16_bf16, lane l, r = l % 16,
+// g = l / 16: A holds A[r][4g .. 4g+3], B holds B[4g .. 4g+3][r], and the
+// result holds D[4g .. 4g+3][r].
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short tg_bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float tg_f32x4;
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  const float r = bf16_round(x);
+  uint32_t u;
+  memcpy(&u, &r, 4);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
 __global__ void __launch_bounds__(256) k_mlp_predict(int64_t count, const uint16_t* __restrict__ Pbf,
                                                      const float* __restrict__ stats, const float* __restrict__ X,
                                                      const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
                                                      const int32_t* __restrict__ deg, const uint32_t* __restrict__ D,
-                                                     const uint8_t* __restrict__ ty, int L, float* __restrict__ out) {
-  __shared__ float P[TG_MLP_NPARAM];
-  __shared__ float st[2 * TG_MLP_IN];
-  load_params_bf16(Pbf, P);
-  for (int q = threadIdx.x; q < 2 * TG_MLP_IN; q += blockDim.x) st[q] = stats[q];
-  __syncthreads();
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count; r += (int64_t)gridDim.x * blockDim.x) {
-    float x[TG_MLP_IN], h1[TG_MLP_H], h2[TG_MLP_H];
-    if (X) {
-      for (int c = 0; c < TG_MLP_IN; ++c) x[c] = X[r * TG_MLP_IN + c];
+                                                     const uint32_t* __restrict__ tau, const uint8_t* __restrict__ ty,
+                                                     int L, float* __restrict__ out) {
+  __shared__ short hbuf[4][16 * TG_MLP_H];  // per wavefront: first hidden layer, bf16, row-major
+  const int wib = threadIdx.x / TG_WAVE, l = lane();
+  const int r = l & 15, g = l >> 4;
+  tg_bf16x4 B1[4], B2[4][4];
+  float b1v[4], b2v[4], w3v[4];
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = nt * 16 + r;
+    for (int j = 0; j < 4; ++j) B1[nt][j] = (short)Pbf[n * TG_MLP_IN + 4 * g + j];
+    for (int ks = 0; ks < 4; ++ks)
+      for (int j = 0; j < 4; ++j) B2[ks][nt][j] = (short)Pbf[TG_MLP_OFF_W2 + n * TG_MLP_H + ks * 16 + 4 * g + j];
+    b1v[nt] = bf16_value(Pbf[TG_MLP_OFF_B1 + n]);
+    b2v[nt] = bf16_value(Pbf[TG_MLP_OFF_B2 + n]);
+    w3v[nt] = bf16_value(Pbf[TG_MLP_OFF_W3 + n]);
+  }
+  const float b3 = bf16_value(Pbf[TG_MLP_OFF_B3]);
+  float mean[4], inv[4];
+  for (int j = 0; j < 4; ++j) {
+    mean[j] = stats[4 * g + j];
+    inv[j] = 1.0f / stats[TG_MLP_IN + 4 * g + j];
+  }
+  short* hb = hbuf[wib];
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wib; tile * 16 < count; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row = tile * 16 + r;
+    float f[TG_MLP_IN];
+    if (row < count) {
+      if (X) {
+        for (int c = 0; c < TG_MLP_IN; ++c) f[c] = X[row * TG_MLP_IN + c];
+      } else {
+        edge_features((int32_t)row, ei[row], ej[row], deg, D, tau, ty, L, f);
+      }
     } else {
-      edge_features(ei[r], ej[r], deg, D, ty, L, x);
+      for (int c = 0; c < TG_MLP_IN; ++c) f[c] = 0.0f;
     }
-    for (int c = 0; c < TG_MLP_IN; ++c) x[c] = (x[c] - st[c]) / st[TG_MLP_IN + c];
-    out[r] = mlp_forward_row(P, x, h1, h2);
+    tg_bf16x4 a;
+    for (int j = 0; j < 4; ++j) a[j] = bf16_bits((f[4 * g + j] - mean[j]) * inv[j]);
+    // layer 1, bias, ReLU, bf16 into LDS
+    for (int nt = 0; nt < 4; ++nt) {
+      tg_f32x4 h = {0.0f, 0.0f, 0.0f, 0.0f};
+      h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, B1[nt], h, 0, 0, 0);
+      for (int j = 0; j < 4; ++j) hb[(4 * g + j) * TG_MLP_H + nt * 16 + r] = bf16_bits(fmaxf(h[j] + b1v[nt], 0.0f));
+    }
+    wave_sync();
+    // layer 2
+    tg_f32x4 o[4];
+    for (int nt = 0; nt < 4; ++nt) o[nt] = (tg_f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ks = 0; ks < 4; ++ks) {
+      tg_bf16x4 a2;
+      for (int j = 0; j < 4; ++j) a2[j] = hb[r * TG_MLP_H + ks * 16 + 4 * g + j];
+      for (int nt = 0; nt < 4; ++nt) o[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, B2[ks][nt], o[nt], 0, 0, 0);
+    }
+    wave_sync();
+    // layer 3: rows 4g .. 4g+3, column r of each tile, summed over the 16
+    // lanes of the group
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int nt = 0; nt < 4; ++nt)
+      for (int j = 0; j < 4; ++j) part[j] = fmaf(w3v[nt], fmaxf(o[nt][j] + b2v[nt], 0.0f), part[j]);
+    for (int off = 1; off < 16; off <<= 1)
+      for (int j = 0; j < 4; ++j) part[j] += __shfl_xor(part[j], off, TG_WAVE);
+    if (r == 0)
+      for (int j = 0; j < 4; ++j) {
+        const int64_t orow = tile * 16 + 4 * g + j;
+        if (orow < count) out[orow] = part[j] + b3;
+      }
   }
 }
 

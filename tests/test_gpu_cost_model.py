@@ -110,3 +110,72 @@ def test_save_and_load_round_trip(trained, tmp_path):
     other = tg.CostModel(seed=1)
     other.load(path)
     assert np.array_equal(other.get_params(), model.get_params())
+
+
+def cpu_features(g):
+    """The 16 per-edge features, recomputed in numpy (float32) for every
+    canonical edge: degrees, the common-neighbour type histogram and the
+    combined neighbour type histogram."""
+    rp, ci, ty, L = g.row_ptr.astype(np.int64), g.col_idx, g.types, g.L
+    d = np.diff(rp)
+    Dt = np.zeros((g.n, L), np.int64)
+    for v in range(g.n):
+        np.add.at(Dt[v], ty[ci[rp[v]:rp[v + 1]]], 1)
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    F = np.zeros((len(ei), 16), np.float32)
+    for e, (i, j) in enumerate(zip(ei, ej)):
+        common = np.intersect1d(ci[rp[i]:rp[i + 1]], ci[rp[j]:rp[j + 1]], assume_unique=True)
+        tau = np.bincount(ty[common], minlength=L).astype(np.float32)
+        h8 = np.zeros(8, np.float32)
+        c8 = np.zeros(8, np.float32)
+        for t in range(L):
+            h8[t % 8] += Dt[i, t] + Dt[j, t]
+            c8[t % 8] += tau[t]
+        nT = np.float32(tau.sum())
+        tot = np.float32(d[i] + d[j])
+        h8 = h8 / tot if tot > 0 else h8
+        c8 = c8 / nT if nT > 0 else c8
+        lo, hi = np.float32(min(d[i], d[j])), np.float32(max(d[i], d[j]))
+        nz = h8[h8 > 0]
+        F[e, 0] = np.log2(np.float32(1) + lo)
+        F[e, 1] = np.log2(np.float32(1) + hi)
+        F[e, 2] = np.log2(np.float32(1) + lo * hi)
+        F[e, 3] = 1.0 if ty[i] == ty[j] else 0.0
+        F[e, 4:12] = c8
+        F[e, 12] = np.log2(np.float32(1) + nT)
+        F[e, 13] = -(nz * np.log2(nz)).sum()
+        F[e, 14] = h8[ty[i] % 8]
+        F[e, 15] = h8[ty[j] % 8]
+    return F
+
+
+def test_matrix_core_inference_matches_cpu_forward():
+    """Inference runs on bf16 MFMA tiles with bf16 inputs and first hidden
+    layer: the CPU forward with the same roundings must agree."""
+    import torch
+
+    import paper_1901_10026_amd as tg
+    from oracle import mlp_ref
+    g = graphgen.chung_lu_small()
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    model = tg.CostModel(seed=9)
+    rng = np.random.default_rng(9)
+    P = tg.CostModel.num_params()
+    params = model.get_params()
+    F = cpu_features(g)
+    params[P:P + 16] = F.mean(axis=0)
+    params[P + 16:] = np.maximum(F.std(axis=0), 1e-3)
+    params[:P] += rng.normal(0, 0.1, P).astype(np.float32)
+    model.set_params(params)
+    pred = model.predict(rp, ci, ty, g.L)
+    torch.cuda.synchronize()
+    got = pred.cpu().numpy().astype(np.float64)
+    w = mlp_ref.bf16_round(params[:P]).astype(np.float64)
+    W1, b1, W2, b2, w3, b3 = mlp_ref.unpack(w)
+    x = mlp_ref.bf16_round(((F - params[P:P + 16]) / params[P + 16:]).astype(np.float32)).astype(np.float64)
+    h1 = mlp_ref.bf16_round(np.maximum(x @ W1.T + b1, 0).astype(np.float32)).astype(np.float64)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    want = h2 @ w3 + b3
+    err = np.abs(got - want)
+    note(f"MFMA inference vs CPU: max abs error {err.max():.2e}, scale {np.abs(want).max():.2e}")
+    assert (err <= 1e-2 + 1e-2 * np.abs(want)).all()
