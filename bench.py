@@ -140,10 +140,11 @@ def time_count(tg, g, rp, ci, ty, out_g, out_e, steps, **kw):
     return s0.elapsed_time(s1) / steps
 
 
-def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=3):
-    """Degree-product schedule (default launch shapes), the same autotuned,
-    and the learned schedule (MLP trained on a 1% edge sample) autotuned; the
-    counts are the same in every case."""
+def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=5):
+    """No cost order, the degree-product schedule and the learned schedule
+    (MLP trained on a 1% edge sample), each with the default launch shapes,
+    then degree and learned autotuned; the counts are the same in every
+    case."""
     import torch
     res = {}
     res["none_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="none")
@@ -160,6 +161,8 @@ def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=3):
     hist = model.train(rp, ci, ty, g.L, sample_frac=0.01, seed=56, epochs=15)
     res["mlp_train_ms"] = (time.time() - t0) * 1e3
     res["mlp_loss_first_last"] = [hist[0], hist[-1]]
+    res["learned_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="learned", model=model)
+    log(f"learned schedule: {res['learned_ms']:.1f} ms")
     t_l, _ = tg.autotune(rp, ci, ty, g.L, out_g, out_e, schedule="learned", model=model)
     res["learned_autotuned_ms"] = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="learned",
                                              model=model, tuning=t_l)
