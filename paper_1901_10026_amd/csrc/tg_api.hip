@@ -215,6 +215,8 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   TG_HIP(S.get(&W.ei, m));
   TG_HIP(S.get(&W.ej, m));
   TG_HIP(S.get(&W.s2e, nnz));
+  TG_HIP(S.get(&W.es_lo, m));
+  TG_HIP(S.get(&W.es_hi, m));
   TG_HIP(S.get(&W.out_col, m));
   TG_HIP(S.get(&W.tau, m * L));
   TG_HIP(S.get(&W.Pn, n * LL));
@@ -234,7 +236,7 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
   if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
   k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
-                                               W.s2e, W.out_col);
+                                               W.s2e, W.es_lo, W.es_hi, W.out_col);
   TG_LAUNCHED("k_fill_edges");
 
   // ---- typed triangles per edge, node tables
@@ -373,26 +375,43 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 
   // ---- non-induced typed 4-cycles per edge
   timer.mark(TG_PHASE_CYCLES);
-  k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
-  TG_LAUNCHED("k_fill_u64");
   const int64_t n_t1 = h_cnt[257], n_t2 = h_cnt[258], n_t3 = h_cnt[259];
   uint32_t* C4n = reinterpret_cast<uint32_t*>(W.C4);
+  // Credits go to one row per CSR slot when those rows fit the budget
+  // (consecutive wedges then credit consecutive rows), folded into per-edge
+  // rows afterwards; else straight to per-edge rows.
+  const int64_t c4_width = c4_wide ? 8 : 4;
+  const bool slot_rows = nnz * P * c4_width <= (16ll << 30);
+  const int32_t* s2x = slot_rows ? nullptr : W.s2e;
+  uint64_t* C4w_t = W.C4;
+  uint32_t* C4n_t = C4n;
+  if (slot_rows) {
+    uint64_t* c4s;
+    TG_HIP(S.get(&c4s, (nnz * P * c4_width + 7) / 8));
+    k_fill_u64<<<grid_for((nnz * P * c4_width + 7) / 8, 256, 8192), 256, 0, st>>>(c4s, (nnz * P * c4_width + 7) / 8,
+                                                                                 0);
+    C4w_t = c4s;
+    C4n_t = reinterpret_cast<uint32_t*>(c4s);
+  } else {
+    k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
+  }
+  TG_LAUNCHED("k_fill_u64");
   if (n_t1 > 0) {
     if (c4_wide)
       k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, W.s2e, W.C4);
+                                                                         L, s2x, C4w_t);
     else
       k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, W.s2e, C4n);
+                                                                         L, s2x, C4n_t);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (n_t2 > 0) {
     if (c4_wide)
       k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, W.s2e, W.C4);
+                                                                          ty, L, s2x, C4w_t);
     else
       k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, W.s2e, C4n);
+                                                                          ty, L, s2x, C4n_t);
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -538,7 +557,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const int Gg = (int)gcount[g];
       const int64_t q0 = gstart[g];
       const bool hashed = q0 >= qd;
-      const int64_t W0 = hwp[q0], Wn = hwp[q0 + Gg] - W0;
+      const int64_t Wn = hwp[q0 + Gg] - hwp[q0];
       if (Wn == 0) continue;
       int64_t ch = CH;
       while ((Wn + ch - 1) / ch > (1ll << 24)) ch *= 2;
@@ -559,8 +578,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
-      Gg, gxg, gsl, wpg, W0, Wn, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, W.s2e, C4P, \
-      STG)
+      Gg, gxg, gsl, wpg, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, s2x, C4P, STG)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
@@ -578,11 +596,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_ALL(HS)                                                  \
   do {                                                                 \
     if (c4_wide) {                                                     \
-      if (half) TG_C4_PHASES(uint64_t, true, HS, W.C4, stage_xu);      \
-      else TG_C4_PHASES(uint64_t, false, HS, W.C4, stage_xu);          \
+      if (half) TG_C4_PHASES(uint64_t, true, HS, C4w_t, stage_xu);     \
+      else TG_C4_PHASES(uint64_t, false, HS, C4w_t, stage_xu);         \
     } else {                                                           \
-      if (half) TG_C4_PHASES(uint32_t, true, HS, C4n, stage_xu);       \
-      else TG_C4_PHASES(uint32_t, false, HS, C4n, stage_xu);           \
+      if (half) TG_C4_PHASES(uint32_t, true, HS, C4n_t, stage_xu);     \
+      else TG_C4_PHASES(uint32_t, false, HS, C4n_t, stage_xu);         \
     }                                                                  \
   } while (0)
       if (hashed) TG_C4_ALL(true);
@@ -592,6 +610,14 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #undef TG_C4_GROUP
       TG_LAUNCHED("k_c4_group");
     }
+  }
+
+  if (slot_rows) {
+    if (c4_wide)
+      k_c4_fold<uint64_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, W.es_lo, W.es_hi, C4w_t, W.C4);
+    else
+      k_c4_fold<uint32_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, W.es_lo, W.es_hi, C4n_t, C4n);
+    TG_LAUNCHED("k_c4_fold");
   }
 
   // ---- per-edge combine

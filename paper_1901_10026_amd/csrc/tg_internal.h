@@ -47,6 +47,8 @@ struct Work {
   int32_t* ei;           // m
   int32_t* ej;           // m
   int32_t* s2e;          // nnz
+  int32_t* es_lo;        // m     slot of each edge in its lower end's row
+  int32_t* es_hi;        // m     slot of each edge in its upper end's row
   int32_t* out_col;      // m
   uint32_t* tau;         // m*L
   uint64_t* Pn;          // n*L*L

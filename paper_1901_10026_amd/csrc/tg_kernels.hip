@@ -189,11 +189,13 @@ __global__ void k_scan_add(int64_t n, T* __restrict__ out, const T* __restrict__
 }
 
 // One wavefront per node v: canonical edge ids of its upper slots, the
-// slot->edge map for every slot, and the degree-ordered out-list.
+// slot->edge map for every slot, both slots of every edge (es_lo in the row
+// of its lower end, es_hi in the other) and the degree-ordered out-list.
 __global__ void k_fill_edges(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                              const int32_t* __restrict__ deg, const int32_t* __restrict__ n_upper,
                              const int32_t* __restrict__ upper_off, const int32_t* __restrict__ out_off,
                              int32_t* __restrict__ ei, int32_t* __restrict__ ej, int32_t* __restrict__ s2e,
+                             int32_t* __restrict__ es_lo, int32_t* __restrict__ es_hi,
                              int32_t* __restrict__ out_col) {
   const int64_t v = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
   if (v >= n) return;
@@ -212,9 +214,12 @@ __global__ void k_fill_edges(int64_t n, const int32_t* __restrict__ rp, const in
         ei[e] = (int32_t)v;
         ej[e] = k;
         s2e[s] = e;
+        es_lo[e] = s;
       } else {
         const int32_t p = rp[k] + lower_bound(ci + rp[k], dk, (int32_t)v);
-        s2e[s] = upper_off[k] + (p - (rp[k + 1] - n_upper[k]));
+        const int32_t e = upper_off[k] + (p - (rp[k + 1] - n_upper[k]));
+        s2e[s] = e;
+        es_hi[e] = s;
       }
     }
     const bool hi = valid && precedes(dv, (int32_t)v, dk, k);
@@ -348,6 +353,9 @@ __device__ __forceinline__ void team_sync() {
   else __syncthreads();
 }
 
+// Credits go to per-edge rows (s2e given: row = s2e[slot]) or to per-slot
+// rows (s2e null: row = slot; consecutive wedges then credit consecutive
+// rows, and k_c4_fold adds an edge's two slot rows afterwards).
 // Credits the cycles through wedge x-u-w (slots sxu of x's row and suw of
 // u's row) given the typed middle counts between x and w.
 // Per-edge 4-cycle counters are 32 bits when every count fits (the count on
@@ -414,7 +422,8 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
           } else {
             const int h = hash_find(kw, LOG2CAP, w);
             if (tw[h] < 2) continue;
-            const int32_t e_xu = s2e[bx + q], e_uw = s2e[bu + b0 + ln];
+            const int32_t e_xu = s2e ? s2e[bx + q] : bx + q;
+            const int32_t e_uw = s2e ? s2e[bu + b0 + ln] : bu + b0 + ln;
             const int phw = ty[w];
             for (int t = 0; t < L; ++t) {
               const int g = hash_find(kt, LOG2CAP, w * L + t);
@@ -454,7 +463,7 @@ __device__ __forceinline__ int32_t wave_excl_scan(int32_t v, int32_t* total) {
 }
 
 // Wedge count of each slot of the heavy nodes (listed in processing order,
-// hs = prefix of their degrees): d_u when the middle u precedes x.
+// hs = prefix of their degrees): d_u when the middle u precedes x, else 0.
 __global__ void k_c4_slot_wedges(int64_t nslots, int64_t nnodes, const int32_t* __restrict__ hx,
                                  const int64_t* __restrict__ hs, const int32_t* __restrict__ rp,
                                  const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
@@ -475,10 +484,13 @@ __global__ void k_c4_slot_wedges(int64_t nslots, int64_t nnodes, const int32_t* 
 // HASH: instead of a dense array per node, node gi of the group has an
 // open-addressing table of 2^hlog[gi] rows starting at row hoff[gi], keyed by
 // w in hkeys (-1 = empty), for nodes whose far ends are few compared with n.
+//
+// wp is the group's part of the slot prefix; a launch of nblk workgroups
+// strides over the group's chunks.
 template <int PHASE, class C4T, bool HALF, bool HASH>
 __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restrict__ gx,
                                                   const int64_t* __restrict__ gslot, const int64_t* __restrict__ wp,
-                                                  int64_t W0, int64_t Wn, int CH, uint32_t* __restrict__ dense,
+                                                  int CH, uint32_t* __restrict__ dense,
                                                   int64_t stride, int RW, const int64_t* __restrict__ hoff,
                                                   const uint8_t* __restrict__ hlog, int32_t* __restrict__ hkeys,
                                                   const int32_t* __restrict__ rp,
@@ -491,22 +503,25 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
   // 4 * 64 * P words in phase 1 with stage_xu, else none
   extern __shared__ uint32_t xu_acc[];
   const int wib = threadIdx.x / TG_WAVE;
-  const int64_t wbeg = ((int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib) * CH;
-  if (wbeg >= Wn) return;
-  const int64_t wend = min(wbeg + (int64_t)CH, Wn);
   const int ln = lane();
   const int P = L * (L + 1) / 2;
   // gslot holds the group's slot prefix with an arbitrary base
   const int64_t sbase = gslot[0];
   const int64_t S = gslot[G] - sbase;
+  const int64_t* wpk = wp;
+  const int64_t W0 = wpk[0], Wn = wpk[S] - W0;
   uint32_t* xacc = xu_acc + wib * TG_WAVE * P;
+  for (int64_t chunk = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib; chunk * CH < Wn;
+       chunk += (int64_t)gridDim.x * (blockDim.x / TG_WAVE)) {
+  const int64_t wbeg = chunk * CH;
+  const int64_t wend = min(wbeg + (int64_t)CH, Wn);
   // first slot: the largest s < S with wp[s] - W0 <= wbeg
   int64_t sa;
   {
     int64_t lo = 0, hi = S;
     while (hi - lo > 1) {
       const int64_t mid = (lo + hi) >> 1;
-      if (wp[mid] - W0 <= wbeg) lo = mid; else hi = mid;
+      if (wpk[mid] - W0 <= wbeg) lo = mid; else hi = mid;
     }
     sa = lo;
   }
@@ -520,7 +535,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
     int32_t x = 0, dx = 0, bu = 0, cu = 0, off = 0, e_xu = 0, gi = 0;
     int phx = 0, phu = 0;
     if (sl < S) {
-      const int64_t ws = wp[sl] - W0, we = wp[sl + 1] - W0;
+      const int64_t ws = wpk[sl] - W0, we = wpk[sl + 1] - W0;
       const int64_t lo = max(ws, wbeg), hi = min(we, wend);
       if (hi > lo) {
         int a = 0, b = G;  // largest g with gslot[g] <= sl
@@ -538,7 +553,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         bu = rp[u];
         phx = ty[x];
         phu = ty[u];
-        e_xu = s2e[sx];
+        e_xu = s2e ? s2e[sx] : sx;
       }
     }
     int32_t tot = 0;
@@ -606,20 +621,24 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
           if (HALF) atomicAdd(&row[o_phu >> 1], 1u << ((o_phu & 1) << 4));
           else atomicAdd(&row[o_phu], 1u);
         } else if (PHASE == 1) {
+          // rows are 16-byte aligned and RW is a multiple of 4 words
           uint32_t c[16];
           uint32_t sum = 0;
-          if (HALF) {
-            for (int q = 0; q < RW; ++q) {
-              const uint32_t wd = row[q];
-              c[2 * q] = wd & 0xffffu;
-              c[2 * q + 1] = wd >> 16;
+          for (int q4 = 0; q4 < RW / 4; ++q4) {
+            const uint4 v4 = reinterpret_cast<const uint4*>(row)[q4];
+            const uint32_t wd[4] = {v4.x, v4.y, v4.z, v4.w};
+            for (int r = 0; r < 4; ++r) {
+              if (HALF) {
+                c[8 * q4 + 2 * r] = wd[r] & 0xffffu;
+                c[8 * q4 + 2 * r + 1] = wd[r] >> 16;
+              } else {
+                c[4 * q4 + r] = wd[r];
+              }
             }
-          } else {
-            for (int t = 0; t < L; ++t) c[t] = row[t];
           }
           for (int t = 0; t < L; ++t) sum += c[t];
           if (sum < 2) continue;
-          const int32_t e_uw = s2e[suw];
+          const int32_t e_uw = s2e ? s2e[suw] : suw;
           const int phw = ty[w];
           for (int t = 0; t < L; ++t) {
             const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
@@ -629,7 +648,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
             else c4_add(C4, (int64_t)o_exu * P + pair_index(phw, t), (uint64_t)cc);
           }
         } else {
-          for (int q = 0; q < RW; ++q) row[q] = 0u;
+          for (int q4 = 0; q4 < RW / 4; ++q4) reinterpret_cast<uint4*>(row)[q4] = make_uint4(0u, 0u, 0u, 0u);
         }
       }
     }
@@ -645,7 +664,19 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
     }
     // next window, unless it starts at or past this wavefront's last wedge
     sa += TG_WAVE;
-    if (sa >= S || wp[sa] - W0 >= wend) break;
+    if (sa >= S || wpk[sa] - W0 >= wend) break;
+  }
+  }
+}
+
+// Per-edge 4-cycle rows from per-slot rows: C4e[e] = C4s[es_lo[e]] + C4s[es_hi[e]].
+template <class C4T>
+__global__ void k_c4_fold(int64_t m, int P, const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
+                          const C4T* __restrict__ C4s, C4T* __restrict__ C4e) {
+  const int64_t total = m * P;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = x / P, p = x - e * P;
+    C4e[x] = C4s[(int64_t)es_lo[e] * P + p] + C4s[(int64_t)es_hi[e] * P + p];
   }
 }
 
