@@ -1102,7 +1102,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->light_max_degree = 64;
   t->heavy_min_degree = 4096;
   t->mid_log2_cost = 18;
-  t->heavy_log2_cost = 20;
+  t->heavy_log2_cost = 64;
   t->combine_grid = 8192;
   t->c4_footprint_mb = 192;
   t->c4_group_kwedges = 16384;

@@ -38,7 +38,6 @@ struct BatchArgs {
 template <int W_MAX>
 struct BatchLds {
   uint64_t adj[64 * W_MAX][W_MAX];     // bit rows, relabelled ids
-  uint64_t seg[TG_BATCH_LMAX][W_MAX];  // bits of type t inside word w
   uint16_t deg_t[64 * W_MAX][TG_BATCH_LMAX];
   uint16_t new_id[64 * W_MAX];
   int32_t rp[64 * W_MAX + 1];
@@ -61,21 +60,45 @@ __device__ __forceinline__ void acc_add(uint64_t* acc, int64_t key, int64_t v) {
   if (v) atomicAdd((unsigned long long*)&acc[key], (unsigned long long)v);
 }
 
-// Counts per type u of the set bits of x[0..W) (bits of type u: seg[u][w]).
+// Bits [lo, hi) of a 64-bit word (0 <= lo, hi <= 64).
+__device__ __forceinline__ uint64_t range_mask(int lo, int hi) {
+  if (hi <= lo) return 0ull;
+  const uint64_t upto_hi = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+  const uint64_t below_lo = lo >= 64 ? ~0ull : ((1ull << lo) - 1ull);
+  return upto_hi & ~below_lo;
+}
+
+// Bits of word w that belong to type u: nodes are relabelled so that type u
+// holds ids [ts[u], ts[u+1]).
+__device__ __forceinline__ uint64_t type_word_mask(const int32_t (&ts)[TG_BATCH_LMAX + 1], int u, int w) {
+  const int base = 64 * w;
+  const int lo = min(max(ts[u] - base, 0), 64), hi = min(max(ts[u + 1] - base, 0), 64);
+  return range_mask(lo, hi);
+}
+
+// Counts per type u of the set bits of a[0..W), b[0..W), c[0..W).
 template <int W_MAX>
-__device__ __forceinline__ void typed_popc(const uint64_t (&x)[W_MAX], const uint64_t (*seg)[W_MAX], int W, int L,
-                                           int32_t (&c)[TG_BATCH_LMAX]) {
+__device__ __forceinline__ void typed_popc3(const uint64_t (&a)[W_MAX], const uint64_t (&b)[W_MAX],
+                                            const uint64_t (&c)[W_MAX], const int32_t (&ts)[TG_BATCH_LMAX + 1],
+                                            int L, int32_t (&ca)[TG_BATCH_LMAX], int32_t (&cb)[TG_BATCH_LMAX],
+                                            int32_t (&cc)[TG_BATCH_LMAX]) {
 #pragma unroll
   for (int u = 0; u < TG_BATCH_LMAX; ++u) {
-    int32_t s = 0;
+    int32_t sa = 0, sb = 0, sc = 0;
     if (u < L) {
 #pragma unroll
       for (int w = 0; w < W_MAX; ++w) {
-        const uint64_t m = (w < W) ? seg[u][w] : 0ull;
-        if (m) s += __popcll(x[w] & m);
+        const uint64_t m = type_word_mask(ts, u, w);
+        if (m) {
+          sa += __popcll(a[w] & m);
+          sb += __popcll(b[w] & m);
+          sc += __popcll(c[w] & m);
+        }
       }
     }
-    c[u] = s;
+    ca[u] = sa;
+    cb[u] = sb;
+    cc[u] = sc;
   }
 }
 
@@ -131,18 +154,6 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
     }
     bteam_sync<NWAVES>();
     for (int v = tid; v < n; v += TSIZE) S.new_id[v] = (uint16_t)(S.new_id[v] + S.type_start[gty[v]]);
-    for (int q = tid; q < TG_BATCH_LMAX * W_MAX; q += TSIZE) {
-      const int t = q / W_MAX, w = q % W_MAX;
-      uint64_t m = 0;
-      if (t < L) {
-        const int lo = S.type_start[t], hi = S.type_start[t + 1];
-        for (int b = 0; b < 64; ++b) {
-          const int pos = w * 64 + b;
-          if (pos >= lo && pos < hi) m |= 1ull << b;
-        }
-      }
-      S.seg[t][w] = m;
-    }
     bteam_sync<NWAVES>();
     for (int s = tid; s < nslots; s += TSIZE) {
       const int v = lower_bound(S.rp, n + 1, s + 1) - 1;  // row holding slot s
@@ -150,12 +161,15 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
       atomicOr((unsigned long long*)&S.adj[a][b >> 6], (unsigned long long)(1ull << (b & 63)));
     }
     bteam_sync<NWAVES>();
+    int32_t ts[TG_BATCH_LMAX + 1];
+#pragma unroll
+    for (int t = 0; t <= TG_BATCH_LMAX; ++t) ts[t] = S.type_start[t];
     for (int v = tid; v < n; v += TSIZE) {
       uint64_t x[W_MAX];
 #pragma unroll
-      for (int w = 0; w < W_MAX; ++w) x[w] = S.adj[v][w];
-      int32_t c[TG_BATCH_LMAX];
-      typed_popc<W_MAX>(x, S.seg, W, L, c);
+      for (int w = 0; w < W_MAX; ++w) x[w] = (w < W) ? S.adj[v][w] : 0ull;
+      int32_t c[TG_BATCH_LMAX], c1[TG_BATCH_LMAX], c2[TG_BATCH_LMAX];
+      typed_popc3<W_MAX>(x, x, x, ts, L, c, c1, c2);
 #pragma unroll
       for (int u = 0; u < TG_BATCH_LMAX; ++u) S.deg_t[v][u] = (uint16_t)c[u];
     }
@@ -179,9 +193,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
         Sj[w] = aj & ~ai & ~bi;
       }
       int32_t nT[TG_BATCH_LMAX], nSi[TG_BATCH_LMAX], nSj[TG_BATCH_LMAX];
-      typed_popc<W_MAX>(T, S.seg, W, L, nT);
-      typed_popc<W_MAX>(Si, S.seg, W, L, nSi);
-      typed_popc<W_MAX>(Sj, S.seg, W, L, nSj);
+      typed_popc3<W_MAX>(T, Si, Sj, ts, L, nT, nSi, nSj);
       // 3-node graphlets and the product terms of Eqs. 7-10, doubled
 #pragma unroll
       for (int u = 0; u < TG_BATCH_LMAX; ++u) {
@@ -221,7 +233,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
         bool any = false;
 #pragma unroll
         for (int w = 0; w < W_MAX; ++w) {
-          const uint64_t m = (w < W) ? S.seg[t][w] : 0ull;
+          const uint64_t m = type_word_mask(ts, t, w);
           uint64_t bits = (T[w] | Si[w] | Sj[w]) & m;
           while (bits) {
             const int b = __builtin_ctzll(bits);
@@ -229,34 +241,38 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
             const int k = w * 64 + b;
             const uint64_t kb = 1ull << b;
             const int cls = (T[w] & kb) ? 0 : ((Si[w] & kb) ? 1 : 2);
-            uint64_t ak[W_MAX], xT[W_MAX], xSi[W_MAX], xSj[W_MAX];
+            uint64_t ak[W_MAX];
 #pragma unroll
-            for (int q = 0; q < W_MAX; ++q) {
-              ak[q] = (q < W) ? S.adj[k][q] : 0ull;
-              xT[q] = ak[q] & T[q];
-              xSi[q] = ak[q] & Si[q];
-              xSj[q] = ak[q] & Sj[q];
-            }
-            int32_t cT[TG_BATCH_LMAX], cSi[TG_BATCH_LMAX], cSj[TG_BATCH_LMAX];
-            typed_popc<W_MAX>(xT, S.seg, W, L, cT);
-            typed_popc<W_MAX>(xSi, S.seg, W, L, cSi);
-            typed_popc<W_MAX>(xSj, S.seg, W, L, cSj);
+            for (int q = 0; q < W_MAX; ++q) ak[q] = (q < W) ? S.adj[k][q] : 0ull;
 #pragma unroll
             for (int u = 0; u < TG_BATCH_LMAX; ++u) {
+              if (u >= L) continue;
+              // k's neighbours of type u in T, S_i and S_j
+              int32_t cT = 0, cSi = 0, cSj = 0;
+#pragma unroll
+              for (int q = 0; q < W_MAX; ++q) {
+                const uint64_t mq = type_word_mask(ts, u, q);
+                if (mq) {
+                  const uint64_t a = ak[q] & mq;
+                  cT += __popcll(a & T[q]);
+                  cSi += __popcll(a & Si[q]);
+                  cSj += __popcll(a & Sj[q]);
+                }
+              }
               const int32_t dku = S.deg_t[k][u];
               if (cls == 0) {
-                const int32_t cI = dku - (pi == u) - (pj == u) - cT[u] - cSi[u] - cSj[u];
-                r12[u] += cT[u];
-                r10[u] += cSi[u] + cSj[u];
+                const int32_t cI = dku - (pi == u) - (pj == u) - cT - cSi - cSj;
+                r12[u] += cT;
+                r10[u] += cSi + cSj;
                 r8[u] += cI;
               } else if (cls == 1) {
-                const int32_t cI = dku - (pi == u) - cT[u] - cSi[u] - cSj[u];
-                r7[u] += cSi[u];
+                const int32_t cI = dku - (pi == u) - cT - cSi - cSj;
+                r7[u] += cSi;
                 r3[u] += cI;
               } else {
-                const int32_t cI = dku - (pj == u) - cT[u] - cSi[u] - cSj[u];
-                r7[u] += cSj[u];
-                r6[u] += cSi[u];
+                const int32_t cI = dku - (pj == u) - cT - cSi - cSj;
+                r7[u] += cSj;
+                r6[u] += cSi;
                 r3[u] += cI;
               }
             }
