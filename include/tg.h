@@ -90,7 +90,10 @@ typedef struct {
                                  a full wavefront (64 = never) */
   int32_t heavy_log2_cost;    /* tg_count: edges whose log2 schedule cost exceeds this use one
                                  workgroup (64 = never) */
-  int32_t combine_grid;       /* tg_count: workgroup count cap of the small-team combine launches */
+  int32_t combine_grid;       /* tg_count: workgroup count cap of the small-team combine launches
+                                 (0 = the number that fits the device at once) */
+  int32_t wg_grid;            /* tg_count: workgroup count cap of the workgroup-per-edge launch
+                                 (0 = the number that fits the device at once) */
   int32_t c4_footprint_mb;    /* tg_count: heavy nodes of the 4-cycle pass are processed in groups
                                  whose count rows touch at most about this many MiB ... */
   int32_t c4_group_kwedges;   /* ... and that close once they hold this many thousand wedges */

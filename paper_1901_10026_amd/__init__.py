@@ -58,12 +58,12 @@ class Tuning(ctypes.Structure):
     """Launch-shape choices (tg_tuning); counts never depend on them."""
     _fields_ = [("light_max_degree", ctypes.c_int32), ("heavy_min_degree", ctypes.c_int32),
                 ("mid_log2_cost", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
-                ("combine_grid", ctypes.c_int32), ("c4_footprint_mb", ctypes.c_int32),
+                ("combine_grid", ctypes.c_int32), ("wg_grid", ctypes.c_int32), ("c4_footprint_mb", ctypes.c_int32),
                 ("c4_group_kwedges", ctypes.c_int32), ("c4_chunk", ctypes.c_int32),
                 ("c4_hash_ratio", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32 * 9)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
-               "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio")
+               "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

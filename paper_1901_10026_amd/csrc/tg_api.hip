@@ -643,19 +643,42 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     need = std::min(need, ea_budget);
     if (need > 0) TG_HIP(S.get(reinterpret_cast<uint64_t**>(&ea), (need + 7) / 8));
   }
-  const unsigned rows_grid = (unsigned)std::max(1, tune.combine_grid);
-  if (class_count[0] > 0)
+  // workgroups that fit the device at once for a launch of `kernel` with
+  // `lds` bytes (the default caps)
+  int dev = 0, cus = 0;
+  TG_HIP(hipGetDevice(&dev));
+  TG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  auto resident = [&](const void* kernel, size_t lds) -> int64_t {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess) per_cu = 1;
+    return (int64_t)std::max(1, cus) * std::max(1, per_cu);
+  };
+  const unsigned rows_grid = tune.combine_grid > 0 ? (unsigned)tune.combine_grid : 8192u;
+  if (class_count[0] > 0) {
+    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
+                                              : resident((const void*)k_combine<16, uint32_t>,
+                                                         combine_lds_bytes<16, uint32_t>(L));
     if (tg_status s2 = combine_class<16, uint32_t>(st, A, class_count[0], W.elist + class_begin[0],
-                                                   grid_for(class_count[0], 16, std::max(1, tune.combine_grid)),
-                                                   nullptr, 0, K, ea, ea_budget, rows_grid))
+                                                   grid_for(class_count[0], 16, cap), nullptr, 0, K, ea, ea_budget,
+                                                   rows_grid))
       return s2;
-  if (class_count[1] > 0)
+  }
+  if (class_count[1] > 0) {
+    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
+                                              : resident((const void*)k_combine<64, uint32_t>,
+                                                         combine_lds_bytes<64, uint32_t>(L));
     if (tg_status s2 = combine_class<64, uint32_t>(st, A, class_count[1], W.elist + class_begin[1],
-                                                   grid_for(class_count[1], 4, std::max(1, tune.combine_grid)),
-                                                   nullptr, 0, K, ea, ea_budget, rows_grid))
+                                                   grid_for(class_count[1], 4, cap), nullptr, 0, K, ea, ea_budget,
+                                                   rows_grid))
       return s2;
+  }
   if (class_count[2] > 0) {
-    const unsigned grid = grid_for(class_count[2], 1, 1024);
+    // default: one workgroup per resident slot (CUs x workgroups per CU at
+    // this launch's LDS), so that no second partial wave of workgroups runs
+    const int64_t cap = tune.wg_grid > 0 ? tune.wg_grid
+                                         : resident((const void*)k_combine<256, uint64_t>,
+                                                    combine_lds_bytes<256, uint64_t>(L));
+    const unsigned grid = grid_for(class_count[2], 1, cap);
     int32_t* t_over = nullptr;
     int64_t t_cap = 0;
     if (max_t_heavy > TG_T_WG_CAP) {
@@ -1104,6 +1127,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->mid_log2_cost = 18;
   t->heavy_log2_cost = 64;
   t->combine_grid = 8192;
+  t->wg_grid = 0;
   t->c4_footprint_mb = 192;
   t->c4_group_kwedges = 16384;
   t->c4_chunk = 256;
@@ -1372,7 +1396,8 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
       axes.push_back({&t.heavy_log2_cost, {64, 18, 20, 22, 24}});
     }
   }
-  axes.push_back({&t.combine_grid, {1024, 2048, 4096, 8192}});
+  axes.push_back({&t.combine_grid, {4096, 8192, 16384}});
+  axes.push_back({&t.wg_grid, {0, 1024, 2048, 4096}});
   axes.push_back({&t.c4_footprint_mb, {64, 192, 1024}});
   axes.push_back({&t.c4_group_kwedges, {1024, 4096, 16384}});
   axes.push_back({&t.c4_chunk, {256, 1024, 4096}});

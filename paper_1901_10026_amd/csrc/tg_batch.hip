@@ -223,9 +223,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs A, int64_t count, const
         }
       }
       // explicit orbits, one type t of k at a time
-#pragma unroll
-      for (int t = 0; t < TG_BATCH_LMAX; ++t) {
-        if (t >= L) continue;
+#pragma unroll 1
+      for (int t = 0; t < L; ++t) {
         int32_t r3[TG_BATCH_LMAX], r6[TG_BATCH_LMAX], r7[TG_BATCH_LMAX], r8[TG_BATCH_LMAX], r10[TG_BATCH_LMAX],
             r12[TG_BATCH_LMAX];
 #pragma unroll
