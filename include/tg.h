@@ -101,6 +101,8 @@ typedef struct {
   int32_t c4_hash_ratio;      /* tg_count: a heavy node uses a hash table of its far ends instead of a
                                  dense array when the table is at least this many times smaller
                                  (0 = never) */
+  int32_t c4_slot_budget_mb;  /* tg_count: 4-cycle counters are kept per CSR slot (then folded per edge)
+                                 when they fit in this many MiB, else per edge */
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */

@@ -381,8 +381,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // (consecutive wedges then credit consecutive rows), folded into per-edge
   // rows afterwards; else straight to per-edge rows.
   const int64_t c4_width = c4_wide ? 8 : 4;
-  const bool slot_rows = nnz * P * c4_width <= (16ll << 30);
+  const bool slot_rows = nnz * P * c4_width <= ((int64_t)std::max(0, tune.c4_slot_budget_mb) << 20);
   const int32_t* s2x = slot_rows ? nullptr : W.s2e;
+  const int64_t crows = slot_rows ? nnz : m;  // counters are C4[p * crows + row]
   uint64_t* C4w_t = W.C4;
   uint32_t* C4n_t = C4n;
   if (slot_rows) {
@@ -399,19 +400,19 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (n_t1 > 0) {
     if (c4_wide)
       k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4w_t);
+                                                                         L, s2x, C4w_t, crows);
     else
       k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4n_t);
+                                                                         L, s2x, C4n_t, crows);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (n_t2 > 0) {
     if (c4_wide)
       k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4w_t);
+                                                                          ty, L, s2x, C4w_t, crows);
     else
       k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4n_t);
+                                                                          ty, L, s2x, C4n_t, crows);
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -578,7 +579,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
-      Gg, gxg, gsl, wpg, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, s2x, C4P, STG)
+      Gg, gxg, gsl, wpg, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, s2x, C4P, crows, \
+      STG)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
@@ -614,9 +616,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 
   if (slot_rows) {
     if (c4_wide)
-      k_c4_fold<uint64_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, W.es_lo, W.es_hi, C4w_t, W.C4);
+      k_c4_fold<uint64_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, nnz, W.es_lo, W.es_hi, C4w_t,
+                                                                       W.C4);
     else
-      k_c4_fold<uint32_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, W.es_lo, W.es_hi, C4n_t, C4n);
+      k_c4_fold<uint32_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, nnz, W.es_lo, W.es_hi, C4n_t, C4n);
     TG_LAUNCHED("k_c4_fold");
   }
 
@@ -627,6 +630,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
+  A.c4_rows = slot_rows ? 0 : m;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
   A.edge_ids = ids; A.n_edge_ids = nids;
   A.gacc_in_lds = (global_counts && K <= TG_GACC_MAX_KEYS) ? 1 : 0;
@@ -961,6 +965,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
   A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
   A.c4_wide = 1;
+  A.c4_rows = 0;
   A.edge_counts = nullptr; A.edge_begin = 0; A.edge_end = 0; A.global_sums = gsink;
   A.edge_ids = nullptr; A.n_edge_ids = 0;
   A.gacc_in_lds = 0;
@@ -1132,6 +1137,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_group_kwedges = 16384;
   t->c4_chunk = 256;
   t->c4_hash_ratio = 2;
+  t->c4_slot_budget_mb = 16384;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }

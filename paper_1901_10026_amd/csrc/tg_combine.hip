@@ -329,7 +329,8 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
                         - sym([&](int x, int y) -> int64_t { return (pi == x) ? Tn(y) : 0; })
                         - sym([&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y]; }) - sym(ETSj);
     const int64_t g7 = (sSiSi + sSjSj) / 2;
-    const int64_t c4 = A.c4_wide ? (int64_t)A.C4[(int64_t)e * P + p] : (int64_t)A.C4n[(int64_t)e * P + p];
+    const int64_t ci4 = A.c4_rows ? (int64_t)p * A.c4_rows + e : (int64_t)e * P + p;
+    const int64_t c4 = A.c4_wide ? (int64_t)A.C4[ci4] : (int64_t)A.C4n[ci4];
     const int64_t g6 = c4 - g10 - 2 * g12;
     const int64_t g3 = sym([&](int x, int y) -> int64_t { return (int64_t)Pi[x * L + y]; })
                      + sym([&](int x, int y) -> int64_t { return (int64_t)Pj[x * L + y]; })

@@ -77,6 +77,7 @@ struct EdgeArgs {
   const uint64_t* C4;     // 64-bit 4-cycle counters (c4_wide), or
   const uint32_t* C4n;    // 32-bit ones
   int c4_wide;
+  int64_t c4_rows;        // 0: P counters per edge; else type-pair major, C4[p * c4_rows + e]
   int L;
   uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or for edge_ids, or null
   int64_t edge_begin, edge_end;

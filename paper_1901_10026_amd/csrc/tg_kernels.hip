@@ -355,7 +355,10 @@ __device__ __forceinline__ void team_sync() {
 
 // Credits go to per-edge rows (s2e given: row = s2e[slot]) or to per-slot
 // rows (s2e null: row = slot; consecutive wedges then credit consecutive
-// rows, and k_c4_fold adds an edge's two slot rows afterwards).
+// rows, and k_c4_fold adds an edge's two slot rows afterwards).  The counters
+// are stored type-pair major, C4[p * crows + row] (crows = number of rows),
+// so that the lanes of a wavefront crediting consecutive rows with one type
+// pair write consecutive words.
 // Credits the cycles through wedge x-u-w (slots sxu of x's row and suw of
 // u's row) given the typed middle counts between x and w.
 // Per-edge 4-cycle counters are 32 bits when every count fits (the count on
@@ -366,12 +369,12 @@ __device__ __forceinline__ void c4_add(uint64_t* C4, int64_t idx, uint64_t v) {
 }
 
 template <class C4T>
-__device__ __forceinline__ void credit_wedge(C4T* __restrict__ C4, int L, int P, int32_t e_xu, int32_t e_uw,
+__device__ __forceinline__ void credit_wedge(C4T* __restrict__ C4, int64_t crows, int32_t e_xu, int32_t e_uw,
                                              int phx, int phu, int phw, int t, uint32_t cnt_t) {
   const int64_t c = (int64_t)cnt_t - (t == phu ? 1 : 0);
   if (c > 0) {
-    c4_add(C4, (int64_t)e_xu * P + pair_index(phw, t), (uint64_t)c);
-    c4_add(C4, (int64_t)e_uw * P + pair_index(phx, t), (uint64_t)c);
+    c4_add(C4, (int64_t)pair_index(phw, t) * crows + e_xu, (uint64_t)c);
+    c4_add(C4, (int64_t)pair_index(phx, t) * crows + e_uw, (uint64_t)c);
   }
 }
 
@@ -382,7 +385,7 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  int L, const int32_t* __restrict__ s2e,
-                                                 C4T* __restrict__ C4) {
+                                                 C4T* __restrict__ C4, int64_t crows) {
   constexpr int CAP = 1 << LOG2CAP;
   constexpr int TEAMS = 4 / NWAVES;
   __shared__ int32_t kw_all[TEAMS][CAP];
@@ -427,7 +430,7 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
             const int phw = ty[w];
             for (int t = 0; t < L; ++t) {
               const int g = hash_find(kt, LOG2CAP, w * L + t);
-              credit_wedge(C4, L, P, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u);
+              credit_wedge(C4, crows, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u);
             }
           }
         }
@@ -497,7 +500,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
-                                                  int stage_xu) {
+                                                  int64_t crows, int stage_xu) {
   // credits to the edges (x, u) of the window's 64 slots are summed in LDS
   // first (stage_xu: L <= 8 and every sum fits 32 bits); dynamic LDS of
   // 4 * 64 * P words in phase 1 with stage_xu, else none
@@ -643,9 +646,9 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
           for (int t = 0; t < L; ++t) {
             const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
             if (cc <= 0) continue;
-            c4_add(C4, (int64_t)e_uw * P + pair_index(o_phx, t), (uint64_t)cc);
+            c4_add(C4, (int64_t)pair_index(o_phx, t) * crows + e_uw, (uint64_t)cc);
             if (stage_xu) atomicAdd(&xacc[o * P + pair_index(phw, t)], (uint32_t)cc);
-            else c4_add(C4, (int64_t)o_exu * P + pair_index(phw, t), (uint64_t)cc);
+            else c4_add(C4, (int64_t)pair_index(phw, t) * crows + o_exu, (uint64_t)cc);
           }
         } else {
           for (int q4 = 0; q4 < RW / 4; ++q4) reinterpret_cast<uint4*>(row)[q4] = make_uint4(0u, 0u, 0u, 0u);
@@ -653,12 +656,11 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
       }
     }
     if (PHASE == 1 && stage_xu) {
+      // each lane flushes the sums of its own slot, one type pair at a time
       wave_sync();
-      for (int q = ln; q < TG_WAVE * P; q += TG_WAVE) {
-        const uint32_t val = xacc[q];
-        const int s = q / P;
-        const int32_t es = __shfl(e_xu, s, TG_WAVE);
-        if (val) c4_add(C4, (int64_t)es * P + (q % P), (uint64_t)val);
+      for (int p = 0; p < P; ++p) {
+        const uint32_t val = xacc[ln * P + p];
+        if (val) c4_add(C4, (int64_t)p * crows + e_xu, (uint64_t)val);
       }
       wave_sync();
     }
@@ -669,14 +671,15 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
   }
 }
 
-// Per-edge 4-cycle rows from per-slot rows: C4e[e] = C4s[es_lo[e]] + C4s[es_hi[e]].
+// Per-edge 4-cycle rows (edge-major, P per edge) from type-pair-major
+// per-slot counters: C4e[e][p] = C4s[p][es_lo[e]] + C4s[p][es_hi[e]].
 template <class C4T>
-__global__ void k_c4_fold(int64_t m, int P, const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
-                          const C4T* __restrict__ C4s, C4T* __restrict__ C4e) {
+__global__ void k_c4_fold(int64_t m, int P, int64_t nslots, const int32_t* __restrict__ es_lo,
+                          const int32_t* __restrict__ es_hi, const C4T* __restrict__ C4s, C4T* __restrict__ C4e) {
   const int64_t total = m * P;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = x / P, p = x - e * P;
-    C4e[x] = C4s[(int64_t)es_lo[e] * P + p] + C4s[(int64_t)es_hi[e] * P + p];
+    C4e[x] = C4s[p * nslots + es_lo[e]] + C4s[p * nslots + es_hi[e]];
   }
 }
 

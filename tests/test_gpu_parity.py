@@ -84,6 +84,17 @@ def test_edge_id_sample():
                                                                                device="cuda:0"))
 
 
+def test_per_edge_cycle_counters():
+    """4-cycle counters kept per edge (the layout for graphs whose per-slot
+    counters exceed the memory budget) give the same counts."""
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    t = tg.Tuning.from_dict({"c4_slot_budget_mb": 0})
+    g2, r2, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=t)
+    assert np.array_equal(g2, gg) and np.array_equal(r2, rr)
+
+
 def test_rows_only_counting():
     import torch
 
