@@ -103,6 +103,7 @@ typedef struct {
                                  (0 = never) */
   int32_t c4_slot_budget_mb;  /* tg_count: 4-cycle counters are kept per CSR slot (then folded per edge)
                                  when they fit in this many MiB, else per edge */
+  int32_t c4_slices;          /* tg_count: far-end slices of the dense 4-cycle groups, one per XCD (1 = none) */
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */

@@ -60,10 +60,11 @@ class Tuning(ctypes.Structure):
                 ("mid_log2_cost", ctypes.c_int32), ("heavy_log2_cost", ctypes.c_int32),
                 ("combine_grid", ctypes.c_int32), ("wg_grid", ctypes.c_int32), ("c4_footprint_mb", ctypes.c_int32),
                 ("c4_group_kwedges", ctypes.c_int32), ("c4_chunk", ctypes.c_int32),
-                ("c4_hash_ratio", ctypes.c_int32), ("c4_slot_budget_mb", ctypes.c_int32),
+                ("c4_hash_ratio", ctypes.c_int32), ("c4_slot_budget_mb", ctypes.c_int32), ("c4_slices", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32 * 9)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
-               "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb")
+               "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
+               "c4_slices")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

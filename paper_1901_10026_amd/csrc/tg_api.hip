@@ -472,6 +472,14 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     // last-level cache; at most Gmax nodes per dense group
     const int64_t foot = (int64_t)std::max(1, tune.c4_footprint_mb) << 20;
     const int64_t wtarget = (int64_t)std::max(1, tune.c4_group_kwedges) * 1000;
+    // dense groups split their far ends into one slice per XCD (c4_slices);
+    // a group's count rows are then capped at 2 MiB per slice so that each
+    // XCD's L2 can hold its part
+    int64_t dense_slots = 0;
+    for (int64_t q = 0; q < qd; ++q) dense_slots += hd[order[q]];
+    const int nsl = (tune.c4_slices > 1 && dense_slots > 0 && dense_slots * tune.c4_slices * 16 <= (4ll << 30))
+                        ? tune.c4_slices : 1;
+    const int64_t foot_dense = nsl > 1 ? (int64_t)nsl << 21 : foot;
     const int CH = std::max(64, tune.c4_chunk);
     std::vector<int64_t> gstart, gcount;
     std::vector<int64_t> hoff(n_t3, 0);
@@ -496,7 +504,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
             rows += 1ll << lg;
           } else {
             touched = std::min<int64_t>((int64_t)wq, n) * RW * (int64_t)sizeof(uint32_t);
-            if (c > 0 && (bytes + touched > foot || wsum >= wtarget)) break;
+            if (c > 0 && (bytes + touched > foot_dense || wsum >= wtarget)) break;
           }
           bytes += touched;
           wsum += (int64_t)wq;
@@ -553,6 +561,24 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     k_c4_slot_wedges<<<grid_for(nslots, 256, 16384), 256, 0, st>>>(nslots, n_t3, d_gx, d_hs, rp, ci, W.deg, d_sc);
     TG_LAUNCHED("k_c4_slot_wedges");
     if (tg_status s2 = scan(S, st, nslots, (const int64_t*)d_sc, d_wp)) return s2;
+    // per-slice prefixes over the dense nodes' slots (slots [0, dense_slots))
+    int32_t* bnd = nullptr;
+    int64_t* d_wps = nullptr;
+    const int64_t wstride = dense_slots + 1;
+    if (nsl > 1) {
+      int64_t* d_scs;
+      TG_HIP(S.get(&bnd, n * (nsl + 1)));
+      TG_HIP(S.get(&d_scs, dense_slots * nsl));
+      TG_HIP(S.get(&d_wps, wstride * nsl));
+      k_slice_bounds<<<grid_for(n * (nsl + 1), 256, 16384), 256, 0, st>>>(n, nsl, rp, ci, bnd);
+      TG_LAUNCHED("k_slice_bounds");
+      k_c4_slot_wedges_sliced<<<grid_for(dense_slots, 256, 16384), 256, 0, st>>>(dense_slots, qd, nsl, d_gx, d_hs,
+                                                                                  rp, ci, W.deg, bnd, d_scs);
+      TG_LAUNCHED("k_c4_slot_wedges_sliced");
+      for (int k = 0; k < nsl; ++k)
+        if (tg_status s2 = scan(S, st, dense_slots, (const int64_t*)(d_scs + k * dense_slots), d_wps + k * wstride))
+          return s2;
+    }
     const size_t xu_lds = (size_t)4 * TG_WAVE * P * sizeof(uint32_t);
     for (int64_t g = 0; g < ngroups; ++g) {
       const int Gg = (int)gcount[g];
@@ -562,12 +588,16 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       if (Wn == 0) continue;
       int64_t ch = CH;
       while ((Wn + ch - 1) / ch > (1ll << 24)) ch *= 2;
-      const unsigned grid = grid_for((Wn + ch - 1) / ch, 4);
+      const int gsl_n = hashed ? 1 : nsl;
+      // sliced: blocks per slice for a quarter more than an even split of
+      // the group's wedges; the kernel strides over any further chunks
+      const unsigned grid = gsl_n == 1 ? grid_for((Wn + ch - 1) / ch, 4)
+                                       : (unsigned)(gsl_n * ((Wn * 5 / 4 / gsl_n + 4 * ch - 1) / (4 * ch) + 1));
       // the group's nodes, slot prefix (global base), wedge prefix and
       // (hashed groups) table offsets and sizes
       const int32_t* gxg = d_gx + q0;
       const int64_t* gsl = d_hs + q0;
-      const int64_t* wpg = d_wp + hs[q0];
+      const int64_t* wpg = gsl_n == 1 ? d_wp + hs[q0] : d_wps + hs[q0];
       const int64_t* hog = hashed ? d_hoff + q0 : nullptr;
       const uint8_t* hlg = hashed ? d_hlog + q0 : nullptr;
       uint32_t* cnt_base = hashed ? hcnt : dense;
@@ -579,8 +609,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
-      Gg, gxg, gsl, wpg, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, s2x, C4P, crows, \
-      STG)
+      Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, \
+      s2x, C4P, crows, STG)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
@@ -1138,6 +1168,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_chunk = 256;
   t->c4_hash_ratio = 2;
   t->c4_slot_budget_mb = 16384;
+  t->c4_slices = 1;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
 }
@@ -1408,6 +1439,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
   axes.push_back({&t.c4_group_kwedges, {1024, 4096, 16384}});
   axes.push_back({&t.c4_chunk, {256, 1024, 4096}});
   axes.push_back({&t.c4_hash_ratio, {0, 4, 16}});
+  axes.push_back({&t.c4_slices, {1, 8}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

@@ -484,15 +484,53 @@ __global__ void k_c4_slot_wedges(int64_t nslots, int64_t nnodes, const int32_t* 
   }
 }
 
+// Far-end slices: slice k holds node ids [k n / nsl, (k+1) n / nsl).  Rows
+// are sorted, so slice k of u's row is the contiguous part [bnd[u][k],
+// bnd[u][k+1]) (offsets inside the row).
+__global__ void k_slice_bounds(int64_t n, int nsl, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               int32_t* __restrict__ bnd) {
+  const int64_t total = n * (nsl + 1);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = q / (nsl + 1);
+    const int k = (int)(q - u * (nsl + 1));
+    const int32_t key = (int32_t)(((int64_t)k * n) / nsl);
+    bnd[q] = lower_bound(ci + rp[u], rp[u + 1] - rp[u], key);
+  }
+}
+
+// Per-slice wedge counts of the first nslots heavy slots:
+// cnt[k * nslots + s] = size of slice k of u's row when u precedes x, else 0.
+__global__ void k_c4_slot_wedges_sliced(int64_t nslots, int64_t nnodes, int nsl, const int32_t* __restrict__ hx,
+                                        const int64_t* __restrict__ hs, const int32_t* __restrict__ rp,
+                                        const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
+                                        const int32_t* __restrict__ bnd, int64_t* __restrict__ cnt) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnodes;  // largest q with hs[q] <= s
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hs[mid] <= s) lo = mid; else hi = mid;
+    }
+    const int32_t x = hx[lo];
+    const int32_t u = ci[rp[x] + (s - hs[lo])];
+    const bool ok = precedes(deg[u], u, deg[x], x);
+    const int32_t* b = bnd + (int64_t)u * (nsl + 1);
+    for (int k = 0; k < nsl; ++k) cnt[(int64_t)k * nslots + s] = ok ? (int64_t)(b[k + 1] - b[k]) : 0;
+  }
+}
+
 // HASH: instead of a dense array per node, node gi of the group has an
 // open-addressing table of 2^hlog[gi] rows starting at row hoff[gi], keyed by
 // w in hkeys (-1 = empty), for nodes whose far ends are few compared with n.
 //
-// wp is the group's part of the slot prefix; a launch of nblk workgroups
-// strides over the group's chunks.
+// Slices (nsl > 1): workgroup b takes the far ends of slice b % nsl, so that
+// with workgroups dealt round-robin to the XCDs and nsl = 8 each XCD's L2
+// holds one eighth of a node's count rows.  wp is the group's part of the
+// slot prefix of slice k at wp + k * wstride; workgroups stride over the
+// chunks of their slice.
 template <int PHASE, class C4T, bool HALF, bool HASH>
 __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restrict__ gx,
                                                   const int64_t* __restrict__ gslot, const int64_t* __restrict__ wp,
+                                                  int64_t wstride, int nsl, const int32_t* __restrict__ bnd,
                                                   int CH, uint32_t* __restrict__ dense,
                                                   int64_t stride, int RW, const int64_t* __restrict__ hoff,
                                                   const uint8_t* __restrict__ hlog, int32_t* __restrict__ hkeys,
@@ -508,14 +546,16 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
   const int wib = threadIdx.x / TG_WAVE;
   const int ln = lane();
   const int P = L * (L + 1) / 2;
+  const int ksl = (int)(blockIdx.x % nsl);
+  const int64_t cb = blockIdx.x / nsl, nblk = gridDim.x / nsl;
   // gslot holds the group's slot prefix with an arbitrary base
   const int64_t sbase = gslot[0];
   const int64_t S = gslot[G] - sbase;
-  const int64_t* wpk = wp;
+  const int64_t* wpk = wp + ksl * wstride;
   const int64_t W0 = wpk[0], Wn = wpk[S] - W0;
   uint32_t* xacc = xu_acc + wib * TG_WAVE * P;
-  for (int64_t chunk = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wib; chunk * CH < Wn;
-       chunk += (int64_t)gridDim.x * (blockDim.x / TG_WAVE)) {
+  for (int64_t chunk = cb * (blockDim.x / TG_WAVE) + wib; chunk * CH < Wn;
+       chunk += nblk * (blockDim.x / TG_WAVE)) {
   const int64_t wbeg = chunk * CH;
   const int64_t wend = min(wbeg + (int64_t)CH, Wn);
   // first slot: the largest s < S with wp[s] - W0 <= wbeg
@@ -553,7 +593,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         const int32_t u = ci[sx];
         cu = (int32_t)(hi - lo);
         off = (int32_t)(lo - ws);
-        bu = rp[u];
+        bu = rp[u] + (nsl > 1 ? bnd[(int64_t)u * (nsl + 1) + ksl] : 0);
         phx = ty[x];
         phu = ty[u];
         e_xu = s2e ? s2e[sx] : sx;

@@ -90,7 +90,7 @@ def test_per_edge_cycle_counters():
     import paper_1901_10026_amd as tg
     g = graphgen.chung_lu_small()
     gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
-    t = tg.Tuning.from_dict({"c4_slot_budget_mb": 0})
+    t = tg.Tuning.from_dict({"c4_slot_budget_mb": 0, "c4_slices": 8})
     g2, r2, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=t)
     assert np.array_equal(g2, gg) and np.array_equal(r2, rr)
 
