@@ -295,8 +295,8 @@ def main():
         "typed_graphlets": total_graphlets,
         "phase_ms": phases,
         "roofline": {"bound": "hbm",
-                     "kernel": "combine phase: k_combine<16>, k_combine<64>, k_combine<256>, one launch each, "
-                               "together every edge once",
+                     "kernel": "combine phase: gather kernels k_combine<16>, k_combine<64>, k_combine<256> and "
+                               "their k_combine_rows launches, together every edge once",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": stored_traffic(g.name)},
     }
