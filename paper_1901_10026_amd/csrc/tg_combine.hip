@@ -190,52 +190,86 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       s_excl[2 * TSIZE + tid] = tk;
       __syncthreads();
     }
-    // U (member, out-slot) pairs per lane at a time, so that U independent
-    // out-list loads are in flight before their lookups
+    // U (member, out-slot) pairs per lane at a time; their owner searches,
+    // out-list loads and first table reads are issued together so that the
+    // lookups of the U pairs overlap
     constexpr int U = 4;
     for (int32_t c0 = 0; c0 < tot; c0 += TSIZE * U) {
-      int32_t r[U];
+      int32_t v[U], o[U], r[U];
       int rtk[U];
 #pragma unroll
       for (int k = 0; k < U; ++k) {
-        const int32_t v = c0 + k * TSIZE + tid;
-        int o = 0;
-        int32_t o_excl, o_start, o_tk;
-        if (TSIZE <= TG_WAVE) {
-          for (int step = TSIZE / 2; step > 0; step >>= 1) {
-            const int32_t ex = __shfl(excl, o + step, TSIZE);
-            if (ex <= v) o += step;
-          }
-          o_excl = __shfl(excl, o, TSIZE);
-          o_start = __shfl(ostart, o, TSIZE);
-          o_tk = __shfl(tk, o, TSIZE);
-        } else {
-          for (int step = TSIZE / 2; step > 0; step >>= 1)
-            if (s_excl[o + step] <= v) o += step;
-          o_excl = s_excl[o];
-          o_start = s_excl[TSIZE + o];
-          o_tk = s_excl[2 * TSIZE + o];
-        }
-        r[k] = v < tot ? A.out_col[o_start + (v - o_excl)] : -1;
-        rtk[k] = o_tk;
+        v[k] = c0 + k * TSIZE + tid;
+        o[k] = 0;
+      }
+      // owner of pair v: the largest member q with excl[q] <= v
+#pragma unroll
+      for (int step = TSIZE / 2; step > 0; step >>= 1) {
+        int32_t ex[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) ex[k] = TSIZE <= TG_WAVE ? __shfl(excl, o[k] + step, TSIZE) : s_excl[o[k] + step];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          if (ex[k] <= v[k]) o[k] += step;
       }
 #pragma unroll
       for (int k = 0; k < U; ++k) {
-        int cell = -1;
-        if (r[k] >= 0) {
-          if (Th) {
-            uint32_t h = thash_home(r[k]);
-            for (;;) {
-              const int32_t sv = Th[h];
-              if (sv == -1) break;
-              if ((sv >> 4) == r[k]) { cell = rtk[k] * L + (sv & 15); break; }
-              h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+        int32_t o_excl, o_start;
+        if (TSIZE <= TG_WAVE) {
+          o_excl = __shfl(excl, o[k], TSIZE);
+          o_start = __shfl(ostart, o[k], TSIZE);
+          rtk[k] = __shfl(tk, o[k], TSIZE);
+        } else {
+          o_excl = s_excl[o[k]];
+          o_start = s_excl[TSIZE + o[k]];
+          rtk[k] = s_excl[2 * TSIZE + o[k]];
+        }
+        r[k] = v[k] < tot ? A.out_col[o_start + (v[k] - o_excl)] : -1;
+      }
+      // membership of r in T and its type
+      int cellv[U];
+      if (Th) {
+        constexpr uint32_t hmask = (1u << TG_THASH_LOG2) - 1;
+        uint32_t h[U];
+        int32_t sv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) h[k] = thash_home(r[k] >= 0 ? r[k] : 0);
+#pragma unroll
+        for (int k = 0; k < U; ++k) sv[k] = r[k] >= 0 ? Th[h[k]] : -1;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          cellv[k] = -1;
+          while (sv[k] != -1) {
+            if ((sv[k] >> 4) == r[k]) {
+              cellv[k] = rtk[k] * L + (sv[k] & 15);
+              break;
             }
-          } else {
-            const int32_t pp = lower_bound(Tid, nT, r[k]);
-            if (pp < nT && Tid[pp] == r[k]) cell = rtk[k] * L + Tty[pp];
+            h[k] = (h[k] + 1) & hmask;
+            sv[k] = Th[h[k]];
           }
         }
+      } else {
+        // lower bound in the sorted ids, the same steps for all U pairs
+        int32_t pos[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) pos[k] = 0;
+        int top = 1;
+        while (top * 2 <= nT) top *= 2;
+        for (int step = top; step > 0; step >>= 1) {
+          int32_t tv[U];
+#pragma unroll
+          for (int k = 0; k < U; ++k) tv[k] = pos[k] + step <= nT ? Tid[pos[k] + step - 1] : INT32_MAX;
+#pragma unroll
+          for (int k = 0; k < U; ++k)
+            if (tv[k] < r[k]) pos[k] += step;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          cellv[k] = (r[k] >= 0 && pos[k] < nT && Tid[pos[k]] == r[k]) ? rtk[k] * L + Tty[pos[k]] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int cell = cellv[k];
         // hits on one typed cell: one LDS atomic per distinct cell and wavefront
         uint64_t pending = ballot(cell >= 0) & tmask;
         while (pending) {
