@@ -86,6 +86,13 @@ __device__ __forceinline__ uint32_t thash_home(int32_t k) {
   return ((uint32_t)k * 2654435761u) >> (32 - TG_THASH_LOG2);
 }
 
+// Copies of the 4-clique cell counters: hits of one cell from several lanes
+// of a wavefront spread over this many LDS words.
+template <int TSIZE>
+struct MuCopies {
+  static constexpr int value = TSIZE >= 64 ? 8 : 4;
+};
+
 template <int TSIZE, class AccT>
 __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
                                             AccT* __restrict__ acc, AccT* __restrict__ out, int32_t* scratch,
@@ -95,8 +102,8 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   AccT* Aa = acc;
   AccT* Ab = acc + LL;
   AccT* Q = acc + 2 * LL;
-  AccT* Mu = acc + 3 * LL;
-  for (int x = tid; x < 4 * LL; x += TSIZE) acc[x] = 0;
+  AccT* Mu = acc + 3 * LL;  // MuCopies<TSIZE> copies, lane l adds to copy l % copies
+  for (int x = tid; x < (3 + MuCopies<TSIZE>::value) * LL; x += TSIZE) acc[x] = 0;
   if (Th)
     for (int x = tid; x < (1 << TG_THASH_LOG2); x += TSIZE) Th[x] = -1;
   tsync<TSIZE>();
@@ -171,7 +178,6 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   // lower end's degree-ordered out-list; (member, out-slot) pairs are dealt
   // to lanes through a team prefix sum
   int32_t* s_excl = scratch + 8;  // TSIZE == 256 only
-  const uint64_t tmask = TSIZE >= TG_WAVE ? ~0ull : (((1ull << TSIZE) - 1ull) << ((lane() / TSIZE) * TSIZE));
   for (int32_t q0 = 0; q0 < nT; q0 += TSIZE) {
     const int32_t q = q0 + tid;
     int32_t ostart = 0, ocnt = 0, tk = 0;
@@ -269,21 +275,18 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       }
 #pragma unroll
       for (int k = 0; k < U; ++k) {
-        const int cell = cellv[k];
-        // hits on one typed cell: one LDS atomic per distinct cell and wavefront
-        uint64_t pending = ballot(cell >= 0) & tmask;
-        while (pending) {
-          const int leader = __builtin_ctzll(pending);
-          const int lc = __shfl(cell, leader, TG_WAVE);
-          const uint64_t same = ballot(cell == lc) & tmask;
-          if (lane() == leader) atomicAdd(&Mu[lc], (AccT)__popcll(same));
-          pending &= ~same;
-        }
+        if (cellv[k] >= 0) atomicAdd(&Mu[(lane() % MuCopies<TSIZE>::value) * LL + cellv[k]], (AccT)1);
       }
     }
     if (TSIZE > TG_WAVE) __syncthreads();
   }
   if (A.work && tid == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
+  tsync<TSIZE>();
+  for (int x = tid; x < LL; x += TSIZE) {
+    AccT sum = Mu[x];
+    for (int c = 1; c < MuCopies<TSIZE>::value; ++c) sum += Mu[c * LL + x];
+    Mu[x] = sum;
+  }
   tsync<TSIZE>();
   if (out)
     for (int x = tid; x < 4 * LL; x += TSIZE) out[x] = acc[x];
@@ -418,7 +421,7 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
   // per-team region, in bytes, rounded to 8
   constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
-  const int acc_bytes = 4 * LL * (int)sizeof(AccT);
+  const int acc_bytes = (3 + MuCopies<TSIZE>::value) * LL * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   char* base = (char*)smem_comb + (int64_t)team * region;
   AccT* acc = (AccT*)base;
@@ -448,7 +451,7 @@ inline size_t combine_lds_bytes(int L) {
   constexpr int TCAP = TeamCap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
   constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
-  const int acc_bytes = 4 * L * L * (int)sizeof(AccT);
+  const int acc_bytes = (3 + MuCopies<TSIZE>::value) * L * L * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   return (size_t)(256 / TSIZE) * region;
 }
