@@ -128,6 +128,10 @@ typedef struct {
                                   entry q for edge edge_ids[q], and edge_begin/edge_end are ignored:
                                   a sample of a graph whose rows would not fit in memory */
   int64_t num_edge_ids;        /* length of edge_ids */
+  uint64_t* edge_orbits;       /* device, uint64[E * tg_edge_orbit_width(L)] or NULL: per-edge orbit counts
+                                  (Table 3's g1..g12) for the same E edges as edge_counts: g1[t], g2[t]
+                                  for t < L, then g3..g12 in blocks of L(L+1)/2 type pairs (the same pair
+                                  order as the row's 4-node blocks) */
 } tg_options;
 
 /* Phases timed through tg_options.phase_ms. */
@@ -151,6 +155,10 @@ size_t tg_num_keys(int L);
 
 /* R(L) = 2L + 3L(L+1) entries per edge row; 0 if L is outside [1, 16]. */
 size_t tg_edge_row_width(int L);
+
+/* 2L + 5L(L+1) entries per edge orbit row (the twelve orbits of Table 3, by
+ * type or type pair); 0 if L is outside [1, 16]. */
+size_t tg_edge_orbit_width(int L);
 
 /* Host.  Decodes a global key into its shape and sorted types; types[3] is
  * 0xFF for 3-node shapes. */
@@ -185,12 +193,35 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
  *   opt             host, or NULL for defaults
  * Canonical edge ids number the edges (i, j), i < j, in (i, j) order.
  * Errors: TG_ERR_INVALID_ARG for a bad edge range, an edge_ids array that
- * is not strictly increasing inside [0, m), or neither output given (nothing
+ * is not strictly increasing inside [0, m), or no output given (nothing
  * written).
  */
 tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
                    int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream);
+
+/* Sparse per-edge output (the Sparse Typed Motif Format subsection: only the
+ * nonzero typed graphlet counts of each edge, with their ids).  Turns dense
+ * per-edge rows into (global key, count) pairs; keys are the dense key rank
+ * of tg_key_encode, already consecutive from 0 (tg_key_decode is the lookup
+ * table).  Two calls on the same arguments:
+ *   pass 1 (keys == NULL): offsets[0..E] receives the exclusive prefix of
+ *     the per-edge nonzero counts (offsets[E] = total) and *total the total
+ *     (host; the call synchronises the stream);
+ *   pass 2 (keys, counts given, capacity >= total): edge e's pairs are
+ *     written at [offsets[e], offsets[e+1]) in row column order.
+ *   rows        device, uint64[E * R(L)] as written by tg_count
+ *   endpoints   device, int32[E * 2] as written by tg_count (the endpoints
+ *               whose types the row is relative to)
+ *   node_types  device, uint8[n]
+ *   offsets     device, int64[E + 1], caller-owned
+ *   keys        device, uint32[capacity] or NULL (pass 1)
+ *   counts      device, uint64[capacity]
+ * Errors: TG_ERR_INVALID_ARG for null pointers or a capacity below the
+ * total (nothing written by pass 2); TG_ERR_UNSUPPORTED_L. */
+tg_status tg_rows_sparse(int64_t E, int L, const uint64_t* rows, const int32_t* endpoints,
+                         const uint8_t* node_types, int64_t* offsets, uint32_t* keys, uint64_t* counts,
+                         int64_t capacity, int64_t* total, hipStream_t stream);
 
 /* Counts many small typed graphs in one call (the batch form of tg_count's
  * global counts, Eq. 17 per graph).  Graph g has n_g = node_off[g+1] -

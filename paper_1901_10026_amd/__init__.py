@@ -93,7 +93,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int), ("model", ctypes.c_void_p), ("tuning", ctypes.c_void_p),
                 ("validate", ctypes.c_int),
                 ("check", ctypes.c_int), ("edge_begin", ctypes.c_int64), ("edge_end", ctypes.c_int64),
-                ("phase_ms", ctypes.c_void_p), ("edge_ids", ctypes.c_void_p), ("num_edge_ids", ctypes.c_int64)]
+                ("phase_ms", ctypes.c_void_p), ("edge_ids", ctypes.c_void_p), ("num_edge_ids", ctypes.c_int64),
+                ("edge_orbits", ctypes.c_void_p)]
 
 
 PHASES = ("prep", "tau", "tables", "schedule", "cycles", "combine", "finalize")
@@ -114,6 +115,8 @@ def lib():
     L.tg_num_keys.argtypes = [i32]
     L.tg_edge_row_width.restype = sz
     L.tg_edge_row_width.argtypes = [i32]
+    L.tg_edge_orbit_width.restype = sz
+    L.tg_edge_orbit_width.argtypes = [i32]
     L.tg_key_decode.restype = i32
     L.tg_key_decode.argtypes = [i32, sz, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint8)]
     L.tg_key_encode.restype = i32
@@ -122,6 +125,8 @@ def lib():
     L.tg_edge_row_key.argtypes = [i32, ctypes.c_uint8, ctypes.c_uint8, sz, ctypes.POINTER(sz)]
     L.tg_count.restype = i32
     L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_rows_sparse.restype = i32
+    L.tg_rows_sparse.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
     L.tg_count_batch.restype = i32
     L.tg_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_tuning_default.restype = None
@@ -175,6 +180,10 @@ def edge_row_width(L: int) -> int:
     return int(lib().tg_edge_row_width(L))
 
 
+def edge_orbit_width(L: int) -> int:
+    return int(lib().tg_edge_orbit_width(L))
+
+
 def key_encode(L: int, shape: int, types) -> int:
     arr = (ctypes.c_uint8 * 4)(*(list(types) + [0] * (4 - len(types))))
     out = ctypes.c_size_t()
@@ -202,7 +211,7 @@ def _stream_handle(torch, device):
 
 def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedule="degree", validate=False,
           check=True, edge_range=None, edge_ids=None, global_counts=True, model=None, out_global=None, out_edges=None,
-          phase_ms=None, tuning=None):
+          out_orbits=None, phase_ms=None, tuning=None):
     """Counts every typed 3/4-node graphlet of one graph with tg_count.
 
     row_ptr, col_idx (int32) and types (uint8) are CUDA (HIP) tensors on the
@@ -212,7 +221,9 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     edge_range (default all), or, when edge_ids (a strictly increasing int64
     device tensor of canonical edge ids) is given, exactly those edges.
     With global_counts=False (rows only) the global result is None and only
-    those edges go through the per-edge step.
+    those edges go through the per-edge step.  out_orbits, a uint64 device
+    tensor [E, edge_orbit_width(L)], receives the orbit counts g1..g12 of
+    the same edges.
     """
     import torch
     dev = row_ptr.device
@@ -233,8 +244,8 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     R = edge_row_width(L)
     if K == 0:
         raise TGError(4, "L must be in [1, 16]")
-    if not global_counts and not per_edge:
-        raise ValueError("rows-only counting needs per_edge=True")
+    if not global_counts and not per_edge and out_orbits is None:
+        raise ValueError("rows-only counting needs per_edge=True or out_orbits")
     g = None
     if global_counts:
         g = out_global if out_global is not None else torch.empty(K, dtype=torch.uint64, device=dev)
@@ -254,6 +265,11 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     opt.edge_end = e1
     times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
     opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    if out_orbits is not None:
+        if out_orbits.dtype != torch.uint64 or not out_orbits.is_contiguous() or out_orbits.device != dev or \
+                out_orbits.numel() < max(e1 - e0, 0) * edge_orbit_width(L):
+            raise ValueError("out_orbits must be a contiguous uint64 tensor of [E, edge_orbit_width(L)] on the device")
+        opt.edge_orbits = out_orbits.data_ptr() if out_orbits.numel() else None
     if edge_ids is not None:
         opt.edge_ids = edge_ids.data_ptr() if edge_ids.numel() else None
         opt.num_edge_ids = edge_ids.numel()
@@ -268,6 +284,29 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     if times is not None:
         phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
     return g, rows, ends
+
+
+def rows_sparse(rows, endpoints, types, L):
+    """Nonzero entries of per-edge rows as (key, count) pairs with
+    tg_rows_sparse: returns (offsets int64 [E+1], keys int32-stored uint32
+    [total], counts uint64 [total]) as device tensors; edge e's pairs are
+    keys/counts[offsets[e]:offsets[e+1]]."""
+    import torch
+    dev = rows.device
+    E = rows.shape[0]
+    offsets = torch.empty(E + 1, dtype=torch.int64, device=dev)
+    total = ctypes.c_int64(0)
+    st = _stream_handle(torch, dev)
+    _check(lib().tg_rows_sparse(E, L, rows.data_ptr() if E else None, endpoints.data_ptr() if E else None,
+                                types.data_ptr() if types.numel() else None, offsets.data_ptr(), None, None, 0,
+                                ctypes.byref(total), st))
+    n = int(total.value)
+    keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    counts = torch.empty(max(n, 1), dtype=torch.uint64, device=dev)
+    _check(lib().tg_rows_sparse(E, L, rows.data_ptr() if E else None, endpoints.data_ptr() if E else None,
+                                types.data_ptr() if types.numel() else None, offsets.data_ptr(), keys.data_ptr(),
+                                counts.data_ptr(), max(n, 1), ctypes.byref(total), st))
+    return offsets, keys[:n], counts[:n]
 
 
 def key_offsets(L_per_graph):

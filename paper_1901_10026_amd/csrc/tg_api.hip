@@ -14,6 +14,7 @@
 #include "tg_kernels.hip"
 #include "tg_batch.hip"
 #include "tg_mlp.hip"
+#include "tg_sparse.hip"
 
 namespace {
 
@@ -263,7 +264,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31))
     return fail(TG_ERR_INVALID_ARG, "n and nnz must be in [0, 2^31)");
   if (n * (int64_t)L >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "n * L must be below 2^31");
-  if (!rp || (!global_counts && !edge_counts) || (nnz > 0 && !ci) || (n > 0 && !ty))
+  if (!rp || (!global_counts && !edge_counts && !opt.edge_orbits) || (nnz > 0 && !ci) || (n > 0 && !ty))
     return fail(TG_ERR_INVALID_ARG, "null input or output pointer");
   if (nnz % 2) return fail(TG_ERR_INVALID_GRAPH, "nnz is odd: some edge is stored in one direction only");
   if (opt.schedule < TG_SCHED_NONE || opt.schedule > TG_SCHED_LEARNED)
@@ -663,6 +664,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.c4_rows = slot_rows ? 0 : m;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
   A.edge_ids = ids; A.n_edge_ids = nids;
+  A.edge_orbits = opt.edge_orbits;
   A.gacc_in_lds = (global_counts && K <= TG_GACC_MAX_KEYS) ? 1 : 0;
   A.work = nullptr;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
@@ -998,6 +1000,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.c4_rows = 0;
   A.edge_counts = nullptr; A.edge_begin = 0; A.edge_end = 0; A.global_sums = gsink;
   A.edge_ids = nullptr; A.n_edge_ids = 0;
+  A.edge_orbits = nullptr;
   A.gacc_in_lds = 0;
   A.work = work_by_edge;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
@@ -1153,6 +1156,7 @@ void tg_options_default(tg_options* opt) {
   opt->phase_ms = nullptr;
   opt->edge_ids = nullptr;
   opt->num_edge_ids = 0;
+  opt->edge_orbits = nullptr;
 }
 
 void tg_tuning_default(tg_tuning* t) {
@@ -1190,6 +1194,50 @@ tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot
 size_t tg_num_keys(int L) { return (L < 1 || L > 16) ? 0 : (size_t)nkeys(L); }
 
 size_t tg_edge_row_width(int L) { return (L < 1 || L > 16) ? 0 : (size_t)(2 * L + 3 * L * (L + 1)); }
+
+tg_status tg_rows_sparse(int64_t E, int L, const uint64_t* rows, const int32_t* endpoints,
+                         const uint8_t* node_types, int64_t* offsets, uint32_t* keys, uint64_t* counts,
+                         int64_t capacity, int64_t* total, hipStream_t stream) {
+  try {
+    if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+    if (E < 0 || !offsets || (E > 0 && (!rows || !endpoints || !node_types)))
+      return fail(TG_ERR_INVALID_ARG, "null input or offsets pointer");
+    const int R = (int)tg_edge_row_width(L);
+    hipStream_t st = stream;
+    if (!keys) {
+      // pass 1: nonzero counts and their exclusive prefix
+      if (!total) return fail(TG_ERR_INVALID_ARG, "pass 1 needs a total pointer");
+      keep_pool_cached();
+      Scratch S(st);
+      int64_t* cnt;
+      TG_HIP(S.get(&cnt, std::max<int64_t>(E, 1)));
+      if (E > 0) {
+        k_sparse_count<<<grid_for(E, 4, 16384), 256, 0, st>>>(E, R, rows, cnt);
+        TG_LAUNCHED("k_sparse_count");
+      }
+      if (tg_status s2 = scan(S, st, E, (const int64_t*)cnt, offsets)) return s2;
+      TG_HIP(hipMemcpyAsync(total, offsets + E, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+      return TG_OK;
+    }
+    // pass 2: the pairs, at the offsets of pass 1
+    if (!counts) return fail(TG_ERR_INVALID_ARG, "null counts pointer");
+    int64_t need = 0;
+    TG_HIP(hipMemcpyAsync(&need, offsets + E, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (need > capacity) return fail(TG_ERR_INVALID_ARG, "keys/counts capacity below the number of nonzeros");
+    if (E > 0) {
+      k_sparse_fill<<<grid_for(E, 4, 16384), 256, 0, st>>>(E, L, rows, endpoints, node_types, offsets, keys, counts);
+      TG_LAUNCHED("k_sparse_fill");
+    }
+    if (total) *total = need;
+    return TG_OK;
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, ex.what());
+  }
+}
+
+size_t tg_edge_orbit_width(int L) { return (L < 1 || L > 16) ? 0 : (size_t)(2 * L + 5 * L * (L + 1)); }
 
 tg_status tg_key_encode(int L, int shape, const uint8_t types[4], size_t* key) {
   if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");

@@ -318,19 +318,23 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
   const uint64_t* Uj = A.Un + (int64_t)j * LL;
   const uint64_t* Pi = A.Pn + (int64_t)i * LL;
   const uint64_t* Pj = A.Pn + (int64_t)j * LL;
-  uint64_t* row = nullptr;
-  if (A.edge_counts) {
+  // output position of this edge (listed ids or range), -1 if none
+  int64_t opos = -1;
+  if (A.edge_counts || A.edge_orbits) {
     if (A.edge_ids) {
       int64_t lo = 0, hi = A.n_edge_ids;  // first id >= e
       while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
         if (A.edge_ids[mid] < e) lo = mid + 1; else hi = mid;
       }
-      if (lo < A.n_edge_ids && A.edge_ids[lo] == e) row = A.edge_counts + lo * R;
+      if (lo < A.n_edge_ids && A.edge_ids[lo] == e) opos = lo;
     } else if (e >= A.edge_begin && e < A.edge_end) {
-      row = A.edge_counts + (int64_t)(e - A.edge_begin) * R;
+      opos = e - A.edge_begin;
     }
   }
+  uint64_t* row = (A.edge_counts && opos >= 0) ? A.edge_counts + opos * R : nullptr;
+  // orbit row: g1[t], g2[t], then g3..g12 in blocks of P
+  uint64_t* orow = (A.edge_orbits && opos >= 0) ? A.edge_orbits + opos * (2 * L + 10 * P) : nullptr;
   auto gadd = [&](int64_t key, int64_t v) {
     if (v == 0) return;
     if (gacc) atomicAdd((unsigned long long*)&gacc[key], (unsigned long long)v);
@@ -342,6 +346,7 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
   for (int c = tid; c < L; c += TSIZE) {
     const int64_t wedge = Si(c) + Sj(c), tri = Tn(c);
     if (row) { row[c] = (uint64_t)wedge; row[L + c] = (uint64_t)tri; }
+    if (orow) { orow[c] = (uint64_t)wedge; orow[L + c] = (uint64_t)tri; }
     gadd(key_of(L, 0, pi, pj, c, 0), wedge);
     gadd(key_of(L, 1, pi, pj, c, 0), tri);
   }
@@ -388,6 +393,10 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
       g5 = Si(t) * Si(u) + Sj(t) * Sj(u) - g7;
       g9 = Tn(t) * (Si(u) + Sj(u)) + Tn(u) * (Si(t) + Sj(t)) - g10;
       g11 = Tn(t) * Tn(u) - g12;
+    }
+    if (orow) {
+      const int64_t g[10] = {g3, g4, g5, g6, g7, g8, g9, g10, g11, g12};
+      for (int q = 0; q < 10; ++q) orow[2 * L + q * P + p] = (uint64_t)g[q];
     }
     const int64_t h[6] = {g3 + g4, g5, g6, g7 + g8 + g9, g10 + g11, g12};  // Eqs. 11-16
     for (int s = 0; s < 6; ++s) {

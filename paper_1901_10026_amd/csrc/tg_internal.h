@@ -82,6 +82,7 @@ struct EdgeArgs {
   uint64_t* edge_counts;  // rows for [edge_begin, edge_end) or for edge_ids, or null
   int64_t edge_begin, edge_end;
   const int64_t* edge_ids;  // sorted sample of edges whose rows are written, or null
+  uint64_t* edge_orbits;    // orbit rows g1..g12 (2L + 10P per edge) for the same edges, or null
   int64_t n_edge_ids;
   uint64_t* global_sums;  // K(L)
   int gacc_in_lds;
