@@ -171,6 +171,38 @@ def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=5):
     return res
 
 
+def outputs_leg(tg, g, rp, ci, ty, out_g, out_e, steps=3):
+    """The two extra per-edge outputs on the same graph: orbit rows (g1..g12
+    per type or type pair) written beside the graphlet rows, and the sparse
+    (key, count) form of the graphlet rows."""
+    import torch
+    dev = rp.device
+    W = tg.edge_orbit_width(g.L)
+    orb = torch.empty((g.m, W), dtype=torch.uint64, device=dev)
+    tg.count(rp, ci, ty, g.L, out_global=out_g, out_edges=out_e, out_orbits=orb)
+    orbit_ms = time_count(tg, g, rp, ci, ty, out_g, out_e, steps, out_orbits=orb)
+    del orb
+    log(f"graphlet + orbit rows: {orbit_ms:.1f} ms")
+    _, _, ends = tg.count(rp, ci, ty, g.L, out_global=out_g, out_edges=out_e, endpoints=True)
+    off, keys, cnts = tg.rows_sparse(out_e, ends, ty, g.L)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(steps):
+        off, keys, cnts = tg.rows_sparse(out_e, ends, ty, g.L)
+    s1.record()
+    torch.cuda.synchronize()
+    sparse_ms = s0.elapsed_time(s1) / steps
+    pairs = int(keys.numel())
+    per_edge = torch.diff(off)
+    res = {"orbit_width": W, "count_with_orbits_ms": orbit_ms, "sparse_ms": sparse_ms, "sparse_pairs": pairs,
+           "sparse_pairs_per_edge_mean": pairs / g.m, "sparse_pairs_per_edge_max": int(per_edge.max().item()),
+           "sparse_bytes": pairs * 12 + (g.m + 1) * 8, "dense_row_bytes": g.m * out_e.shape[1] * 8}
+    log(f"sparse rows: {pairs} pairs ({pairs / g.m:.1f} per edge), {sparse_ms:.1f} ms")
+    return res
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -211,6 +243,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs leg")
+    ap.add_argument("--no-outputs", action="store_true", help="skip the orbit-row and sparse-row leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -302,6 +335,8 @@ def main():
     }
     if not args.no_compare:
         rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)
+    if not args.no_outputs:
+        rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
     if not args.no_batch:
         rec["batch"] = batch_leg(tg, dev)
     if not args.no_cpu_baseline:
