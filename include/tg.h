@@ -107,6 +107,11 @@ typedef struct {
   int32_t batch_variant[9];   /* tg_count_batch: kernel variant per size class W = ceil(n/64)
                                  (0: wavefront, 64 nodes; 1: wavefront, 128; 2: workgroup, 128;
                                  3: wavefront, 256; 4: workgroup, 256; 5: workgroup, 512) */
+  int32_t clique_team_max;    /* tg_count_global: edges whose 4-clique intersection loop is at most this
+                                 long (<= 64) use a 16-lane team ... */
+  int32_t clique_wave_max;    /* ... at most this long (<= 1024) a wavefront, longer ones a workgroup */
+  int32_t clique_lds_ids;     /* tg_count_global: common higher neighbours kept in LDS by a workgroup
+                                 team (<= 4096); more go to global scratch */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */
@@ -199,6 +204,29 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
 tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
                    int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream);
+
+/* Global counts only, every instance counted a fixed number of times instead
+ * of once per edge (the Global Typed Graphlet Counts section notes that an
+ * ordering makes a global-only count cheaper).  Non-induced typed counts of
+ * the eight shape patterns are summed per type multiset -- 4-cliques once
+ * from their two lowest nodes in degree order, 4-cycles from degree-ordered
+ * wedges, the rest from typed degrees and typed common-neighbour counts --
+ * and converted into induced counts.  The result equals tg_count's global
+ * counts.
+ *   arguments as for tg_count; global_counts (device, uint64[tg_num_keys(L)])
+ *   must not be NULL
+ *   opt             host, or NULL: validate, check, phase_ms and tuning (its
+ *                   4-cycle fields) apply; edge ranges, edge_ids, schedule,
+ *                   model and edge_orbits are ignored
+ * Every true count, and every non-induced pattern total (for instance the
+ * number of 4-paths including those inside denser subgraphs), must be below
+ * 2^63.  With check set, the call synchronises and reports
+ * TG_ERR_INTERNAL if a sum is inconsistent (a 4-cycle or tailed-triangle sum
+ * odd, a triangle sum not a multiple of 3, or a negative result).
+ */
+tg_status tg_count_global(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                          const uint8_t* node_types, int L, uint64_t* global_counts, const tg_options* opt,
+                          hipStream_t stream);
 
 /* Sparse per-edge output (the Sparse Typed Motif Format subsection: only the
  * nonzero typed graphlet counts of each edge, with their ids).  Turns dense

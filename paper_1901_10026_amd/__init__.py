@@ -61,10 +61,11 @@ class Tuning(ctypes.Structure):
                 ("combine_grid", ctypes.c_int32), ("wg_grid", ctypes.c_int32), ("c4_footprint_mb", ctypes.c_int32),
                 ("c4_group_kwedges", ctypes.c_int32), ("c4_chunk", ctypes.c_int32),
                 ("c4_hash_ratio", ctypes.c_int32), ("c4_slot_budget_mb", ctypes.c_int32), ("c4_slices", ctypes.c_int32),
-                ("batch_variant", ctypes.c_int32 * 9)]
+                ("batch_variant", ctypes.c_int32 * 9), ("clique_team_max", ctypes.c_int32),
+                ("clique_wave_max", ctypes.c_int32), ("clique_lds_ids", ctypes.c_int32)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
                "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
-               "c4_slices")
+               "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
@@ -125,6 +126,8 @@ def lib():
     L.tg_edge_row_key.argtypes = [i32, ctypes.c_uint8, ctypes.c_uint8, sz, ctypes.POINTER(sz)]
     L.tg_count.restype = i32
     L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_count_global.restype = i32
+    L.tg_count_global.argtypes = [i64, i64, vp, vp, vp, i32, vp, ctypes.POINTER(_Options), vp]
     L.tg_rows_sparse.restype = i32
     L.tg_rows_sparse.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
     L.tg_count_batch.restype = i32
@@ -284,6 +287,40 @@ def count(row_ptr, col_idx, types, L, *, per_edge=True, endpoints=False, schedul
     if times is not None:
         phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
     return g, rows, ends
+
+
+def count_global(row_ptr, col_idx, types, L, *, validate=False, check=True, out=None, phase_ms=None, tuning=None):
+    """Global typed-graphlet counts only, with tg_count_global (every instance
+    counted a fixed number of times instead of once per edge).  Same inputs
+    as count(); returns the uint64 [K(L)] device tensor."""
+    import torch
+    dev = row_ptr.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (types, torch.uint8)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("row_ptr/col_idx must be contiguous int32 and types contiguous uint8 on one device")
+    K = num_keys(L)
+    if K == 0:
+        raise TGError(4, "L must be in [1, 16]")
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    g = out if out is not None else torch.empty(K, dtype=torch.uint64, device=dev)
+    if g.dtype != torch.uint64 or not g.is_contiguous() or g.device != dev or g.numel() < K:
+        raise ValueError("out must be a contiguous uint64 tensor of K(L) entries on the inputs' device")
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
+    opt.validate = 1 if validate else 0
+    opt.check = 1 if check else 0
+    times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
+    opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    st = lib().tg_count_global(n, nnz, row_ptr.data_ptr(), col_idx.data_ptr() if nnz else None,
+                               types.data_ptr() if n else None, L, g.data_ptr(), ctypes.byref(opt),
+                               _stream_handle(torch, dev))
+    _check(st)
+    if times is not None:
+        phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
+    return g
 
 
 def rows_sparse(rows, endpoints, types, L):

@@ -15,6 +15,7 @@
 #include "tg_batch.hip"
 #include "tg_mlp.hip"
 #include "tg_sparse.hip"
+#include "tg_global.hip"
 
 namespace {
 
@@ -202,8 +203,10 @@ tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, con
 
 // Scratch allocation, preprocessing, typed triangles and node tables: the
 // part of the pipeline shared by counting and by cost-model training.
+// Without `tables` (global counts counted once) the node tables P, U and the
+// per-edge 4-cycle counters are neither allocated nor filled.
 tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
-                        const uint8_t* ty, int L, Work& W, PhaseTimer* timer) {
+                        const uint8_t* ty, int L, Work& W, PhaseTimer* timer, bool tables = true) {
   const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
   TG_HIP(S.get(&W.deg, n));
   TG_HIP(S.get(&W.D, n * L));
@@ -220,9 +223,12 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   TG_HIP(S.get(&W.es_hi, m));
   TG_HIP(S.get(&W.out_col, m));
   TG_HIP(S.get(&W.tau, m * L));
-  TG_HIP(S.get(&W.Pn, n * LL));
-  TG_HIP(S.get(&W.Un, n * LL));
-  TG_HIP(S.get(&W.C4, m * P));
+  W.Pn = W.Un = W.C4 = nullptr;
+  if (tables) {
+    TG_HIP(S.get(&W.Pn, n * LL));
+    TG_HIP(S.get(&W.Un, n * LL));
+    TG_HIP(S.get(&W.C4, m * P));
+  }
   TG_HIP(S.get(&W.elist, m));
   TG_HIP(S.get(&W.nlist, n));
   TG_HIP(S.get(&W.counters, 512));
@@ -247,19 +253,43 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
   TG_LAUNCHED("k_tau<64>");
   if (timer) timer->mark(TG_PHASE_TABLES);
-  k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D, W.tau,
-                                                                                     W.s2e, W.Pn, W.Un);
-  TG_LAUNCHED("k_node_tables");
+  if (tables) {
+    k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D,
+                                                                                       W.tau, W.s2e, W.Pn, W.Un);
+    TG_LAUNCHED("k_node_tables");
+  }
 
   return TG_OK;
 }
 
+// Host-side choice of LDS copies for the key sums [k0, k0 + nk) of one kernel
+// within `budget` bytes (no copies: straight global atomics).
+GAcc make_gacc(uint64_t* g, int64_t k0, int64_t nk, int64_t budget) {
+  const int64_t c = budget / std::max<int64_t>(1, nk * (int64_t)sizeof(uint64_t));
+  return GAcc{g, k0, nk, (int)std::min<int64_t>(8, std::max<int64_t>(0, c))};
+}
+
+size_t gacc_bytes(const GAcc& a) { return (size_t)a.copies * a.nk * sizeof(uint64_t); }
+
+// once: global counts only, every instance counted a fixed number of times
+// (tg_count_global); otherwise per-edge counting with Eq. 17 (tg_count).
 tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L,
                      uint64_t* global_counts, uint64_t* edge_counts, int32_t* edge_endpoints,
-                     const tg_options* opt_in, hipStream_t st) {
+                     const tg_options* opt_in, hipStream_t st, bool once = false) {
   tg_options opt;
   tg_options_default(&opt);
   if (opt_in) opt = *opt_in;
+  if (once) {
+    if (!global_counts) return fail(TG_ERR_INVALID_ARG, "null global_counts");
+    edge_counts = nullptr;
+    edge_endpoints = nullptr;
+    opt.edge_orbits = nullptr;
+    opt.edge_ids = nullptr;
+    opt.num_edge_ids = 0;
+    opt.edge_begin = 0;
+    opt.edge_end = -1;
+    opt.schedule = TG_SCHED_DEGREE;
+  }
   if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
   if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31))
     return fail(TG_ERR_INVALID_ARG, "n and nnz must be in [0, 2^31)");
@@ -314,7 +344,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (m == 0) return TG_OK;
 
   Work W;
-  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer)) return s;
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once)) return s;
 
   // ---- schedule: edge classes and cost buckets, node tiers
   timer.mark(TG_PHASE_SCHEDULE);
@@ -340,9 +370,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // [264] max |T| of workgroup-class edges, [272] divisibility flag
   int32_t* cnt = W.counters;
   TG_HIP(hipMemsetAsync(cnt, 0, 512 * sizeof(int32_t), st));
-  k_edge_bin_count<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
-                                                                   W.tau, L, bp, pred, cnt, (uint32_t*)(cnt + 264));
-  TG_LAUNCHED("k_edge_bin_count");
+  if (!once) {
+    k_edge_bin_count<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
+                                                                     W.tau, L, bp, pred, cnt,
+                                                                     (uint32_t*)(cnt + 264));
+    TG_LAUNCHED("k_edge_bin_count");
+  }
   k_node_tier_count<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256);
   TG_LAUNCHED("k_node_tier_count");
   k_max_degree<<<grid_for(n, 256, 1024), 256, 0, st>>>(n, W.deg, cnt + 268);
@@ -368,9 +401,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // LDS counters (a window holds at most one chunk of wedges, each credit at
   // most the maximum degree)
   TG_HIP(hipMemcpyAsync(cnt, cur, 264 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  k_edge_bin_scatter<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
-                                                                     W.tau, L, bp, pred, cnt, W.elist);
-  TG_LAUNCHED("k_edge_bin_scatter");
+  if (!once) {
+    k_edge_bin_scatter<<<grid_for(sel_count, 256, 8192), 256, 0, st>>>(sel_count, sel, sel_e0, W.ei, W.ej, W.deg,
+                                                                       W.tau, L, bp, pred, cnt, W.elist);
+    TG_LAUNCHED("k_edge_bin_scatter");
+  }
   k_node_tier_scatter<<<grid_for(n, 256, 8192), 256, 0, st>>>(n, W.wedge_work, cnt + 256, W.nlist);
   TG_LAUNCHED("k_node_tier_scatter");
 
@@ -382,7 +417,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // (consecutive wedges then credit consecutive rows), folded into per-edge
   // rows afterwards; else straight to per-edge rows.
   const int64_t c4_width = c4_wide ? 8 : 4;
-  const bool slot_rows = nnz * P * c4_width <= ((int64_t)std::max(0, tune.c4_slot_budget_mb) << 20);
+  const bool slot_rows = !once && nnz * P * c4_width <= ((int64_t)std::max(0, tune.c4_slot_budget_mb) << 20);
   const int32_t* s2x = slot_rows ? nullptr : W.s2e;
   const int64_t crows = slot_rows ? nnz : m;  // counters are C4[p * crows + row]
   uint64_t* C4w_t = W.C4;
@@ -394,26 +429,40 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                                                  0);
     C4w_t = c4s;
     C4n_t = reinterpret_cast<uint32_t*>(c4s);
-  } else {
+  } else if (!once) {
     k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
   }
   TG_LAUNCHED("k_fill_u64");
-  if (n_t1 > 0) {
+  // once: the 4-cycle keys, summed twice per cycle
+  const int64_t C3k = per_shape(L, 3), C4k = per_shape(L, 4);
+  const GAcc ga_cyc = make_gacc(global_counts, 2 * C3k + 2 * C4k, C4k, 8 << 10);
+  const GAcc ga_cyc_g = make_gacc(global_counts, 2 * C3k + 2 * C4k, C4k, 16 << 10);
+  if (once && n_t1 > 0) {
+    k_c4_hash<1, 8, uint32_t, true><<<grid_for(n_t1, 4, 4096), 256, gacc_bytes(ga_cyc), st>>>(
+        n_t1, W.nlist + cur[257], rp, ci, W.deg, ty, L, nullptr, nullptr, 0, ga_cyc);
+    TG_LAUNCHED("k_c4_hash<1, glob>");
+  }
+  if (once && n_t2 > 0) {
+    k_c4_hash<4, 12, uint32_t, true><<<grid_for(n_t2, 1, 2048), 256, gacc_bytes(ga_cyc), st>>>(
+        n_t2, W.nlist + cur[258], rp, ci, W.deg, ty, L, nullptr, nullptr, 0, ga_cyc);
+    TG_LAUNCHED("k_c4_hash<4, glob>");
+  }
+  if (!once && n_t1 > 0) {
     if (c4_wide)
       k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4w_t, crows);
+                                                                         L, s2x, C4w_t, crows, GAcc{});
     else
       k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4n_t, crows);
+                                                                         L, s2x, C4n_t, crows, GAcc{});
     TG_LAUNCHED("k_c4_hash<1>");
   }
-  if (n_t2 > 0) {
+  if (!once && n_t2 > 0) {
     if (c4_wide)
       k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4w_t, crows);
+                                                                          ty, L, s2x, C4w_t, crows, GAcc{});
     else
       k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4n_t, crows);
+                                                                          ty, L, s2x, C4n_t, crows, GAcc{});
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -608,14 +657,19 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       // wedge); hashed groups always by a fill of their rows
       const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 256;
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
+      // phase 3 (once): at most a few resident waves of workgroups, so that
+      // few LDS key copies are flushed
+      const unsigned grid3 = std::min<unsigned>(grid, 4096u);
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
-  k_c4_group<PH, T, HF, HS><<<grid, 256, (PH == 1 && STG) ? xu_lds : 0, st>>>(                                     \
+  k_c4_group<PH, T, HF, HS><<<PH == 3 ? grid3 : grid, 256,                                                         \
+                              PH == 3 ? gacc_bytes(ga_cyc_g) : ((PH == 1 && STG) ? xu_lds : 0), st>>>(             \
       Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, \
-      s2x, C4P, crows, STG)
+      s2x, C4P, crows, STG, ga_cyc_g)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
-    TG_C4_GROUP(1, T, HF, HS, C4P, STG);                                                                           \
+    if (once) TG_C4_GROUP(3, T, HF, HS, C4P, STG);                                                                 \
+    else TG_C4_GROUP(1, T, HF, HS, C4P, STG);                                                                      \
     if (HS) {                                                                                                      \
       k_fill_u32<<<grid_for(rows, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(hkeys), rows,             \
                                                              0xffffffffu);                                         \
@@ -652,6 +706,73 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     else
       k_c4_fold<uint32_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, nnz, W.es_lo, W.es_hi, C4n_t, C4n);
     TG_LAUNCHED("k_c4_fold");
+  }
+
+  if (once) {
+    // ---- the other shapes, each instance a fixed number of times
+    timer.mark(TG_PHASE_COMBINE);
+    const int64_t kbudget = 32 << 10;
+    const GAcc ga_all = make_gacc(global_counts, 0, K, kbudget);
+    k_glob_nodes<<<grid_for(n, 16, 8192), 256, gacc_bytes(ga_all), st>>>(n, W.deg, W.D, ty, L, ga_all);
+    TG_LAUNCHED("k_glob_nodes");
+    k_glob_edges<<<grid_for(m, 16, 8192), 256, gacc_bytes(ga_all), st>>>(m, W.ei, W.ej, W.D, W.tau, ty, L, ga_all);
+    TG_LAUNCHED("k_glob_edges");
+    // 4-cliques: edges in three classes by intersection length
+    int32_t* kc = cnt + 280;
+    TG_HIP(hipMemsetAsync(kc, 0, 8 * sizeof(int32_t), st));
+    const int team_max = std::min(64, std::max(0, tune.clique_team_max));
+    const int2 lim = make_int2(team_max, std::min(1024, std::max(team_max, tune.clique_wave_max)));
+    const int tcap = std::min(K4Cap<256>::value, std::max(0, tune.clique_lds_ids));
+    k_k4_class_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim, kc);
+    TG_LAUNCHED("k_k4_class_count");
+    int32_t hk[8];
+    TG_HIP(hipMemcpyAsync(hk, kc, sizeof(hk), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    const int32_t kcur[4] = {0, hk[0], hk[0] + hk[1], 0};
+    TG_HIP(hipMemcpyAsync(kc + 4, kcur, 3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    k_k4_class_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim,
+                                                               kc + 4, W.elist);
+    TG_LAUNCHED("k_k4_class_scatter");
+    const GAcc ga_k4 = make_gacc(global_counts, 2 * C3k + 5 * C4k, C4k, 16 << 10);
+    if (hk[0] > 0) {
+      k_glob_k4<16><<<grid_for(hk[0], 16, 8192), 256, k4_lds_bytes<16>(ga_k4), st>>>(
+          hk[0], W.elist, W.ei, W.ej, rp, ci, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0, ga_k4);
+      TG_LAUNCHED("k_glob_k4<16>");
+    }
+    if (hk[1] > 0) {
+      k_glob_k4<64><<<grid_for(hk[1], 4, 8192), 256, k4_lds_bytes<64>(ga_k4), st>>>(
+          hk[1], W.elist + kcur[1], W.ei, W.ej, rp, ci, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0,
+          ga_k4);
+      TG_LAUNCHED("k_glob_k4<64>");
+    }
+    if (hk[2] > 0) {
+      const unsigned grid = grid_for(hk[2], 1, 2048);
+      int32_t* t_over = nullptr;
+      int64_t t_cap = 0;
+      if (hk[3] > tcap) {
+        t_cap = hk[3];
+        TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
+      }
+      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej, rp, ci,
+                                                                   W.deg, ty, W.out_off, W.out_col, W.tau, L, tcap,
+                                                                   t_over, t_cap, ga_k4);
+      TG_LAUNCHED("k_glob_k4<256>");
+    }
+    timer.mark(TG_PHASE_FINALIZE);
+    int32_t* flag = cnt + 272;
+    TG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+    k_glob_finalize<<<grid_for(std::max(C3k, C4k), 256), 256, 0, st>>>(global_counts, L, flag);
+    TG_LAUNCHED("k_glob_finalize");
+    timer.mark(TG_NUM_PHASES);
+    if (opt.check) {
+      int32_t hf = 0;
+      TG_HIP(hipMemcpyAsync(&hf, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+      if (hf) return fail(TG_ERR_INTERNAL, "a non-induced key sum is inconsistent (odd, not a multiple of 3, or "
+                                           "larger than its pattern total)");
+    }
+    timer.finish();
+    return TG_OK;
   }
 
   // ---- per-edge combine
@@ -1175,6 +1296,9 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_slices = 1;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
   for (int w = 0; w <= 8; ++w) t->batch_variant[w] = v[w];
+  t->clique_team_max = 64;
+  t->clique_wave_max = 1024;
+  t->clique_lds_ids = 4096;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
@@ -1305,6 +1429,18 @@ tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t
   try {
     return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, edge_counts, edge_endpoints, opt,
                       stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+tg_status tg_count_global(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                          const uint8_t* node_types, int L, uint64_t* global_counts, const tg_options* opt,
+                          hipStream_t stream) {
+  try {
+    return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, nullptr, nullptr, opt, stream, true);
   } catch (const std::exception& ex) {
     return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
   } catch (...) {

@@ -90,4 +90,36 @@ struct EdgeArgs {
   int thash_ok;           // node ids fit the packed (id << 4 | type) hash slots
 };
 
+// Global key sums of one kernel: keys [k0, k0 + nk) are summed in `copies`
+// LDS copies (lane l adds to copy l % copies) and flushed once per
+// workgroup; other keys, or all keys when copies == 0, go straight to g.
+struct GAcc {
+  uint64_t* g;  // global key vector
+  int64_t k0, nk;
+  int copies;
+};
+
+__device__ __forceinline__ void gacc_init(const GAcc& a, uint64_t* s) {
+  for (int64_t x = threadIdx.x; x < (int64_t)a.copies * a.nk; x += blockDim.x) s[x] = 0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void gacc_add(const GAcc& a, uint64_t* s, int64_t key, uint64_t v) {
+  const int64_t r = key - a.k0;
+  if (a.copies && r >= 0 && r < a.nk)
+    atomicAdd((unsigned long long*)&s[(int64_t)(lane() % a.copies) * a.nk + r], (unsigned long long)v);
+  else
+    atomicAdd((unsigned long long*)&a.g[key], (unsigned long long)v);
+}
+
+__device__ __forceinline__ void gacc_flush(const GAcc& a, uint64_t* s) {
+  if (!a.copies) return;
+  __syncthreads();
+  for (int64_t x = threadIdx.x; x < a.nk; x += blockDim.x) {
+    uint64_t v = 0;
+    for (int c = 0; c < a.copies; ++c) v += s[(int64_t)c * a.nk + x];
+    if (v) atomicAdd((unsigned long long*)&a.g[a.k0 + x], (unsigned long long)v);
+  }
+}
+
 }  // namespace tg

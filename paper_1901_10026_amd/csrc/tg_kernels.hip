@@ -380,12 +380,17 @@ __device__ __forceinline__ void credit_wedge(C4T* __restrict__ C4, int64_t crows
 
 // One team (NWAVES wavefronts) per node x, middle counts in LDS hash tables:
 // kw/tw keyed by w (totals), kt/ct keyed by w*L+t (typed counts).
-template <int NWAVES, int LOG2CAP, class C4T>
+// GLOB: instead of crediting edges, every cycle x-u-w-u' adds its count to the
+// global 4-cycle key of {phi_x, phi_u, phi_w, phi_u'}; each cycle is reached
+// through both of its wedges at x, so the key sums are twice the counts.
+template <int NWAVES, int LOG2CAP, class C4T, bool GLOB = false>
 __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* __restrict__ list,
                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  int L, const int32_t* __restrict__ s2e,
-                                                 C4T* __restrict__ C4, int64_t crows) {
+                                                 C4T* __restrict__ C4, int64_t crows, GAcc ga) {
+  extern __shared__ uint64_t hash_gacc[];
+  if (GLOB) gacc_init(ga, hash_gacc);
   constexpr int CAP = 1 << LOG2CAP;
   constexpr int TEAMS = 4 / NWAVES;
   __shared__ int32_t kw_all[TEAMS][CAP];
@@ -430,7 +435,12 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
             const int phw = ty[w];
             for (int t = 0; t < L; ++t) {
               const int g = hash_find(kt, LOG2CAP, w * L + t);
-              credit_wedge(C4, crows, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u);
+              if (GLOB) {
+                const int64_t c = (int64_t)(g >= 0 ? ct[g] : 0u) - (t == phu ? 1 : 0);
+                if (c > 0) gacc_add(ga, hash_gacc, key_of(L, 4, phx, phu, phw, t), (uint64_t)c);
+              } else {
+                credit_wedge(C4, crows, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u);
+              }
             }
           }
         }
@@ -438,13 +448,16 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
       team_sync<NWAVES>();
     }
   }
+  if (GLOB) gacc_flush(ga, hash_gacc);
 }
 
 // Nodes with large wedge work: a group of nodes at a time, each with a dense
 // per-node array of typed middle counts in global memory, one row of RW
 // 32-bit words per far end w (RW = CS words of 32-bit counts, or CS / 2
 // words holding two 16-bit counts when no count can exceed 65535, i.e. the
-// maximum degree is below 65536).  Phase 0 counts, phase 1 credits, phase 2
+// maximum degree is below 65536).  Phase 0 counts, phase 1 credits (phase 3
+// instead adds each cycle to its global 4-cycle key, as k_c4_hash does with
+// GLOB), phase 2
 // clears; kernel boundaries order the phases.
 //
 // Work mapping: the group's wedges x-u-w, in (node, slot of x's row,
@@ -538,11 +551,14 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
-                                                  int64_t crows, int stage_xu) {
+                                                  int64_t crows, int stage_xu, GAcc ga) {
   // credits to the edges (x, u) of the window's 64 slots are summed in LDS
   // first (stage_xu: L <= 8 and every sum fits 32 bits); dynamic LDS of
-  // 4 * 64 * P words in phase 1 with stage_xu, else none
+  // 4 * 64 * P words in phase 1 with stage_xu, the key copies of ga in
+  // phase 3, else none
   extern __shared__ uint32_t xu_acc[];
+  uint64_t* gsm = reinterpret_cast<uint64_t*>(xu_acc);
+  if (PHASE == 3) gacc_init(ga, gsm);
   const int wib = threadIdx.x / TG_WAVE;
   const int ln = lane();
   const int P = L * (L + 1) / 2;
@@ -663,7 +679,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         if (PHASE == 0) {
           if (HALF) atomicAdd(&row[o_phu >> 1], 1u << ((o_phu & 1) << 4));
           else atomicAdd(&row[o_phu], 1u);
-        } else if (PHASE == 1) {
+        } else if (PHASE == 1 || PHASE == 3) {
           // rows are 16-byte aligned and RW is a multiple of 4 words
           uint32_t c[16];
           uint32_t sum = 0;
@@ -681,8 +697,15 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
           }
           for (int t = 0; t < L; ++t) sum += c[t];
           if (sum < 2) continue;
-          const int32_t e_uw = s2e ? s2e[suw] : suw;
           const int phw = ty[w];
+          if (PHASE == 3) {
+            for (int t = 0; t < L; ++t) {
+              const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
+              if (cc > 0) gacc_add(ga, gsm, key_of(L, 4, o_phx, o_phu, phw, t), (uint64_t)cc);
+            }
+            continue;
+          }
+          const int32_t e_uw = s2e ? s2e[suw] : suw;
           for (int t = 0; t < L; ++t) {
             const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
             if (cc <= 0) continue;
@@ -709,6 +732,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
     if (sa >= S || wpk[sa] - W0 >= wend) break;
   }
   }
+  if (PHASE == 3) gacc_flush(ga, gsm);
 }
 
 // Per-edge 4-cycle rows (edge-major, P per edge) from type-pair-major

@@ -87,3 +87,16 @@ def test_count_rejects_arguments_before_touching_the_device():
     opt.schedule = 2   # learned without a model
     assert lib.tg_count(4, 6, dummy, dummy, dummy, 2, dummy, None, None, ctypes.byref(opt), None) == 1
     assert "model" in lib.tg_last_error().decode()
+
+
+def test_count_global_rejects_arguments_before_touching_the_device():
+    lib = tg.lib()
+    opt = tg._Options()
+    lib.tg_options_default(ctypes.byref(opt))
+    dummy = ctypes.c_void_p(8)   # never dereferenced: every call below fails its host checks
+    assert lib.tg_count_global(4, 6, dummy, dummy, dummy, 0, dummy, ctypes.byref(opt), None) == 4
+    assert lib.tg_count_global(4, 6, dummy, dummy, dummy, 17, dummy, ctypes.byref(opt), None) == 4
+    assert lib.tg_count_global(4, 6, dummy, dummy, dummy, 2, None, ctypes.byref(opt), None) == 1
+    assert lib.tg_count_global(4, 6, None, dummy, dummy, 2, dummy, ctypes.byref(opt), None) == 1
+    assert lib.tg_count_global(4, 5, dummy, dummy, dummy, 2, dummy, ctypes.byref(opt), None) == 2
+    assert lib.tg_count_global(-1, 6, dummy, dummy, dummy, 2, dummy, None, None) == 1

@@ -40,7 +40,10 @@ def run(name):
     note(f"{name} n={g.n} m={g.m} L={g.L}")
     rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
     glob, rows, _ = tg.count(rp, ci, ty, g.L)
+    # global counts counted once per instance agree at full size
+    once = tg.count_global(rp, ci, ty, g.L)
     torch.cuda.synchronize()
+    assert torch.equal(once.view(torch.int64), glob.view(torch.int64))
     return g, glob, rows
 
 
