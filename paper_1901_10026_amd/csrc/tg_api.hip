@@ -736,12 +736,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     const GAcc ga_k4 = make_gacc(global_counts, 2 * C3k + 5 * C4k, C4k, 16 << 10);
     if (hk[0] > 0) {
       k_glob_k4<16><<<grid_for(hk[0], 16, 8192), 256, k4_lds_bytes<16>(ga_k4), st>>>(
-          hk[0], W.elist, W.ei, W.ej, rp, ci, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0, ga_k4);
+          hk[0], W.elist, W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0, ga_k4);
       TG_LAUNCHED("k_glob_k4<16>");
     }
     if (hk[1] > 0) {
       k_glob_k4<64><<<grid_for(hk[1], 4, 8192), 256, k4_lds_bytes<64>(ga_k4), st>>>(
-          hk[1], W.elist + kcur[1], W.ei, W.ej, rp, ci, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0,
+          hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0,
           ga_k4);
       TG_LAUNCHED("k_glob_k4<64>");
     }
@@ -753,7 +753,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
         t_cap = hk[3];
         TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
       }
-      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej, rp, ci,
+      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej,
                                                                    W.deg, ty, W.out_off, W.out_col, W.tau, L, tcap,
                                                                    t_over, t_cap, ga_k4);
       TG_LAUNCHED("k_glob_k4<256>");

@@ -27,7 +27,8 @@
 //   4-cycles: twice, from the degree-ordered wedge pass (GLOB variants of
 //   k_c4_hash and phase 3 of k_c4_group);
 //   4-cliques: once, from their two lowest nodes a < b in degree order as the
-//   typed edges inside T+_ab = {k ~ a, k ~ b, b before k} (k_glob_k4).
+//   typed edges inside T+_ab = {k ~ a, k ~ b, b before k} = out(a) ∩ out(b)
+//   (k_glob_k4).
 
 // multiset t1 <= t2 of colex rank q (q < L(L+1)/2)
 __device__ __forceinline__ void unrank2(int q, int& t1, int& t2) {
@@ -141,9 +142,9 @@ __global__ void __launch_bounds__(256) k_glob_edges(int64_t m, const int32_t* __
 }
 
 // 4-clique edge classes: by the length of the T+ intersection loop,
-// min(|out(b)|, d_a) with a before b, against lim = (16-lane team limit,
-// wavefront limit); edges with fewer than two common neighbours hold no
-// 4-clique and are left out.
+// min(|out(a)|, |out(b)|), against lim = (16-lane team limit, wavefront
+// limit); edges with fewer than two common neighbours hold no 4-clique and
+// are left out.
 __device__ __forceinline__ int k4_class(int32_t e, const int32_t* ei, const int32_t* ej, const int32_t* deg,
                                         const int32_t* out_off, const uint32_t* tau, int L, int2 lim,
                                         int32_t* len_out) {
@@ -151,14 +152,12 @@ __device__ __forceinline__ int k4_class(int32_t e, const int32_t* ei, const int3
   for (int t = 0; t < L; ++t) tsum += tau[(int64_t)e * L + t];
   if (tsum < 2) return -1;
   const int32_t i = ei[e], j = ej[e];
-  const int32_t di = deg[i], dj = deg[j];
-  const bool i_first = precedes(di, i, dj, j);
-  const int32_t a_deg = i_first ? di : dj, b = i_first ? j : i;
-  const int32_t nb = out_off[b + 1] - out_off[b];
-  const int32_t len = min(min(nb, a_deg), (int32_t)tsum);
+  const int32_t ni = out_off[i + 1] - out_off[i], nj = out_off[j + 1] - out_off[j];
+  const int32_t loop = min(ni, nj);
+  const int32_t len = min(loop, (int32_t)tsum);
   *len_out = len;
   if (len < 2) return -1;
-  return min(nb, a_deg) <= lim.x ? 0 : (min(nb, a_deg) <= lim.y ? 1 : 2);
+  return loop <= lim.x ? 0 : (loop <= lim.y ? 1 : 2);
 }
 
 // counters: [0, 3) class sizes, [3] largest T+ bound of class 2
@@ -182,17 +181,28 @@ __global__ void __launch_bounds__(256) k_k4_class_count(int64_t m, const int32_t
   if (threadIdx.x == 3 && local[3]) atomicMax(&cnt[3], local[3]);
 }
 
-// cur[c] holds the next free position of class c in list
+// cur[c] holds the next free position of class c in list; one atomic per
+// class and wavefront reserves the wavefront's positions
 __global__ void __launch_bounds__(256) k_k4_class_scatter(int64_t m, const int32_t* __restrict__ ei,
                                                           const int32_t* __restrict__ ej,
                                                           const int32_t* __restrict__ deg,
                                                           const int32_t* __restrict__ out_off,
                                                           const uint32_t* __restrict__ tau, int L, int2 lim,
                                                           int32_t* __restrict__ cur, int32_t* __restrict__ list) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < m; e0 += stride) {
+    const int64_t e = e0 + threadIdx.x;
     int32_t len = 0;
-    const int c = k4_class((int32_t)e, ei, ej, deg, out_off, tau, L, lim, &len);
-    if (c >= 0) list[atomicAdd(&cur[c], 1)] = (int32_t)e;
+    const int c = e < m ? k4_class((int32_t)e, ei, ej, deg, out_off, tau, L, lim, &len) : -1;
+    for (int k = 0; k < 3; ++k) {
+      const uint64_t mask = ballot(c == k);
+      if (!mask) continue;
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      int32_t base = 0;
+      if (lane() == leader) base = atomicAdd(&cur[k], __popcll(mask));
+      base = __shfl(base, leader, TG_WAVE);
+      if (c == k) list[base + lanes_below(mask)] = (int32_t)e;
+    }
   }
 }
 
@@ -214,8 +224,8 @@ inline size_t k4_lds_bytes(const GAcc& ga) {
 }
 
 // Typed 4-cliques, once each: one team of TSIZE lanes per edge (a, b) of
-// list, a before b in degree order.  T+ = out(b) intersect Gamma(a), built
-// by searching the shorter list's ids in the longer one (both sorted), so it
+// list, a before b in degree order.  T+ = out(a) intersect out(b), built by
+// searching the shorter list's ids in the longer one (both sorted), so it
 // comes out sorted; each edge {c, d} inside T+ is then found once, from the
 // out-list of its lower end, by binary search in T+.  A T+ that may exceed
 // the team's LDS capacity (workgroup teams only: min(tcap, 4096) ids) lives
@@ -224,7 +234,6 @@ inline size_t k4_lds_bytes(const GAcc& ga) {
 template <int TSIZE>
 __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* __restrict__ list,
                                                  const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
-                                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  const int32_t* __restrict__ out_off,
                                                  const int32_t* __restrict__ out_col,
@@ -247,10 +256,13 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
     const int32_t di = deg[i], dj = deg[j];
     const bool i_first = precedes(di, i, dj, j);
     const int32_t a = i_first ? i : j, b = i_first ? j : i;
-    const int32_t da = i_first ? di : dj;
-    const int32_t ob = out_off[b], nb = out_off[b + 1] - ob, ra = rp[a];
-    const bool scan_out = nb <= da;
-    const int32_t len = scan_out ? nb : da;
+    // T+ = out(a) ∩ out(b): every member ranks above b, hence above a
+    const int32_t oa = out_off[a], na = out_off[a + 1] - oa;
+    const int32_t ob = out_off[b], nb = out_off[b + 1] - ob;
+    const bool a_short = na <= nb;
+    const int32_t os = a_short ? oa : ob, ns = a_short ? na : nb;  // scanned
+    const int32_t ol = a_short ? ob : oa, nl = a_short ? nb : na;  // searched
+    const int32_t len = ns;
     // |T+| is at most the loop length and at most |T_ab|
     bool big = false;
     if (TSIZE > TG_WAVE) {
@@ -268,15 +280,9 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
       bool found = false;
       int32_t k = 0;
       if (idx < len) {
-        if (scan_out) {
-          k = out_col[ob + idx];
-          const int32_t p = lower_bound(ci + ra, da, k);
-          found = p < da && ci[ra + p] == k;
-        } else {
-          k = ci[ra + idx];
-          const int32_t p = lower_bound(out_col + ob, nb, k);
-          found = p < nb && out_col[ob + p] == k;
-        }
+        k = out_col[os + idx];
+        const int32_t p = lower_bound(out_col + ol, nl, k);
+        found = p < nl && out_col[ol + p] == k;
       }
       const uint64_t wmask = ballot(found);
       int32_t before, total;
