@@ -668,6 +668,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
+    if (once && (HS || fill_clear)) {                                                                              \
+      const int64_t nrows = HS ? rows : Gg * n;                                                                    \
+      k_c4_scan<HF, HS><<<grid_for(nrows, 256, 8192), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
+          nrows, cnt_base, RW, n, Gg, gxg, hog, hkeys, ty, L, ga_cyc_g);                                           \
+      break;                                                                                                       \
+    }                                                                                                              \
     if (once) TG_C4_GROUP(3, T, HF, HS, C4P, STG);                                                                 \
     else TG_C4_GROUP(1, T, HF, HS, C4P, STG);                                                                      \
     if (HS) {                                                                                                      \

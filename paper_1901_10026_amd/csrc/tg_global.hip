@@ -25,10 +25,75 @@
 //   chordal cycles (once, by the chord), tailed triangles (twice: the
 //   triangle edge at the tail's node that is not the other one);
 //   4-cycles: twice, from the degree-ordered wedge pass (GLOB variants of
-//   k_c4_hash and phase 3 of k_c4_group);
+//   k_c4_hash, phase 3 of k_c4_group, k_c4_scan);
 //   4-cliques: once, from their two lowest nodes a < b in degree order as the
 //   typed edges inside T+_ab = {k ~ a, k ~ b, b before k} = out(a) ∩ out(b)
 //   (k_glob_k4).
+
+// Typed 4-cycles from the count rows of one heavy group of the wedge pass,
+// after its counting phase: row (x, w) holds the typed middle counts c_t of
+// x's wedges x-u-w, and the cycles with opposite corners x and w and middle
+// types {s, t} number c_s c_t (s < t) or C(c_s, 2) -- each cycle once, since
+// x is its highest node and w is fixed by x.  The sums are doubled to match
+// the wedge-based sums of the other tiers.  Every nonzero row (and, for hash
+// tables, its key) is cleared on the way, which replaces the clearing pass.
+// Rows: dense groups, row q * n + w for group node q (count array of RW
+// words per row); hashed groups, table row h of the node q with
+// hoff[q] <= h < hoff[q + 1], far end hkeys[h] (-1: empty).
+template <bool HALF, bool HASH>
+__global__ void __launch_bounds__(256) k_c4_scan(int64_t nrows, uint32_t* __restrict__ cnt, int RW, int64_t n,
+                                                 int Gg, const int32_t* __restrict__ gx,
+                                                 const int64_t* __restrict__ hoff, int32_t* __restrict__ hkeys,
+                                                 const uint8_t* __restrict__ ty, int L, GAcc ga) {
+  extern __shared__ uint64_t gsm_scan[];
+  gacc_init(ga, gsm_scan);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    int32_t w;
+    int q;
+    if (HASH) {
+      w = hkeys[r];
+      if (w < 0) continue;
+      hkeys[r] = -1;
+      int lo = 0, hi = Gg;  // largest q with hoff[q] <= r
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (hoff[mid] <= r) lo = mid; else hi = mid;
+      }
+      q = lo;
+    } else {
+      q = (int)(r / n);
+      w = (int32_t)(r - (int64_t)q * n);
+    }
+    uint4* row = reinterpret_cast<uint4*>(cnt + r * RW);
+    uint32_t c[16];
+    bool any = false;
+    for (int q4 = 0; q4 < RW / 4; ++q4) {
+      const uint4 v4 = row[q4];
+      any |= (v4.x | v4.y | v4.z | v4.w) != 0u;
+      const uint32_t wd[4] = {v4.x, v4.y, v4.z, v4.w};
+      for (int k = 0; k < 4; ++k) {
+        if (HALF) {
+          c[8 * q4 + 2 * k] = wd[k] & 0xffffu;
+          c[8 * q4 + 2 * k + 1] = wd[k] >> 16;
+        } else {
+          c[4 * q4 + k] = wd[k];
+        }
+      }
+    }
+    if (!any) continue;
+    for (int q4 = 0; q4 < RW / 4; ++q4) row[q4] = make_uint4(0u, 0u, 0u, 0u);
+    const int phx = ty[gx[q]], phw = ty[w];
+    for (int t = 0; t < L; ++t) {
+      const uint64_t ct = c[t];
+      if (!ct) continue;
+      if (ct >= 2) gacc_add(ga, gsm_scan, key_of(L, 4, phx, phw, t, t), ct * (ct - 1));
+      for (int s = 0; s < t; ++s)
+        if (c[s]) gacc_add(ga, gsm_scan, key_of(L, 4, phx, phw, s, t), 2 * ct * c[s]);
+    }
+  }
+  gacc_flush(ga, gsm_scan);
+}
 
 // multiset t1 <= t2 of colex rank q (q < L(L+1)/2)
 __device__ __forceinline__ void unrank2(int q, int& t1, int& t2) {
