@@ -670,7 +670,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
     if (once && (HS || fill_clear)) {                                                                              \
       const int64_t nrows = HS ? rows : Gg * n;                                                                    \
-      k_c4_scan<HF, HS><<<grid_for(nrows, 256, 8192), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
+      k_c4_scan<HF, HS><<<grid_for(nrows, 256, 2048), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
           nrows, cnt_base, RW, n, Gg, gxg, hog, hkeys, ty, L, ga_cyc_g);                                           \
       break;                                                                                                       \
     }                                                                                                              \
@@ -719,9 +719,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     timer.mark(TG_PHASE_COMBINE);
     const int64_t kbudget = 32 << 10;
     const GAcc ga_all = make_gacc(global_counts, 0, K, kbudget);
-    k_glob_nodes<<<grid_for(n, 16, 8192), 256, gacc_bytes(ga_all), st>>>(n, W.deg, W.D, ty, L, ga_all);
+    k_glob_nodes<<<grid_for(n, 16, 2048), 256, gacc_bytes(ga_all), st>>>(n, W.deg, W.D, ty, L, ga_all);
     TG_LAUNCHED("k_glob_nodes");
-    k_glob_edges<<<grid_for(m, 16, 8192), 256, gacc_bytes(ga_all), st>>>(m, W.ei, W.ej, W.D, W.tau, ty, L, ga_all);
+    k_glob_edges<<<grid_for(m, 16, 2048), 256, gacc_bytes(ga_all), st>>>(m, W.ei, W.ej, W.D, W.tau, ty, L, ga_all);
     TG_LAUNCHED("k_glob_edges");
     // 4-cliques: edges in three classes by intersection length
     int32_t* kc = cnt + 280;
@@ -740,14 +740,16 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                                kc + 4, W.elist);
     TG_LAUNCHED("k_k4_class_scatter");
     const GAcc ga_k4 = make_gacc(global_counts, 2 * C3k + 5 * C4k, C4k, 16 << 10);
+    // lane-spread copies of each edge's L x L clique cells: about 2 KiB per team
+    const int mcop = (int)std::max<int64_t>(1, std::min<int64_t>(8, 512 / (LL)));
     if (hk[0] > 0) {
-      k_glob_k4<16><<<grid_for(hk[0], 16, 8192), 256, k4_lds_bytes<16>(ga_k4), st>>>(
-          hk[0], W.elist, W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0, ga_k4);
+      k_glob_k4<16><<<grid_for(hk[0], 16, 4096), 256, k4_lds_bytes<16>(ga_k4, L, mcop), st>>>(
+          hk[0], W.elist, W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0, ga_k4);
       TG_LAUNCHED("k_glob_k4<16>");
     }
     if (hk[1] > 0) {
-      k_glob_k4<64><<<grid_for(hk[1], 4, 8192), 256, k4_lds_bytes<64>(ga_k4), st>>>(
-          hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, 0, nullptr, 0,
+      k_glob_k4<64><<<grid_for(hk[1], 4, 4096), 256, k4_lds_bytes<64>(ga_k4, L, mcop), st>>>(
+          hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0,
           ga_k4);
       TG_LAUNCHED("k_glob_k4<64>");
     }
@@ -759,8 +761,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
         t_cap = hk[3];
         TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
       }
-      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej,
-                                                                   W.deg, ty, W.out_off, W.out_col, W.tau, L, tcap,
+      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4, L, mcop), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej,
+                                                                   W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, tcap,
                                                                    t_over, t_cap, ga_k4);
       TG_LAUNCHED("k_glob_k4<256>");
     }

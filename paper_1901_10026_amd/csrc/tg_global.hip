@@ -277,32 +277,37 @@ struct K4Cap {
 };
 
 // per-team LDS bytes of k_glob_k4 after the key copies: scan scratch, the
-// T+ ids and types
+// cell counters (mcopies copies of L x L), the T+ ids and types
 template <int TSIZE>
-constexpr int k4_team_bytes() {
-  return ((TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8) * 4 + K4Cap<TSIZE>::value * 5 + 7) & ~7;
+__host__ __device__ inline int k4_team_bytes(int L, int mcopies) {
+  return ((TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8) * 4 + mcopies * L * L * 4 + K4Cap<TSIZE>::value * 5 + 7) & ~7;
 }
 
 template <int TSIZE>
-inline size_t k4_lds_bytes(const GAcc& ga) {
-  return (size_t)ga.copies * ga.nk * sizeof(uint64_t) + (size_t)(256 / TSIZE) * k4_team_bytes<TSIZE>();
+inline size_t k4_lds_bytes(const GAcc& ga, int L, int mcopies) {
+  return (size_t)ga.copies * ga.nk * sizeof(uint64_t) + (size_t)(256 / TSIZE) * k4_team_bytes<TSIZE>(L, mcopies);
 }
 
 // Typed 4-cliques, once each: one team of TSIZE lanes per edge (a, b) of
 // list, a before b in degree order.  T+ = out(a) intersect out(b), built by
 // searching the shorter list's ids in the longer one (both sorted), so it
 // comes out sorted; each edge {c, d} inside T+ is then found once, from the
-// out-list of its lower end, by binary search in T+.  A T+ that may exceed
-// the team's LDS capacity (workgroup teams only: min(tcap, 4096) ids) lives
-// in t_over, t_over_cap ids and types per workgroup (t_over_cap at least
-// min(loop length, |T_ab|) over the list).
+// out-list of its lower end, by binary search in T+, and counted in the
+// edge's L x L cell (phi_c, phi_d) (mcopies lane-spread copies of 32-bit
+// counters: an edge has fewer than 2^32 of them, as |T+| is at most the
+// largest out-degree, below 2^16); the cells then go to the 4-clique keys.
+// Each lane runs U searches at a time, step by step together, so that U
+// loads are in flight.  A T+ that may exceed the team's LDS capacity
+// (workgroup teams only: min(tcap, 4096) ids) lives in t_over, t_over_cap
+// ids and types per workgroup (t_over_cap at least min(loop length,
+// |T_ab|) over the list).
 template <int TSIZE>
 __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* __restrict__ list,
                                                  const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  const int32_t* __restrict__ out_off,
                                                  const int32_t* __restrict__ out_col,
-                                                 const uint32_t* __restrict__ tau, int L,
+                                                 const uint32_t* __restrict__ tau, int L, int mcopies,
                                                  int tcap, int32_t* __restrict__ t_over, int64_t t_over_cap,
                                                  GAcc ga) {
   extern __shared__ uint64_t gsm_k4[];
@@ -310,10 +315,13 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
   constexpr int TEAMS = 256 / TSIZE;
   constexpr int TCAP = K4Cap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
+  constexpr int U = 4;
+  const int LL = L * L;
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE, wv = tid / TG_WAVE;
-  char* base = (char*)(gsm_k4 + (int64_t)ga.copies * ga.nk) + team * k4_team_bytes<TSIZE>();
+  char* base = (char*)(gsm_k4 + (int64_t)ga.copies * ga.nk) + team * k4_team_bytes<TSIZE>(L, mcopies);
   int32_t* scratch = (int32_t*)base;
-  int32_t* Tid_l = scratch + SCR;
+  uint32_t* cell = (uint32_t*)(scratch + SCR);
+  int32_t* Tid_l = (int32_t*)(cell + mcopies * LL);
   uint8_t* Tty_l = (uint8_t*)(Tid_l + TCAP);
   for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
     const int32_t e = list[w];
@@ -327,57 +335,72 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
     const bool a_short = na <= nb;
     const int32_t os = a_short ? oa : ob, ns = a_short ? na : nb;  // scanned
     const int32_t ol = a_short ? ob : oa, nl = a_short ? nb : na;  // searched
-    const int32_t len = ns;
     // |T+| is at most the loop length and at most |T_ab|
     bool big = false;
     if (TSIZE > TG_WAVE) {
       uint32_t tsum = 0;
       for (int t = 0; t < L; ++t) tsum += tau[(int64_t)e * L + t];
-      big = min((int64_t)len, (int64_t)tsum) > min(tcap, TCAP);
+      big = min((int64_t)ns, (int64_t)tsum) > min(tcap, TCAP);
     }
     int32_t* Tid = big ? t_over + (int64_t)blockIdx.x * t_over_cap : Tid_l;
     uint8_t* Tty = big ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
                        : Tty_l;
-    // ---- T+, in id order
+    for (int x = tid; x < mcopies * LL; x += TSIZE) cell[x] = 0u;
+    // ---- T+, in id order: U scanned ids per lane, searched together
     int32_t nT = 0;
-    for (int32_t b0 = 0; b0 < len; b0 += TSIZE) {
-      const int32_t idx = b0 + tid;
-      bool found = false;
-      int32_t k = 0;
-      if (idx < len) {
-        k = out_col[os + idx];
-        const int32_t p = lower_bound(out_col + ol, nl, k);
-        found = p < nl && out_col[ol + p] == k;
+    int top = 1;
+    while (top * 2 <= nl) top *= 2;
+    for (int32_t b0 = 0; b0 < ns; b0 += TSIZE * U) {
+      int32_t kv[U], pos[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int32_t idx = b0 + k * TSIZE + tid;
+        kv[k] = idx < ns ? out_col[os + idx] : -1;
+        pos[k] = 0;
       }
-      const uint64_t wmask = ballot(found);
-      int32_t before, total;
-      if (TSIZE <= TG_WAVE) {
-        const uint64_t tm = team_bits<TSIZE>(wmask);
-        before = __popcll(tm & bits_below(tid));
-        total = __popcll(tm);
-      } else {
-        if (lane() == 0) scratch[wv] = __popcll(wmask);
-        __syncthreads();
-        before = __popcll(wmask & bits_below(lane()));
-        total = 0;
-        for (int q = 0; q < TSIZE / TG_WAVE; ++q) {
-          const int32_t c = scratch[q];
-          if (q < wv) before += c;
-          total += c;
+      // lower bound of kv in the searched list, the same steps for all U
+      for (int step = top; step > 0; step >>= 1) {
+        int32_t tv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) tv[k] = pos[k] + step <= nl ? out_col[ol + pos[k] + step - 1] : INT32_MAX;
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+          if (tv[k] < kv[k]) pos[k] += step;
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const bool found = kv[k] >= 0 && pos[k] < nl && out_col[ol + pos[k]] == kv[k];
+        const uint64_t wmask = ballot(found);
+        int32_t before, total;
+        if (TSIZE <= TG_WAVE) {
+          const uint64_t tm = team_bits<TSIZE>(wmask);
+          before = __popcll(tm & bits_below(tid));
+          total = __popcll(tm);
+        } else {
+          if (lane() == 0) scratch[wv] = __popcll(wmask);
+          __syncthreads();
+          before = __popcll(wmask & bits_below(lane()));
+          total = 0;
+          for (int q = 0; q < TSIZE / TG_WAVE; ++q) {
+            const int32_t c = scratch[q];
+            if (q < wv) before += c;
+            total += c;
+          }
+          __syncthreads();
         }
-        __syncthreads();
+        if (found) {
+          Tid[nT + before] = kv[k];
+          Tty[nT + before] = ty[kv[k]];
+        }
+        nT += total;
       }
-      if (found) {
-        Tid[nT + before] = k;
-        Tty[nT + before] = ty[k];
-      }
-      nT += total;
     }
     tsync<TSIZE>();
     if (nT >= 2) {
-      const int pa = ty[a], pb = ty[b];
       // (member, out-slot) pairs dealt to lanes through a team prefix sum
       int32_t* s_excl = scratch + 8;  // TSIZE == 256 only
+      int ttop = 1;
+      while (ttop * 2 <= nT) ttop *= 2;
       for (int32_t q0 = 0; q0 < nT; q0 += TSIZE) {
         const int32_t q = q0 + tid;
         int32_t ostart = 0, ocnt = 0, tk = 0;
@@ -395,30 +418,61 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
           s_excl[2 * TSIZE + tid] = tk;
           __syncthreads();
         }
-        for (int32_t c0 = 0; c0 < tot; c0 += TSIZE) {
-          const int32_t v = c0 + tid;
-          int o = 0;
+        for (int32_t c0 = 0; c0 < tot; c0 += TSIZE * U) {
+          int32_t v[U], o[U], r[U], rtk[U], p[U];
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            v[k] = c0 + k * TSIZE + tid;
+            o[k] = 0;
+          }
+          // owner of pair v: the largest member q with excl[q] <= v
+#pragma unroll
           for (int step = TSIZE / 2; step > 0; step >>= 1) {
-            const int32_t ex = TSIZE <= TG_WAVE ? __shfl(excl, o + step, TSIZE) : s_excl[o + step];
-            if (ex <= v) o += step;
+            int32_t ex[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+              ex[k] = TSIZE <= TG_WAVE ? __shfl(excl, o[k] + step, TSIZE) : s_excl[o[k] + step];
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+              if (ex[k] <= v[k]) o[k] += step;
           }
-          int32_t o_excl, o_start, o_tk;
-          if (TSIZE <= TG_WAVE) {
-            o_excl = __shfl(excl, o, TSIZE);
-            o_start = __shfl(ostart, o, TSIZE);
-            o_tk = __shfl(tk, o, TSIZE);
-          } else {
-            o_excl = s_excl[o];
-            o_start = s_excl[TSIZE + o];
-            o_tk = s_excl[2 * TSIZE + o];
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            int32_t o_excl, o_start;
+            if (TSIZE <= TG_WAVE) {
+              o_excl = __shfl(excl, o[k], TSIZE);
+              o_start = __shfl(ostart, o[k], TSIZE);
+              rtk[k] = __shfl(tk, o[k], TSIZE);
+            } else {
+              o_excl = s_excl[o[k]];
+              o_start = s_excl[TSIZE + o[k]];
+              rtk[k] = s_excl[2 * TSIZE + o[k]];
+            }
+            r[k] = v[k] < tot ? out_col[o_start + (v[k] - o_excl)] : -1;
+            p[k] = 0;
           }
-          if (v < tot) {
-            const int32_t r = out_col[o_start + (v - o_excl)];
-            const int32_t p = lower_bound(Tid, nT, r);
-            if (p < nT && Tid[p] == r) gacc_add(ga, gsm_k4, key_of(L, 7, pa, pb, o_tk, Tty[p]), 1ull);
+          // lower bound in the sorted T+, the same steps for all U pairs
+          for (int step = ttop; step > 0; step >>= 1) {
+            int32_t tv[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) tv[k] = p[k] + step <= nT ? Tid[p[k] + step - 1] : INT32_MAX;
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+              if (tv[k] < r[k]) p[k] += step;
           }
+#pragma unroll
+          for (int k = 0; k < U; ++k)
+            if (r[k] >= 0 && p[k] < nT && Tid[p[k]] == r[k])
+              atomicAdd(&cell[(lane() % mcopies) * LL + rtk[k] * L + Tty[p[k]]], 1u);
         }
         if (TSIZE > TG_WAVE) __syncthreads();
+      }
+      tsync<TSIZE>();
+      const int pa = ty[a], pb = ty[b];
+      for (int x = tid; x < LL; x += TSIZE) {
+        uint64_t sum = 0;
+        for (int c = 0; c < mcopies; ++c) sum += cell[c * LL + x];
+        if (sum) gacc_add(ga, gsm_k4, key_of(L, 7, pa, pb, x / L, x % L), sum);
       }
     }
     tsync<TSIZE>();
