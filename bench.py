@@ -126,7 +126,7 @@ def cpu_baseline(g, seconds, threads):
                        f"per-edge method (all rows) in {t_used:.1f} s on {threads} host threads")
 
 
-def time_count(tg, g, rp, ci, ty, out_g, out_e, steps, **kw):
+def time_count(tg, g, rp, ci, ty, out_g, out_e, steps, per_edge=True, **kw):
     import torch
     torch.cuda.synchronize()
     s0 = torch.cuda.Event(enable_timing=True)
@@ -134,7 +134,7 @@ def time_count(tg, g, rp, ci, ty, out_g, out_e, steps, **kw):
     stream = torch.cuda.current_stream()
     s0.record(stream)
     for _ in range(steps):
-        tg.count(rp, ci, ty, g.L, per_edge=True, out_global=out_g, out_edges=out_e, **kw)
+        tg.count(rp, ci, ty, g.L, per_edge=per_edge, out_global=out_g, out_edges=out_e, **kw)
     s1.record(stream)
     torch.cuda.synchronize()
     return s0.elapsed_time(s1) / steps
@@ -203,6 +203,35 @@ def outputs_leg(tg, g, rp, ci, ty, out_g, out_e, steps=3):
     return res
 
 
+def global_leg(tg, g, rp, ci, ty, out_g, steps=3):
+    """Global counts alone on the same graph: tg_count_global (each instance
+    counted a fixed number of times) against tg_count without per-edge rows;
+    both must give the global vector of the timed step."""
+    import torch
+    want = out_g.clone()
+    glob = torch.empty_like(out_g)
+    tg.count_global(rp, ci, ty, g.L, out=glob)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    phases = {}
+    s0.record()
+    for _ in range(steps):
+        ph = {}
+        tg.count_global(rp, ci, ty, g.L, out=glob, phase_ms=ph)
+        for k, v in ph.items():
+            phases[k] = phases.get(k, 0.0) + v / steps
+    s1.record()
+    torch.cuda.synchronize()
+    once_ms = s0.elapsed_time(s1) / steps
+    same = bool(torch.equal(glob.view(torch.int64), want.view(torch.int64)))
+    per_edge_ms = time_count(tg, g, rp, ci, ty, glob, None, steps, per_edge=False)
+    same = same and bool(torch.equal(glob.view(torch.int64), want.view(torch.int64)))
+    log(f"global only: counted once {once_ms:.1f} ms, per-edge path without rows {per_edge_ms:.1f} ms, equal={same}")
+    return {"count_global_ms": once_ms, "count_global_edges_per_s": g.m / (once_ms * 1e-3),
+            "count_global_phase_ms": phases, "per_edge_path_global_only_ms": per_edge_ms, "equal": same}
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -244,6 +273,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs leg")
     ap.add_argument("--no-outputs", action="store_true", help="skip the orbit-row and sparse-row leg")
+    ap.add_argument("--no-global", action="store_true", help="skip the global-counts-only leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -335,6 +365,8 @@ def main():
     }
     if not args.no_compare:
         rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)
+    if not args.no_global:
+        rec["global_only"] = global_leg(tg, g, rp, ci, ty, out_g)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
     if not args.no_batch:
