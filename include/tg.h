@@ -228,6 +228,28 @@ tg_status tg_count_global(int64_t n, int64_t nnz, const int32_t* row_ptr, const 
                           const uint8_t* node_types, int L, uint64_t* global_counts, const tg_options* opt,
                           hipStream_t stream);
 
+/* Global counts for several type vectors of one graph, as tg_count_global
+ * gives them for each, sharing the work that does not depend on the types
+ * (degree order, out-lists, 4-cycle groups, 4-clique edge classes).  This
+ * is the type-permutation null model of the exploratory analysis (the
+ * randomized typed triangle and 4-node motif distributions): the caller
+ * passes permutations of the real type vector (random numbers are the
+ * caller's) and gets every permutation's counts and their mean.
+ *   num_type_vectors  B >= 1
+ *   node_types        device, uint8[B * n]: vector b at node_types + b * n
+ *   global_counts     device, uint64[B * tg_num_keys(L)]: vector b's counts
+ *                     at global_counts + b * K(L); must not be NULL
+ *   mean_counts       device, double[tg_num_keys(L)] receiving the mean over
+ *                     the B vectors (exact integer sums, one rounding), or
+ *                     NULL
+ * Other arguments, options and errors as for tg_count_global; validate
+ * checks every type vector.
+ */
+tg_status tg_count_global_types(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                                int64_t num_type_vectors, const uint8_t* node_types, int L,
+                                uint64_t* global_counts, double* mean_counts, const tg_options* opt,
+                                hipStream_t stream);
+
 /* Sparse per-edge output (the Sparse Typed Motif Format subsection: only the
  * nonzero typed graphlet counts of each edge, with their ids).  Turns dense
  * per-edge rows into (global key, count) pairs; keys are the dense key rank

@@ -128,6 +128,8 @@ def lib():
     L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_count_global.restype = i32
     L.tg_count_global.argtypes = [i64, i64, vp, vp, vp, i32, vp, ctypes.POINTER(_Options), vp]
+    L.tg_count_global_types.restype = i32
+    L.tg_count_global_types.argtypes = [i64, i64, vp, vp, i64, vp, i32, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_rows_sparse.restype = i32
     L.tg_rows_sparse.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
     L.tg_count_batch.restype = i32
@@ -321,6 +323,66 @@ def count_global(row_ptr, col_idx, types, L, *, validate=False, check=True, out=
     if times is not None:
         phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
     return g
+
+
+def count_global_types(row_ptr, col_idx, type_vectors, L, *, validate=False, check=True, out=None, mean=True,
+                       phase_ms=None, tuning=None):
+    """Global counts of one graph under several type vectors with
+    tg_count_global_types.  type_vectors: contiguous uint8 device tensor
+    [B, n].  Returns (counts uint64 [B, K(L)], mean float64 [K(L)] or None)."""
+    import torch
+    dev = row_ptr.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (type_vectors, torch.uint8)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("row_ptr/col_idx must be contiguous int32 and type_vectors contiguous uint8 on one device")
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if type_vectors.dim() != 2 or type_vectors.shape[1] != n or type_vectors.shape[0] < 1:
+        raise ValueError("type_vectors must have shape [B, n] with B >= 1")
+    B = type_vectors.shape[0]
+    K = num_keys(L)
+    if K == 0:
+        raise TGError(4, "L must be in [1, 16]")
+    g = out if out is not None else torch.empty((B, K), dtype=torch.uint64, device=dev)
+    if g.dtype != torch.uint64 or not g.is_contiguous() or g.device != dev or g.numel() < B * K:
+        raise ValueError("out must be a contiguous uint64 tensor of [B, K(L)] on the inputs' device")
+    mu = torch.empty(K, dtype=torch.float64, device=dev) if mean else None
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
+    opt.validate = 1 if validate else 0
+    opt.check = 1 if check else 0
+    times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
+    opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    st = lib().tg_count_global_types(n, nnz, row_ptr.data_ptr(), col_idx.data_ptr() if nnz else None, B,
+                                     type_vectors.data_ptr() if n else None, L, g.data_ptr(),
+                                     mu.data_ptr() if mu is not None else None, ctypes.byref(opt),
+                                     _stream_handle(torch, dev))
+    _check(st)
+    if times is not None:
+        phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
+    return g, mu
+
+
+def type_permutations(types, count, seed):
+    """count permutations of a host uint8 type vector, drawn by numpy's
+    seeded default generator: row b is types[perm_b] (the null model's random
+    relabellings, which keep every type's frequency)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = np.ascontiguousarray(types, dtype=np.uint8)
+    return np.stack([t[rng.permutation(len(t))] for _ in range(count)]) if count else np.zeros((0, len(t)), np.uint8)
+
+
+def null_model(row_ptr, col_idx, types, L, *, permutations=100, seed=0, **kw):
+    """Type-permutation null model: global counts under `permutations`
+    seeded random permutations of the node types, and their mean.  Returns
+    (counts uint64 [permutations, K(L)], mean float64 [K(L)])."""
+    import torch
+    perms = type_permutations(types.cpu().numpy(), permutations, seed)
+    tv = torch.from_numpy(perms).to(row_ptr.device)
+    return count_global_types(row_ptr, col_idx, tv, L, **kw)
 
 
 def rows_sparse(rows, endpoints, types, L):

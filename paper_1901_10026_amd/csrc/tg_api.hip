@@ -273,12 +273,17 @@ size_t gacc_bytes(const GAcc& a) { return (size_t)a.copies * a.nk * sizeof(uint6
 
 // once: global counts only, every instance counted a fixed number of times
 // (tg_count_global); otherwise per-edge counting with Eq. 17 (tg_count).
+// With once, ty may hold nty type vectors of n entries each and
+// global_counts then receives nty vectors of K(L) counts; the work that does
+// not depend on types (degree order, out-lists, 4-cycle groups, 4-clique
+// edge classes) is done once.
 tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L,
                      uint64_t* global_counts, uint64_t* edge_counts, int32_t* edge_endpoints,
-                     const tg_options* opt_in, hipStream_t st, bool once = false) {
+                     const tg_options* opt_in, hipStream_t st, bool once = false, int64_t nty = 1) {
   tg_options opt;
   tg_options_default(&opt);
   if (opt_in) opt = *opt_in;
+  if (nty < 1 || (nty > 1 && !once)) return fail(TG_ERR_INVALID_ARG, "bad number of type vectors");
   if (once) {
     if (!global_counts) return fail(TG_ERR_INVALID_ARG, "null global_counts");
     edge_counts = nullptr;
@@ -324,7 +329,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   PhaseTimer timer(st, opt.phase_ms);
 
   if (global_counts) {
-    k_fill_u64<<<grid_for(K, 256, 64), 256, 0, st>>>(global_counts, K, 0);
+    k_fill_u64<<<grid_for(K * nty, 256, 1024), 256, 0, st>>>(global_counts, K * nty, 0);
     TG_LAUNCHED("k_fill_u64");
   }
   // without global counts only the edges whose rows are asked for go through
@@ -333,8 +338,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   const int64_t sel_e0 = (global_counts || ids) ? 0 : eb;
   const int64_t sel_count = global_counts ? m : (ids ? nids : ee - eb);
   if (opt.validate && n > 0) {
-    tg_status vs = validate_graph(S, st, n, nnz, rp, ci, ty, L);
-    if (vs != TG_OK) return vs;
+    for (int64_t b = 0; b < nty; ++b) {
+      tg_status vs = validate_graph(S, st, n, nnz, rp, ci, ty + b * n, L);
+      if (vs != TG_OK) return vs;
+    }
   } else if (opt.validate) {
     int32_t h0 = -1;
     TG_HIP(hipMemcpyAsync(&h0, rp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -435,17 +442,22 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   TG_LAUNCHED("k_fill_u64");
   // once: the 4-cycle keys, summed twice per cycle
   const int64_t C3k = per_shape(L, 3), C4k = per_shape(L, 4);
-  const GAcc ga_cyc = make_gacc(global_counts, 2 * C3k + 2 * C4k, C4k, 8 << 10);
-  const GAcc ga_cyc_g = make_gacc(global_counts, 2 * C3k + 2 * C4k, C4k, 16 << 10);
-  if (once && n_t1 > 0) {
-    k_c4_hash<1, 8, uint32_t, true><<<grid_for(n_t1, 4, 4096), 256, gacc_bytes(ga_cyc), st>>>(
-        n_t1, W.nlist + cur[257], rp, ci, W.deg, ty, L, nullptr, nullptr, 0, ga_cyc);
-    TG_LAUNCHED("k_c4_hash<1, glob>");
-  }
-  if (once && n_t2 > 0) {
-    k_c4_hash<4, 12, uint32_t, true><<<grid_for(n_t2, 1, 2048), 256, gacc_bytes(ga_cyc), st>>>(
-        n_t2, W.nlist + cur[258], rp, ci, W.deg, ty, L, nullptr, nullptr, 0, ga_cyc);
-    TG_LAUNCHED("k_c4_hash<4, glob>");
+  // key copies of type vector b's 4-cycle sums within `budget` bytes
+  auto gacc_cyc = [&](int64_t b, int64_t budget) {
+    return make_gacc(global_counts + b * K, 2 * C3k + 2 * C4k, C4k, budget);
+  };
+  for (int64_t b = 0; once && b < nty; ++b) {
+    const GAcc ga_cyc = gacc_cyc(b, 8 << 10);
+    if (n_t1 > 0) {
+      k_c4_hash<1, 8, uint32_t, true><<<grid_for(n_t1, 4, 4096), 256, gacc_bytes(ga_cyc), st>>>(
+          n_t1, W.nlist + cur[257], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc);
+      TG_LAUNCHED("k_c4_hash<1, glob>");
+    }
+    if (n_t2 > 0) {
+      k_c4_hash<4, 12, uint32_t, true><<<grid_for(n_t2, 1, 2048), 256, gacc_bytes(ga_cyc), st>>>(
+          n_t2, W.nlist + cur[258], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc);
+      TG_LAUNCHED("k_c4_hash<4, glob>");
+    }
   }
   if (!once && n_t1 > 0) {
     if (c4_wide)
@@ -663,15 +675,15 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<PH == 3 ? grid3 : grid, 256,                                                         \
                               PH == 3 ? gacc_bytes(ga_cyc_g) : ((PH == 1 && STG) ? xu_lds : 0), st>>>(             \
-      Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, ty, L, \
-      s2x, C4P, crows, STG, ga_cyc_g)
+      Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, tyb,   \
+      L, s2x, C4P, crows, STG, ga_cyc_g)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
     if (once && (HS || fill_clear)) {                                                                              \
       const int64_t nrows = HS ? rows : Gg * n;                                                                    \
       k_c4_scan<HF, HS><<<grid_for(nrows, 256, 2048), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
-          nrows, cnt_base, RW, n, Gg, gxg, hog, hkeys, ty, L, ga_cyc_g);                                           \
+          nrows, cnt_base, RW, n, Gg, gxg, hog, hkeys, tyb, L, ga_cyc_g);                                          \
       break;                                                                                                       \
     }                                                                                                              \
     if (once) TG_C4_GROUP(3, T, HF, HS, C4P, STG);                                                                 \
@@ -696,8 +708,13 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       else TG_C4_PHASES(uint32_t, false, HS, C4n_t, stage_xu);         \
     }                                                                  \
   } while (0)
-      if (hashed) TG_C4_ALL(true);
-      else TG_C4_ALL(false);
+      // every type vector in turn reuses the group's count rows
+      for (int64_t b = 0; b < nty; ++b) {
+        const uint8_t* tyb = ty + b * n;
+        const GAcc ga_cyc_g = once ? gacc_cyc(b, 16 << 10) : GAcc{};
+        if (hashed) TG_C4_ALL(true);
+        else TG_C4_ALL(false);
+      }
 #undef TG_C4_ALL
 #undef TG_C4_PHASES
 #undef TG_C4_GROUP
@@ -717,13 +734,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (once) {
     // ---- the other shapes, each instance a fixed number of times
     timer.mark(TG_PHASE_COMBINE);
-    const int64_t kbudget = 32 << 10;
-    const GAcc ga_all = make_gacc(global_counts, 0, K, kbudget);
-    k_glob_nodes<<<grid_for(n, 16, 2048), 256, gacc_bytes(ga_all), st>>>(n, W.deg, W.D, ty, L, ga_all);
-    TG_LAUNCHED("k_glob_nodes");
-    k_glob_edges<<<grid_for(m, 16, 2048), 256, gacc_bytes(ga_all), st>>>(m, W.ei, W.ej, W.D, W.tau, ty, L, ga_all);
-    TG_LAUNCHED("k_glob_edges");
-    // 4-cliques: edges in three classes by intersection length
+    // 4-cliques: edges in three classes by intersection length (|T_ij| does
+    // not depend on the types, so neither do the classes)
     int32_t* kc = cnt + 280;
     TG_HIP(hipMemsetAsync(kc, 0, 8 * sizeof(int32_t), st));
     const int team_max = std::min(64, std::max(0, tune.clique_team_max));
@@ -739,38 +751,57 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     k_k4_class_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim,
                                                                kc + 4, W.elist);
     TG_LAUNCHED("k_k4_class_scatter");
-    const GAcc ga_k4 = make_gacc(global_counts, 2 * C3k + 5 * C4k, C4k, 16 << 10);
     // lane-spread copies of each edge's L x L clique cells: about 2 KiB per team
     const int mcop = (int)std::max<int64_t>(1, std::min<int64_t>(8, 512 / (LL)));
-    if (hk[0] > 0) {
-      k_glob_k4<16><<<grid_for(hk[0], 16, 4096), 256, k4_lds_bytes<16>(ga_k4, L, mcop), st>>>(
-          hk[0], W.elist, W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0, ga_k4);
-      TG_LAUNCHED("k_glob_k4<16>");
+    const unsigned grid_wg = grid_for(hk[2], 1, 2048);
+    int32_t* t_over = nullptr;
+    int64_t t_cap = 0;
+    if (hk[2] > 0 && hk[3] > tcap) {
+      t_cap = hk[3];
+      TG_HIP(S.get(&t_over, ((int64_t)grid_wg * t_cap * 5 + 3) / 4));
     }
-    if (hk[1] > 0) {
-      k_glob_k4<64><<<grid_for(hk[1], 4, 4096), 256, k4_lds_bytes<64>(ga_k4, L, mcop), st>>>(
-          hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0,
-          ga_k4);
-      TG_LAUNCHED("k_glob_k4<64>");
-    }
-    if (hk[2] > 0) {
-      const unsigned grid = grid_for(hk[2], 1, 2048);
-      int32_t* t_over = nullptr;
-      int64_t t_cap = 0;
-      if (hk[3] > tcap) {
-        t_cap = hk[3];
-        TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
-      }
-      k_glob_k4<256><<<grid, 256, k4_lds_bytes<256>(ga_k4, L, mcop), st>>>(hk[2], W.elist + kcur[2], W.ei, W.ej,
-                                                                   W.deg, ty, W.out_off, W.out_col, W.tau, L, mcop, tcap,
-                                                                   t_over, t_cap, ga_k4);
-      TG_LAUNCHED("k_glob_k4<256>");
-    }
-    timer.mark(TG_PHASE_FINALIZE);
     int32_t* flag = cnt + 272;
     TG_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-    k_glob_finalize<<<grid_for(std::max(C3k, C4k), 256), 256, 0, st>>>(global_counts, L, flag);
-    TG_LAUNCHED("k_glob_finalize");
+    for (int64_t b = 0; b < nty; ++b) {
+      const uint8_t* tyb = ty + b * n;
+      uint64_t* gb = global_counts + b * K;
+      if (b > 0) {
+        // typed degrees and typed common-neighbour counts of this type vector
+        k_node_stats<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, tyb, L, W.D, W.n_upper, W.n_out,
+                                                     W.wedge_work, W.nbr_deg_sum);
+        TG_LAUNCHED("k_node_stats");
+        k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau);
+        k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau);
+        TG_LAUNCHED("k_tau");
+      }
+      const GAcc ga_all = make_gacc(gb, 0, K, 32 << 10);
+      k_glob_nodes<<<grid_for(n, 16, 2048), 256, gacc_bytes(ga_all), st>>>(n, W.deg, W.D, tyb, L, ga_all);
+      TG_LAUNCHED("k_glob_nodes");
+      k_glob_edges<<<grid_for(m, 16, 2048), 256, gacc_bytes(ga_all), st>>>(m, W.ei, W.ej, W.D, W.tau, tyb, L,
+                                                                            ga_all);
+      TG_LAUNCHED("k_glob_edges");
+      const GAcc ga_k4 = make_gacc(gb, 2 * C3k + 5 * C4k, C4k, 16 << 10);
+      if (hk[0] > 0) {
+        k_glob_k4<16><<<grid_for(hk[0], 16, 4096), 256, k4_lds_bytes<16>(ga_k4, L, mcop), st>>>(
+            hk[0], W.elist, W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0, ga_k4);
+        TG_LAUNCHED("k_glob_k4<16>");
+      }
+      if (hk[1] > 0) {
+        k_glob_k4<64><<<grid_for(hk[1], 4, 4096), 256, k4_lds_bytes<64>(ga_k4, L, mcop), st>>>(
+            hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0,
+            ga_k4);
+        TG_LAUNCHED("k_glob_k4<64>");
+      }
+      if (hk[2] > 0) {
+        k_glob_k4<256><<<grid_wg, 256, k4_lds_bytes<256>(ga_k4, L, mcop), st>>>(
+            hk[2], W.elist + kcur[2], W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, tcap, t_over,
+            t_cap, ga_k4);
+        TG_LAUNCHED("k_glob_k4<256>");
+      }
+      k_glob_finalize<<<grid_for(std::max(C3k, C4k), 256), 256, 0, st>>>(gb, L, flag);
+      TG_LAUNCHED("k_glob_finalize");
+    }
+    timer.mark(TG_PHASE_FINALIZE);
     timer.mark(TG_NUM_PHASES);
     if (opt.check) {
       int32_t hf = 0;
@@ -1449,6 +1480,27 @@ tg_status tg_count_global(int64_t n, int64_t nnz, const int32_t* row_ptr, const 
                           hipStream_t stream) {
   try {
     return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, nullptr, nullptr, opt, stream, true);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+tg_status tg_count_global_types(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                                int64_t num_type_vectors, const uint8_t* node_types, int L,
+                                uint64_t* global_counts, double* mean_counts, const tg_options* opt,
+                                hipStream_t stream) {
+  try {
+    if (num_type_vectors < 1) return fail(TG_ERR_INVALID_ARG, "num_type_vectors must be at least 1");
+    if (!global_counts) return fail(TG_ERR_INVALID_ARG, "null global_counts");
+    tg_status s = count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, nullptr, nullptr, opt, stream,
+                             true, num_type_vectors);
+    if (s != TG_OK || !mean_counts) return s;
+    const int64_t K = nkeys(L);
+    k_mean_counts<<<grid_for(K, 256), 256, 0, stream>>>(num_type_vectors, K, global_counts, mean_counts);
+    TG_LAUNCHED("k_mean_counts");
+    return TG_OK;
   } catch (const std::exception& ex) {
     return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
   } catch (...) {

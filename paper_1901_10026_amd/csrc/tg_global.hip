@@ -480,6 +480,21 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
   gacc_flush(ga, gsm_k4);
 }
 
+// Mean over nty count vectors of K keys (the type-permutation null model's
+// average): exact 128-bit sums, then one division in double.
+__global__ void k_mean_counts(int64_t nty, int64_t K, const uint64_t* __restrict__ counts,
+                              double* __restrict__ mean) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  uint64_t lo = 0, hi = 0;
+  for (int64_t b = 0; b < nty; ++b) {
+    const uint64_t v = counts[b * K + k];
+    lo += v;
+    hi += lo < v ? 1u : 0u;
+  }
+  mean[k] = ((double)hi * 18446744073709551616.0 + (double)lo) / (double)nty;
+}
+
 // Induced counts from the non-induced sums, in place (inverting the
 // relations above per type multiset); flag gets 1 when a sum is not a
 // multiple of its repetition count or a result is negative.

@@ -100,3 +100,16 @@ def test_count_global_rejects_arguments_before_touching_the_device():
     assert lib.tg_count_global(4, 6, None, dummy, dummy, 2, dummy, ctypes.byref(opt), None) == 1
     assert lib.tg_count_global(4, 5, dummy, dummy, dummy, 2, dummy, ctypes.byref(opt), None) == 2
     assert lib.tg_count_global(-1, 6, dummy, dummy, dummy, 2, dummy, None, None) == 1
+    assert lib.tg_count_global_types(4, 6, dummy, dummy, 0, dummy, 2, dummy, None, None, None) == 1
+    assert lib.tg_count_global_types(4, 6, dummy, dummy, 2, dummy, 2, None, None, None, None) == 1
+    assert lib.tg_count_global_types(4, 6, dummy, dummy, 2, dummy, 0, dummy, None, None, None) == 4
+
+
+def test_type_permutations_keep_type_frequencies():
+    types = np.array([0, 1, 1, 2, 2, 2, 3], np.uint8)
+    perms = tg.type_permutations(types, 5, seed=9)
+    assert perms.shape == (5, 7)
+    for p in perms:
+        assert np.array_equal(np.sort(p), types)
+    assert np.array_equal(perms, tg.type_permutations(types, 5, seed=9))
+    assert not np.array_equal(perms, tg.type_permutations(types, 5, seed=10))
