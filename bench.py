@@ -232,6 +232,38 @@ def global_leg(tg, g, rp, ci, ty, out_g, steps=3):
             "count_global_phase_ms": phases, "per_edge_path_global_only_ms": per_edge_ms, "equal": same}
 
 
+def null_leg(tg, g, rp, ci, ty, permutations=100, seed=2024):
+    """Type-permutation null model on the same graph: global counts under
+    `permutations` seeded random permutations of the node types (one
+    tg_count_global_types call) and their mean; the first two permutations
+    are checked against separate tg_count_global calls."""
+    import torch
+    perms = tg.type_permutations(g.types, permutations, seed)
+    tv = torch.from_numpy(perms).to(rp.device)
+    counts, mean = tg.count_global_types(rp, ci, tv[:2].contiguous(), g.L)   # warm-up
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record()
+    counts, mean = tg.count_global_types(rp, ci, tv, g.L)
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1)
+    same = all(bool(torch.equal(counts[b].view(torch.int64),
+                                tg.count_global(rp, ci, tv[b].contiguous(), g.L).view(torch.int64)))
+               for b in range(2))
+    actual = tg.count_global(rp, ci, ty, g.L).cpu().numpy().view(np.uint64).astype(np.float64)
+    mu = mean.cpu().numpy()
+    # keys that occur under the real types but never in any permutation, and
+    # the reverse (the paper's "forbidden" typed motifs)
+    occurs = counts.view(torch.int64).ne(0).any(dim=0).cpu().numpy()
+    log(f"null model: {permutations} permutations in {ms:.0f} ms ({ms / permutations:.1f} ms each), equal={same}")
+    return {"permutations": permutations, "seed": seed, "ms": ms, "ms_per_permutation": ms / permutations,
+            "equal_to_single_calls": same, "keys_only_in_real": int(((actual > 0) & ~occurs).sum()),
+            "keys_only_in_permuted": int(((actual == 0) & occurs).sum()),
+            "keys_nonzero_real": int((actual > 0).sum()), "keys_nonzero_mean": int((mu > 0).sum())}
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -274,6 +306,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs leg")
     ap.add_argument("--no-outputs", action="store_true", help="skip the orbit-row and sparse-row leg")
     ap.add_argument("--no-global", action="store_true", help="skip the global-counts-only leg")
+    ap.add_argument("--no-null", action="store_true", help="skip the type-permutation null-model leg")
+    ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -367,6 +401,8 @@ def main():
         rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)
     if not args.no_global:
         rec["global_only"] = global_leg(tg, g, rp, ci, ty, out_g)
+    if not args.no_null:
+        rec["null_model"] = null_leg(tg, g, rp, ci, ty, permutations=args.permutations)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
     if not args.no_batch:
