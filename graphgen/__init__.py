@@ -211,6 +211,39 @@ class Graph:
 # ---------------------------------------------------------------------------
 # Workload recipes.  Every constant of every input lives here.
 
+def orient(row_ptr, col_idx, seed, p_both=0.2):
+    """Seeded orientation of an undirected CSR graph into a directed one:
+    each edge {u, v} becomes reciprocal with probability p_both, else one arc
+    in a uniformly random direction.  Returns the per-slot direction bits
+    (uint8 [nnz]; bit 0: row -> column, bit 1: column -> row), consistent on
+    the two slots of every edge."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    ci = np.asarray(col_idx, dtype=np.int64)
+    n = len(rp) - 1
+    if len(ci) == 0:
+        return np.zeros(0, np.uint8)
+    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    lo, hi = np.minimum(u, ci), np.maximum(u, ci)
+    order = np.argsort(lo * n + hi, kind="stable")   # the two slots of an edge end up side by side
+    rng = np.random.default_rng(seed)
+    m = len(ci) // 2
+    both = rng.random(m) < p_both
+    fwd = rng.integers(1, 3, size=m)                  # 1: low id -> high id, 2: high -> low
+    code = np.where(both, 3, fwd).astype(np.uint8)    # relative to (low, high)
+    per_slot = np.repeat(code, 2)
+    out = np.empty(len(ci), np.uint8)
+    out[order] = per_slot
+    swap = u > ci                                     # slot read from the high end: swap the two bits
+    out[swap] = ((out[swap] & 1) << 1) | ((out[swap] >> 1) & 1)
+    return out
+
+
+def tiny_digraph(idx: int):
+    """(Graph, slot direction bits) of the idx-th tiny directed test graph."""
+    g = tiny_graph(idx)
+    return g, orient(g.row_ptr, g.col_idx, 5000 + idx, p_both=0.25)
+
+
 def tiny_graph(idx: int) -> Graph:
     """One of the 200 brute-force-checkable graphs: G(n, p), n ~ U{6..12},
     p ~ U(0.2, 0.8), L ~ U{1..4}, uniform types; seed 1000 + idx."""

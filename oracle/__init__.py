@@ -6,7 +6,8 @@ it shares no code with the GPU path.
 
 ``oracle.c`` holds two independent CPU counters (brute force over all 3/4-node
 subsets, and the paper's Algorithms 1-3 with Eqs. 7-17); this module builds
-that file with gcc and wraps it with ctypes.
+that file with gcc and wraps it with ctypes.  ``directed.py`` holds the
+directed typed 3-node counters (plain Python).
 """
 from __future__ import annotations
 

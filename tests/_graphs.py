@@ -20,6 +20,18 @@ def csr_from_edges(n, edges):
     return row_ptr, np.array(cols, dtype=np.int32)
 
 
+def csr_from_arcs(n, arcs):
+    """Support CSR of a set of arcs (u, v) and its per-slot direction bits
+    (bit 0: row -> column, bit 1: column -> row)."""
+    row_ptr, col_idx = csr_from_edges(n, {(min(u, v), max(u, v)) for (u, v) in arcs})
+    sd = np.zeros(len(col_idx), np.uint8)
+    for u in range(n):
+        for s in range(row_ptr[u], row_ptr[u + 1]):
+            v = int(col_idx[s])
+            sd[s] = (1 if (u, v) in arcs else 0) | (2 if (v, u) in arcs else 0)
+    return row_ptr, col_idx, sd
+
+
 def complete(n):
     return csr_from_edges(n, itertools.combinations(range(n), 2))
 
