@@ -250,6 +250,48 @@ tg_status tg_count_global_types(int64_t n, int64_t nnz, const int32_t* row_ptr, 
                                 uint64_t* global_counts, double* mean_counts, const tg_options* opt,
                                 hipStream_t stream);
 
+/* Directed typed 3-node graphlets (the Directed Typed Graphlets subsection:
+ * typed neighbour sets split into typed out- and in-neighbour sets).
+ * Graph: the symmetric support CSR (conventions above) plus one direction
+ * byte per slot, bit 0 for the arc row -> column and bit 1 for column -> row
+ * (so 1, 2 or 3; the two slots of an edge mirror each other).  The direction
+ * code c(u, v) of a pair is the byte at u's slot for v, 0 if not adjacent.
+ * Triad of ordered nodes (a, b, c): arc bits a->b, b->a, a->c, c->a, b->c,
+ * c->b (bits 0..5).  A directed typed triad's key numbers, in increasing
+ * order, the canonical codes (arcs | types[0] << 6 | types[1] << 10 |
+ * types[2] << 14, smallest over the six node orderings) of the weakly
+ * connected triads with types below L: tg_directed3_num_keys(L) keys (13 for
+ * L = 1, the connected triads of the triad census).
+ *   slot_dir      device, uint8[nnz]
+ *   global_counts device, uint64[tg_directed3_num_keys(L)]: the number of
+ *                 node triples inducing each typed triad; or NULL
+ *   edge_rows     device, uint64[m * 15 L], or NULL: per canonical edge
+ *                 (i, j), i < j, column ((4 c(i,k) + c(j,k)) - 1) L + t counts
+ *                 the nodes k of type t with those direction codes to i and j
+ *                 (one of them nonzero)
+ *   edge_info     device, int32[m * 3] receiving (i, j, c(i, j)), or NULL
+ *   opt           host or NULL: validate (also checks the direction bytes),
+ *                 check (global sums divisible by the triad's support
+ *                 edges), phase_ms
+ * Global counts are the row entries summed per key over the triad's 2 or 3
+ * support edges and divided by that number (Eq. 17's argument for triads).
+ */
+tg_status tg_count_directed3(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const uint8_t* slot_dir, const uint8_t* node_types, int L, uint64_t* global_counts,
+                             uint64_t* edge_rows, int32_t* edge_info, const tg_options* opt, hipStream_t stream);
+
+/* Number of directed typed 3-node keys for L types (0 if L is outside
+ * [1, 16]). */
+size_t tg_directed3_num_keys(int L);
+
+/* Host.  Canonical triad of a directed key: *arcs gets its six arc bits,
+ * types its three node types, in the canonical node order. */
+tg_status tg_directed3_key_decode(int L, size_t key, uint8_t* arcs, uint8_t types[3]);
+
+/* Host.  Key of the triad with arc bits `arcs` and node types `types` (any
+ * node order); TG_ERR_INVALID_ARG if the triad is not weakly connected. */
+tg_status tg_directed3_key_encode(int L, uint8_t arcs, const uint8_t types[3], size_t* key);
+
 /* Sparse per-edge output (the Sparse Typed Motif Format subsection: only the
  * nonzero typed graphlet counts of each edge, with their ids).  Turns dense
  * per-edge rows into (global key, count) pairs; keys are the dense key rank

@@ -138,6 +138,20 @@ def edge_rows(row_ptr, col_idx, slot_dir, types, L):
     return np.array(rows, dtype=np.uint64).reshape(-1, 15 * L), np.array(codes, np.int64), ends
 
 
+def rows_for_edges(row_ptr, col_idx, slot_dir, types, L, pairs):
+    """Rows of the given support edges (i, j) only, by the same definition,
+    reading just the rows of their endpoints (for large graphs)."""
+    def row_of(v):
+        lo, hi = int(row_ptr[v]), int(row_ptr[v + 1])
+        return {int(col_idx[s]): int(slot_dir[s]) for s in range(lo, hi)}
+    out = np.zeros((len(pairs), 15 * L), dtype=np.uint64)
+    for e, (i, j) in enumerate(pairs):
+        ri, rj = row_of(int(i)), row_of(int(j))
+        for k in (set(ri) | set(rj)) - {int(i), int(j)}:
+            out[e, (4 * ri.get(k, 0) + rj.get(k, 0) - 1) * L + int(types[k])] += 1
+    return out
+
+
 def rows_to_global(rows, codes, ends, types, L):
     """Global counts from per-edge rows: each triad is seen from each of its
     support edges, so the sums are divided by that number."""

@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1302,6 +1304,8 @@ tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t, const i
 
 // ------------------------------------------------------------------ ABI --
 
+#include "tg_directed.hip"
+
 extern "C" {
 
 void tg_options_default(tg_options* opt) {
@@ -1505,6 +1509,61 @@ tg_status tg_count_global_types(int64_t n, int64_t nnz, const int32_t* row_ptr, 
     return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
   } catch (...) {
     return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+tg_status tg_count_directed3(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const uint8_t* slot_dir, const uint8_t* node_types, int L, uint64_t* global_counts,
+                             uint64_t* edge_rows, int32_t* edge_info, const tg_options* opt, hipStream_t stream) {
+  try {
+    return directed3_impl(n, nnz, row_ptr, col_idx, slot_dir, node_types, L, global_counts, edge_rows, edge_info,
+                          opt, stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+size_t tg_directed3_num_keys(int L) {
+  if (L < 1 || L > 16) return 0;
+  try {
+    return dir3::tables(L).canon.size();
+  } catch (...) {
+    return 0;
+  }
+}
+
+tg_status tg_directed3_key_decode(int L, size_t key, uint8_t* arcs, uint8_t types[3]) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (!arcs || !types) return fail(TG_ERR_INVALID_ARG, "null output pointer");
+  try {
+    const dir3::Tables& T = dir3::tables(L);
+    if (key >= T.canon.size()) return fail(TG_ERR_INVALID_ARG, "key out of range");
+    const int c = T.canon[key];
+    *arcs = (uint8_t)(c & 63);
+    types[0] = (uint8_t)((c >> 6) & 15);
+    types[1] = (uint8_t)((c >> 10) & 15);
+    types[2] = (uint8_t)((c >> 14) & 15);
+    return TG_OK;
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "table construction failed");
+  }
+}
+
+tg_status tg_directed3_key_encode(int L, uint8_t arcs, const uint8_t types[3], size_t* key) {
+  if (L < 1 || L > 16) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 16]");
+  if (!types || !key) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  if (arcs > 63) return fail(TG_ERR_INVALID_ARG, "arcs must be six bits");
+  for (int q = 0; q < 3; ++q)
+    if (types[q] >= L) return fail(TG_ERR_TYPE_RANGE, "type >= L");
+  try {
+    const int32_t r = dir3::tables(L).code2rank[arcs | (types[0] << 6) | (types[1] << 10) | (types[2] << 14)];
+    if (r < 0) return fail(TG_ERR_INVALID_ARG, "the triad is not weakly connected");
+    *key = (size_t)r;
+    return TG_OK;
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "table construction failed");
   }
 }
 

@@ -105,6 +105,31 @@ def test_count_global_rejects_arguments_before_touching_the_device():
     assert lib.tg_count_global_types(4, 6, dummy, dummy, 2, dummy, 0, dummy, None, None, None) == 4
 
 
+def test_directed_keys_agree_with_the_oracle():
+    from oracle import directed as od
+    for L in (1, 2, 5, 16):
+        assert tg.directed3_num_keys(L) == len(od.keys(L))
+    for L in (1, 3):
+        ks = od.keys(L)
+        for q in range(len(ks)):
+            arcs, types = tg.directed3_key_decode(L, q)
+            assert arcs | (types[0] << 6) | (types[1] << 10) | (types[2] << 14) == int(ks[q])
+            # the key does not depend on the node order
+            assert tg.directed3_key_encode(L, arcs, types) == q
+    # the 2-path 0 -> 1 -> 2 (types 1, 0, 0) read backwards as 2 -> 1 -> 0
+    assert tg.directed3_key_encode(2, 0b010001, [1, 0, 0]) == tg.directed3_key_encode(2, 0b100010, [0, 0, 1])
+    with pytest.raises(tg.TGError):
+        tg.directed3_key_encode(2, 0b000001, [0, 0, 0])   # one arc: not connected
+    lib = tg.lib()
+    opt = tg._Options()
+    lib.tg_options_default(ctypes.byref(opt))
+    dummy = ctypes.c_void_p(8)
+    assert lib.tg_count_directed3(4, 6, dummy, dummy, dummy, dummy, 0, dummy, None, None, ctypes.byref(opt), None) == 4
+    assert lib.tg_count_directed3(4, 6, dummy, dummy, None, dummy, 2, dummy, None, None, ctypes.byref(opt), None) == 1
+    assert lib.tg_count_directed3(4, 6, dummy, dummy, dummy, dummy, 2, None, None, None, ctypes.byref(opt), None) == 1
+    assert lib.tg_count_directed3(4, 5, dummy, dummy, dummy, dummy, 2, dummy, None, None, ctypes.byref(opt), None) == 2
+
+
 def test_type_permutations_keep_type_frequencies():
     types = np.array([0, 1, 1, 2, 2, 2, 3], np.uint8)
     perms = tg.type_permutations(types, 5, seed=9)
