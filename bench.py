@@ -264,6 +264,35 @@ def null_leg(tg, g, rp, ci, ty, permutations=100, seed=2024):
             "keys_nonzero_real": int((actual > 0).sum()), "keys_nonzero_mean": int((mu > 0).sum())}
 
 
+def directed_leg(tg, g, rp, ci, ty, steps=3):
+    """Directed typed 3-node graphlets on the same graph oriented by a seeded
+    draw (20% of edges reciprocal, the rest one arc in a random direction):
+    per-edge rows (15 L columns) and global counts."""
+    import torch
+
+    import graphgen
+    sd = torch.from_numpy(graphgen.orient(g.row_ptr, g.col_idx, 99, 0.2)).to(rp.device)
+    K = tg.directed3_num_keys(g.L)
+    glob, rows, _ = tg.count_directed3(rp, ci, sd, ty, g.L)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    phases = {}
+    s0.record()
+    for _ in range(steps):
+        ph = {}
+        tg.count_directed3(rp, ci, sd, ty, g.L, phase_ms=ph)
+        for k, v in ph.items():
+            phases[k] = phases.get(k, 0.0) + v / steps
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / steps
+    log(f"directed 3-node: {ms:.1f} ms ({K} keys, rows of {15 * g.L})")
+    del rows
+    return {"orientation": "seed 99, 20% reciprocal", "keys": K, "row_width": 15 * g.L, "ms": ms,
+            "edges_per_s": g.m / (ms * 1e-3), "phase_ms": {k: v for k, v in phases.items() if v > 0}}
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -307,6 +336,7 @@ def main():
     ap.add_argument("--no-outputs", action="store_true", help="skip the orbit-row and sparse-row leg")
     ap.add_argument("--no-global", action="store_true", help="skip the global-counts-only leg")
     ap.add_argument("--no-null", action="store_true", help="skip the type-permutation null-model leg")
+    ap.add_argument("--no-directed", action="store_true", help="skip the directed 3-node leg")
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -403,6 +433,8 @@ def main():
         rec["global_only"] = global_leg(tg, g, rp, ci, ty, out_g)
     if not args.no_null:
         rec["null_model"] = null_leg(tg, g, rp, ci, ty, permutations=args.permutations)
+    if not args.no_directed:
+        rec["directed3"] = directed_leg(tg, g, rp, ci, ty)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
     if not args.no_batch:
