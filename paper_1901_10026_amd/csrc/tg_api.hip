@@ -881,7 +881,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     int64_t t_cap = 0;
     if (max_t_heavy > TG_T_WG_CAP) {
       t_cap = max_t_heavy;
-      TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
+      TG_HIP(S.get(&t_over, over_scratch_ints(grid, t_cap)));
     }
     if (tg_status s2 = combine_class<256, uint64_t>(st, A, class_count[2], W.elist + class_begin[2], grid, t_over,
                                                     t_cap, K, ea, ea_budget, rows_grid))
@@ -1171,7 +1171,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   int64_t t_cap = 0;
   if (h_tmax > TG_T_WG_CAP) {
     t_cap = h_tmax;
-    TG_HIP(S.get(&t_over, ((int64_t)grid * t_cap * 5 + 3) / 4));
+    TG_HIP(S.get(&t_over, over_scratch_ints(grid, t_cap)));
   }
   const size_t lds = combine_lds_bytes<256, uint64_t>(L);
   k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, count, list, nullptr, t_over, t_cap);

@@ -80,10 +80,24 @@ __device__ __forceinline__ int32_t team_excl_scan(int32_t v, int32_t* total, int
   }
 }
 
-// LDS hash of T_ij for workgroup teams: slot = (node id << 4) | type, -1 empty.
+// Hash of T_ij for workgroup teams: slot = (node id << 4) | type, -1 empty;
+// 2^TG_THASH_LOG2 slots in LDS, or, for a T_ij too long for LDS, 2^hlog
+// slots of global scratch (over_hash_log2 of the scratch capacity).
 #define TG_THASH_LOG2 12
-__device__ __forceinline__ uint32_t thash_home(int32_t k) {
-  return ((uint32_t)k * 2654435761u) >> (32 - TG_THASH_LOG2);
+__device__ __forceinline__ uint32_t thash_home(int32_t k, int hlog) {
+  return ((uint32_t)k * 2654435761u) >> (32 - hlog);
+}
+
+__host__ __device__ inline int over_hash_log2(int64_t cap) {
+  int k = TG_THASH_LOG2 + 1;  // never the LDS table's size, which tells the two apart
+  while ((1ll << k) < 2 * cap) ++k;
+  return k;
+}
+
+// int32 units of the global overflow scratch of `grid` workgroups with
+// capacity `cap`: ids, types (bytes, rounded up to ints), hash slots
+inline int64_t over_scratch_ints(int64_t grid, int64_t cap) {
+  return grid * cap + (grid * cap + 3) / 4 + grid * (1ll << over_hash_log2(cap));
 }
 
 // Copies of the 4-clique cell counters: hits of one cell from several lanes
@@ -96,7 +110,7 @@ struct MuCopies {
 template <int TSIZE, class AccT>
 __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
                                             AccT* __restrict__ acc, AccT* __restrict__ out, int32_t* scratch,
-                                            int tid, int32_t* Th) {
+                                            int tid, int32_t* Th, int hlog) {
   const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
   const int R = 2 * L + 6 * P;
   AccT* Aa = acc;
@@ -105,7 +119,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   AccT* Mu = acc + 3 * LL;  // MuCopies<TSIZE> copies, lane l adds to copy l % copies
   for (int x = tid; x < (3 + MuCopies<TSIZE>::value) * LL; x += TSIZE) acc[x] = 0;
   if (Th)
-    for (int x = tid; x < (1 << TG_THASH_LOG2); x += TSIZE) Th[x] = -1;
+    for (int x = tid; x < (1 << hlog); x += TSIZE) Th[x] = -1;
   tsync<TSIZE>();
   const int32_t i = A.ei[e], j = A.ej[e];
   const int32_t di = A.deg[i], dj = A.deg[j];
@@ -161,8 +175,8 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       Tid[nT + before] = k;
       Tty[nT + before] = (uint8_t)t;
       if (Th) {
-        uint32_t h = thash_home(k);
-        while (atomicCAS(&Th[h], -1, (k << 4) | t) != -1) h = (h + 1) & ((1u << TG_THASH_LOG2) - 1);
+        uint32_t h = thash_home(k, hlog);
+        while (atomicCAS(&Th[h], -1, (k << 4) | t) != -1) h = (h + 1) & ((1u << hlog) - 1);
       }
     }
     nT += total;
@@ -235,13 +249,19 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       // membership of r in T and its type
       int cellv[U];
       if (Th) {
-        constexpr uint32_t hmask = (1u << TG_THASH_LOG2) - 1;
+        const uint32_t hmask = (1u << hlog) - 1;
+        // a table in global scratch was filled by device-scope atomics: read
+        // it at device scope too, past this CU's cache
+        const bool th_global = hlog != TG_THASH_LOG2;
+        auto th_read = [&](uint32_t hh) {
+          return th_global ? __hip_atomic_load(&Th[hh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Th[hh];
+        };
         uint32_t h[U];
         int32_t sv[U];
 #pragma unroll
-        for (int k = 0; k < U; ++k) h[k] = thash_home(r[k] >= 0 ? r[k] : 0);
+        for (int k = 0; k < U; ++k) h[k] = thash_home(r[k] >= 0 ? r[k] : 0, hlog);
 #pragma unroll
-        for (int k = 0; k < U; ++k) sv[k] = r[k] >= 0 ? Th[h[k]] : -1;
+        for (int k = 0; k < U; ++k) sv[k] = r[k] >= 0 ? th_read(h[k]) : -1;
 #pragma unroll
         for (int k = 0; k < U; ++k) {
           cellv[k] = -1;
@@ -251,7 +271,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
               break;
             }
             h[k] = (h[k] + 1) & hmask;
-            sv[k] = Th[h[k]];
+            sv[k] = th_read(h[k]);
           }
         }
       } else {
@@ -441,6 +461,12 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   int32_t* Tid_g = t_over ? t_over + (int64_t)blockIdx.x * t_over_cap : nullptr;
   uint8_t* Tty_g = t_over ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
                           : nullptr;
+  // a T_ij past the LDS capacity keeps its hash in global scratch too
+  const int hlog_g = t_over ? over_hash_log2(t_over_cap) : 0;
+  int32_t* Th_g = (t_over && A.thash_ok)
+                      ? t_over + (int64_t)gridDim.x * t_over_cap + ((int64_t)gridDim.x * t_over_cap + 3) / 4 +
+                            (int64_t)blockIdx.x * (1ll << hlog_g)
+                      : nullptr;
   for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
     const int32_t e = list[w];
     bool big = false;
@@ -450,7 +476,8 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
       big = tsum > (uint32_t)TCAP;
     }
     gather_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
-                             ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? nullptr : Th);
+                             ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? Th_g : Th,
+                             big ? hlog_g : TG_THASH_LOG2);
   }
 }
 
