@@ -84,12 +84,15 @@ __device__ __forceinline__ int32_t team_excl_scan(int32_t v, int32_t* total, int
 // 2^TG_THASH_LOG2 slots in LDS, or, for a T_ij too long for LDS, 2^hlog
 // slots of global scratch (over_hash_log2 of the scratch capacity).
 #define TG_THASH_LOG2 12
+#ifndef TG_THASH16_LOG2
+#define TG_THASH16_LOG2 0
+#endif
 __device__ __forceinline__ uint32_t thash_home(int32_t k, int hlog) {
   return ((uint32_t)k * 2654435761u) >> (32 - hlog);
 }
 
 __host__ __device__ inline int over_hash_log2(int64_t cap) {
-  int k = TG_THASH_LOG2 + 1;  // never the LDS table's size, which tells the two apart
+  int k = 6;
   while ((1ll << k) < 2 * cap) ++k;
   return k;
 }
@@ -110,7 +113,7 @@ struct MuCopies {
 template <int TSIZE, class AccT>
 __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
                                             AccT* __restrict__ acc, AccT* __restrict__ out, int32_t* scratch,
-                                            int tid, int32_t* Th, int hlog) {
+                                            int tid, int32_t* Th, int hlog, bool th_global) {
   const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
   const int R = 2 * L + 6 * P;
   AccT* Aa = acc;
@@ -252,26 +255,37 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
         const uint32_t hmask = (1u << hlog) - 1;
         // a table in global scratch was filled by device-scope atomics: read
         // it at device scope too, past this CU's cache
-        const bool th_global = hlog != TG_THASH_LOG2;
         auto th_read = [&](uint32_t hh) {
           return th_global ? __hip_atomic_load(&Th[hh], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Th[hh];
         };
+        // the home slot and the next one are read for all U ids at once and
+        // decide almost every lookup without a branch; only a run of more
+        // than two occupied slots goes on probing
         uint32_t h[U];
-        int32_t sv[U];
+        int32_t sv[U], sw[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) h[k] = thash_home(r[k] >= 0 ? r[k] : 0, hlog);
 #pragma unroll
-        for (int k = 0; k < U; ++k) sv[k] = r[k] >= 0 ? th_read(h[k]) : -1;
+        for (int k = 0; k < U; ++k) {
+          sv[k] = r[k] >= 0 ? th_read(h[k]) : -1;
+          sw[k] = r[k] >= 0 ? th_read((h[k] + 1) & hmask) : -1;
+        }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-          cellv[k] = -1;
-          while (sv[k] != -1) {
-            if ((sv[k] >> 4) == r[k]) {
-              cellv[k] = rtk[k] * L + (sv[k] & 15);
-              break;
+          const bool hit0 = sv[k] != -1 && (sv[k] >> 4) == r[k];
+          const bool hit1 = sv[k] != -1 && sw[k] != -1 && (sw[k] >> 4) == r[k];
+          cellv[k] = hit0 ? rtk[k] * L + (sv[k] & 15) : (hit1 ? rtk[k] * L + (sw[k] & 15) : -1);
+          if (!hit0 && !hit1 && sv[k] != -1 && sw[k] != -1) {
+            uint32_t hh = (h[k] + 2) & hmask;
+            int32_t x = th_read(hh);
+            while (x != -1) {
+              if ((x >> 4) == r[k]) {
+                cellv[k] = rtk[k] * L + (x & 15);
+                break;
+              }
+              hh = (hh + 1) & hmask;
+              x = th_read(hh);
             }
-            h[k] = (h[k] + 1) & hmask;
-            sv[k] = th_read(h[k]);
           }
         }
       } else {
@@ -432,6 +446,14 @@ struct TeamCap {
   static constexpr int value = TSIZE == 16 ? 64 : (TSIZE == 64 ? 256 : TG_T_WG_CAP);
 };
 
+// log2 of the LDS hash slots of T_ij per team (0: no hash; the sorted ids are
+// searched instead): four slots per id of capacity for wavefront teams, two
+// for workgroup teams
+template <int TSIZE>
+struct THashLog2 {
+  static constexpr int value = TSIZE == 16 ? TG_THASH16_LOG2 : (TSIZE == 64 ? 10 : TG_THASH_LOG2);
+};
+
 // Gather kernel: one team per edge, grid-stride over list[0, count); the
 // accumulators of list[w] go to ea[w * 4L^2 ...] (or nowhere when ea is
 // null: work measurement only).  LDS per team: [acc 4L^2 AccT][scan
@@ -449,7 +471,7 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   const int LL = A.L * A.L;
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
   // per-team region, in bytes, rounded to 8
-  constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
+  constexpr int HBYTES = THashLog2<TSIZE>::value ? (4 << THashLog2<TSIZE>::value) : 0;
   const int acc_bytes = (3 + MuCopies<TSIZE>::value) * LL * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   char* base = (char*)smem_comb + (int64_t)team * region;
@@ -477,7 +499,7 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
     }
     gather_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
                              ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? Th_g : Th,
-                             big ? hlog_g : TG_THASH_LOG2);
+                             big ? hlog_g : THashLog2<TSIZE>::value, big);
   }
 }
 
@@ -486,7 +508,7 @@ template <int TSIZE, class AccT>
 inline size_t combine_lds_bytes(int L) {
   constexpr int TCAP = TeamCap<TSIZE>::value;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
-  constexpr int HBYTES = TSIZE > TG_WAVE ? (4 << TG_THASH_LOG2) : 0;
+  constexpr int HBYTES = THashLog2<TSIZE>::value ? (4 << THashLog2<TSIZE>::value) : 0;
   const int acc_bytes = (3 + MuCopies<TSIZE>::value) * L * L * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   return (size_t)(256 / TSIZE) * region;
