@@ -492,14 +492,16 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
   for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
     const int32_t e = list[w];
     bool big = false;
+    uint32_t tsum = 0;
     if (TSIZE > TG_WAVE) {
-      uint32_t tsum = 0;
       for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
       big = tsum > (uint32_t)TCAP;
     }
+    // a global table sized for this T_ij (at most the block's 2^hlog_g slots)
+    // keeps the probed region small
     gather_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
                              ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? Th_g : Th,
-                             big ? hlog_g : THashLog2<TSIZE>::value, big);
+                             big ? min(hlog_g, over_hash_log2(tsum)) : THashLog2<TSIZE>::value, big);
   }
 }
 
