@@ -293,6 +293,45 @@ def directed_leg(tg, g, rp, ci, ty, steps=3):
             "edges_per_s": g.m / (ms * 1e-3), "phase_ms": {k: v for k, v in phases.items() if v > 0}}
 
 
+def giant_schedules_leg(tg, dev, frac=0.01, seed=31):
+    """The 20M-node skewed graph: per-edge rows of a seeded uniform edge
+    sample (rows only; its rows for all edges would not fit) under the
+    degree-product schedule and the learned one (MLP trained on a 1% edge
+    sample of the same graph), with identical rows."""
+    import torch
+
+    import graphgen
+    t0 = time.time()
+    g = graphgen.workload("cl-20m")
+    log(f"cl-20m: n={g.n} m={g.m} ({time.time() - t0:.0f} s to generate)")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    ty = torch.from_numpy(g.types).to(dev)
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(g.m, size=int(g.m * frac), replace=False)).astype(np.int64)
+    d_ids = torch.from_numpy(ids).to(dev)
+    model = tg.CostModel(seed=57)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    model.train(rp, ci, ty, g.L, sample_frac=0.01, seed=58, epochs=15)
+    train_ms = (time.time() - t0) * 1e3
+    res = {"workload": "cl-20m", "sample_edges": len(ids), "mlp_train_ms": train_ms}
+    rows = {}
+    for sched in ("degree", "learned"):
+        ph = {}
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, r, _ = tg.count(rp, ci, ty, g.L, edge_ids=d_ids, global_counts=False, schedule=sched,
+                           model=model if sched == "learned" else None, phase_ms=ph)
+        torch.cuda.synchronize()
+        res[sched] = {"ms": (time.time() - t0) * 1e3, "phase_ms": ph}
+        rows[sched] = r
+        log(f"cl-20m sample, {sched} schedule: " + " ".join(f"{k}={v:.0f}ms" for k, v in ph.items()))
+    res["equal"] = bool(torch.equal(rows["degree"].view(torch.int64), rows["learned"].view(torch.int64)))
+    log(f"cl-20m rows identical under both schedules: {res['equal']}")
+    return res
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -337,6 +376,9 @@ def main():
     ap.add_argument("--no-global", action="store_true", help="skip the global-counts-only leg")
     ap.add_argument("--no-null", action="store_true", help="skip the type-permutation null-model leg")
     ap.add_argument("--no-directed", action="store_true", help="skip the directed 3-node leg")
+    ap.add_argument("--giant-schedules", action="store_true",
+                    help="also compare the degree and learned schedules on a 1%% edge sample of the 20M-node graph "
+                         "(several minutes)")
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -437,6 +479,8 @@ def main():
         rec["directed3"] = directed_leg(tg, g, rp, ci, ty)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
+    if args.giant_schedules:
+        rec["giant_schedules"] = giant_schedules_leg(tg, dev)
     if not args.no_batch:
         rec["batch"] = batch_leg(tg, dev)
     if not args.no_cpu_baseline:
