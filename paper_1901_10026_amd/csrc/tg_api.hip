@@ -1032,7 +1032,11 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
   std::vector<uint64_t> sig = {(uint64_t)dev, (uint64_t)G, (uint64_t)node_off, (uint64_t)slot_off, (uint64_t)rp,
                                (uint64_t)ci, (uint64_t)ty, (uint64_t)Lg, (uint64_t)key_off, (uint64_t)out,
                                (uint64_t)ctr, (uint64_t)list};
-  for (auto& l : plan) { sig.push_back((uint64_t)l.variant); sig.push_back((uint64_t)l.offset); sig.push_back((uint64_t)l.count); }
+  for (auto& l : plan) {
+    sig.push_back((uint64_t)l.variant);
+    sig.push_back((uint64_t)l.offset);
+    sig.push_back((uint64_t)l.count);
+  }
   BatchGraphCache& C = batch_cache();
   if (!C.valid || C.sig != sig) {
     C.reset();
