@@ -2,6 +2,7 @@
 // The kernels live in tg_kernels.hip, compiled into this translation unit.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -60,26 +61,86 @@ tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t n, const
 
 // Stream-ordered scratch: every allocation is released on the same stream when
 // the owner goes out of scope.  The default pool keeps freed memory cached.
+// A per-device workspace reused by successive calls: allocation through the
+// stream-ordered pool costs tens of microseconds per buffer, which a call
+// with forty buffers pays twice, with the device idle in between once the
+// caller waits for a result.  One call at a time holds the workspace (others
+// allocate from the pool as before); its buffers are carved out of it in
+// order, and requests beyond its size go to the pool and make the next
+// holder grow it to the last call's total.  A holder on another stream
+// first waits for the previous holder's work.
+struct Workspace {
+  std::atomic<bool> busy{false};
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t want = 0;  // total of the last holder's requests
+  hipEvent_t done = nullptr;
+  hipStream_t last = nullptr;
+  bool used = false;
+};
+
+inline Workspace* device_workspace() {
+  static Workspace ws[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  return &ws[dev];
+}
+
 struct Scratch {
   hipStream_t stream;
-  std::vector<void*> ptrs;
-  explicit Scratch(hipStream_t s) : stream(s) {}
+  std::vector<void*> ptrs;  // pool allocations
+  Workspace* ws = nullptr;  // held workspace, or null
+  size_t off = 0, total = 0;
+  explicit Scratch(hipStream_t s) : stream(s) {
+    Workspace* w = device_workspace();
+    bool expect = false;
+    if (!w || !w->busy.compare_exchange_strong(expect, true)) return;
+    ws = w;
+    if (ws->used && ws->last != stream && ws->done) (void)hipStreamWaitEvent(stream, ws->done, 0);
+    if (ws->want > ws->cap) {
+      // grow to the last call's total (a tenth more), freed in stream order
+      if (ws->base) (void)hipFreeAsync(ws->base, stream);
+      ws->base = nullptr;
+      ws->cap = 0;
+      const size_t cap = ws->want + ws->want / 10;
+      void* p = nullptr;
+      if (hipMallocAsync(&p, cap, stream) == hipSuccess) {
+        ws->base = (char*)p;
+        ws->cap = cap;
+      }
+    }
+  }
   ~Scratch() {
     for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+    if (!ws) return;
+    if (!ws->done) (void)hipEventCreateWithFlags(&ws->done, hipEventDisableTiming);
+    if (ws->done) (void)hipEventRecord(ws->done, stream);
+    ws->last = stream;
+    ws->used = true;
+    ws->want = total;
+    ws->busy.store(false);
   }
   template <class T>
   hipError_t get(T** out, int64_t count) {
     *out = nullptr;
     if (count <= 0) count = 1;
+    const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+    if (ws) {
+      total += bytes;
+      if (ws->base && off + bytes <= ws->cap) {
+        *out = (T*)(ws->base + off);
+        off += bytes;
+        return hipSuccess;
+      }
+    }
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(T), stream);
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
     if (e != hipSuccess) return e;
     ptrs.push_back(p);
     *out = (T*)p;
     return hipSuccess;
   }
 };
-
 void keep_pool_cached() {
   static bool done[64] = {};
   int dev = 0;
