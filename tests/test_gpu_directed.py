@@ -135,3 +135,16 @@ def test_full_size_rows_and_directions():
     supp = np.array([od.support_edges(tg.directed3_key_decode(L, k)[0]) for k in range(len(gl))])
     total_rows = int(rows.view(torch.int64).sum().item())
     assert int((gl.astype(object) * supp).sum()) == total_rows
+
+
+def test_edgeless_and_empty_digraphs():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    for n in (0, 4):
+        rp, ci, ty = to_dev(np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(n, np.uint8))
+        sd = torch.zeros(0, dtype=torch.uint8, device=rp.device)
+        glob, rows, _ = tg.count_directed3(rp, ci, sd, ty, 3, validate=n > 0)
+        torch.cuda.synchronize()
+        assert rows.shape == (0, 45) and int(glob.view(torch.int64).abs().sum()) == 0
+        assert glob.numel() == tg.directed3_num_keys(3)

@@ -89,3 +89,21 @@ def test_full_size_permutations_equal_single_counts():
         single = tg.count_global(rp, ci, tv[b].contiguous(), g.L)
         torch.cuda.synchronize()
         assert torch.equal(counts[b].view(torch.int64), single.view(torch.int64)), b
+
+
+def test_one_type_vector_and_an_edgeless_graph():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.tiny_graph(17)
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    counts, mean = tg.count_global_types(rp, ci, ty.view(1, -1).contiguous(), g.L)
+    single = tg.count_global(rp, ci, ty, g.L)
+    torch.cuda.synchronize()
+    assert torch.equal(counts[0].view(torch.int64), single.view(torch.int64))
+    assert np.array_equal(mean.cpu().numpy(), single.cpu().numpy().view(np.uint64).astype(np.float64))
+    rp0, ci0, _ = to_dev(np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(5, np.uint8))
+    tv = torch.zeros((3, 5), dtype=torch.uint8, device=rp0.device)
+    counts, mean = tg.count_global_types(rp0, ci0, tv, 2)
+    torch.cuda.synchronize()
+    assert int(counts.view(torch.int64).abs().sum()) == 0 and float(mean.abs().sum()) == 0.0

@@ -103,3 +103,15 @@ def test_sparse_rows_of_the_five_node_census():
         dense = rows.cpu().numpy().view(np.uint64)
         assert int(off[-1]) == int((dense != 0).sum()), gi
         assert int(cnts.cpu().numpy().view(np.uint64).sum()) == int(dense.sum()), gi
+
+
+def test_sparse_rows_of_an_edgeless_graph():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    rp, ci, ty = to_dev(np.zeros(4, np.int32), np.zeros(0, np.int32), np.zeros(3, np.uint8))
+    _, rows, ends = tg.count(rp, ci, ty, 2, endpoints=True)
+    off, keys, cnts = tg.rows_sparse(rows, ends, ty, 2)
+    torch.cuda.synchronize()
+    assert rows.shape == (0, tg.edge_row_width(2))
+    assert off.cpu().tolist() == [0] and keys.numel() == 0 and cnts.numel() == 0
