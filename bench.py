@@ -332,6 +332,40 @@ def giant_schedules_leg(tg, dev, frac=0.01, seed=31):
     return res
 
 
+def giant_global_leg(tg, dev):
+    """The 20M-node skewed graph counted in full for its global counts alone
+    (tg_count_global), with its 8 types and again with one type: the typed
+    counts of each shape must add up to the untyped one."""
+    import torch
+
+    import graphgen
+    g = graphgen.workload("cl-20m")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    ty = torch.from_numpy(g.types).to(dev)
+    res = {"workload": "cl-20m", "n": g.n, "m": g.m, "L": g.L}
+    out = {}
+    for label, types, L in (("typed", ty, g.L), ("untyped", torch.zeros_like(ty), 1)):
+        ph = {}
+        torch.cuda.synchronize()
+        t0 = time.time()
+        glob = tg.count_global(rp, ci, types, L, phase_ms=ph)
+        torch.cuda.synchronize()
+        res[label] = {"ms": (time.time() - t0) * 1e3, "phase_ms": ph}
+        out[label] = glob.cpu().numpy().view(np.uint64)
+        log(f"cl-20m global counts, {label}: {res[label]['ms']:.0f} ms (" +
+            " ".join(f"{k}={v:.0f}" for k, v in ph.items()) + ")")
+    per_shape = {}
+    for k in range(len(out["typed"])):
+        sh = tg.key_decode(g.L, k)[0]
+        per_shape[sh] = per_shape.get(sh, 0) + int(out["typed"][k])
+    res["per_shape"] = [per_shape.get(sh, 0) for sh in range(8)]
+    res["untyped"]["counts"] = [int(x) for x in out["untyped"]]
+    res["partition_holds"] = res["per_shape"] == res["untyped"]["counts"]
+    log(f"cl-20m typed counts add up to the untyped ones per shape: {res['partition_holds']}")
+    return res
+
+
 def batch_leg(tg, dev, steps=3):
     """100,000 small typed graphs (n log-uniform in [10, 500], density
     U(0.02, 0.3), L uniform in 2..8) counted by tg_count_batch, autotuned."""
@@ -376,6 +410,8 @@ def main():
     ap.add_argument("--no-global", action="store_true", help="skip the global-counts-only leg")
     ap.add_argument("--no-null", action="store_true", help="skip the type-permutation null-model leg")
     ap.add_argument("--no-directed", action="store_true", help="skip the directed 3-node leg")
+    ap.add_argument("--giant-global", action="store_true",
+                    help="also count the 20M-node graph's global counts in full, typed and untyped (minutes)")
     ap.add_argument("--giant-schedules", action="store_true",
                     help="also compare the degree and learned schedules on a 1%% edge sample of the 20M-node graph "
                          "(several minutes)")
@@ -479,6 +515,8 @@ def main():
         rec["directed3"] = directed_leg(tg, g, rp, ci, ty)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
+    if args.giant_global:
+        rec["giant_global"] = giant_global_leg(tg, dev)
     if args.giant_schedules:
         rec["giant_schedules"] = giant_schedules_leg(tg, dev)
     if not args.no_batch:
