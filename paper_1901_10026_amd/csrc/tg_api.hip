@@ -846,19 +846,19 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       const GAcc ga_k4 = make_gacc(gb, 2 * C3k + 5 * C4k, C4k, 16 << 10);
       if (hk[0] > 0) {
         k_glob_k4<16><<<grid_for(hk[0], 16, 4096), 256, k4_lds_bytes<16>(ga_k4, L, mcop), st>>>(
-            hk[0], W.elist, W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0, ga_k4);
+            hk[0], W.elist, W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0, 0, ga_k4);
         TG_LAUNCHED("k_glob_k4<16>");
       }
       if (hk[1] > 0) {
         k_glob_k4<64><<<grid_for(hk[1], 4, 4096), 256, k4_lds_bytes<64>(ga_k4, L, mcop), st>>>(
             hk[1], W.elist + kcur[1], W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, 0, nullptr, 0,
-            ga_k4);
+            0, ga_k4);
         TG_LAUNCHED("k_glob_k4<64>");
       }
       if (hk[2] > 0) {
         k_glob_k4<256><<<grid_wg, 256, k4_lds_bytes<256>(ga_k4, L, mcop), st>>>(
             hk[2], W.elist + kcur[2], W.ei, W.ej, W.deg, tyb, W.out_off, W.out_col, W.tau, L, mcop, tcap, t_over,
-            t_cap, ga_k4);
+            t_cap, n < (1ll << 27) ? 1 : 0, ga_k4);
         TG_LAUNCHED("k_glob_k4<256>");
       }
       k_glob_finalize<<<grid_for(std::max(C3k, C4k), 256), 256, 0, st>>>(gb, L, flag);

@@ -276,11 +276,20 @@ struct K4Cap {
   static constexpr int value = TSIZE == 16 ? 64 : (TSIZE == 64 ? 1024 : 4096);
 };
 
+// LDS hash slots of T+ for workgroup teams (two per id of capacity; slot =
+// id << 4 | type, -1 empty): their edges probe T+ hundreds of thousands of
+// times, where a lookup of one or two reads beats a 12-step search
+template <int TSIZE>
+struct K4Hash {
+  static constexpr int value = TSIZE > TG_WAVE ? 2 * K4Cap<TSIZE>::value : 0;
+};
+
 // per-team LDS bytes of k_glob_k4 after the key copies: scan scratch, the
-// cell counters (mcopies copies of L x L), the T+ ids and types
+// cell counters (mcopies copies of L x L), the T+ ids and types, the hash
 template <int TSIZE>
 __host__ __device__ inline int k4_team_bytes(int L, int mcopies) {
-  return ((TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8) * 4 + mcopies * L * L * 4 + K4Cap<TSIZE>::value * 5 + 7) & ~7;
+  return ((TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8) * 4 + mcopies * L * L * 4 + K4Cap<TSIZE>::value * 5 +
+          K4Hash<TSIZE>::value * 4 + 7) & ~7;
 }
 
 template <int TSIZE>
@@ -309,7 +318,7 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
                                                  const int32_t* __restrict__ out_col,
                                                  const uint32_t* __restrict__ tau, int L, int mcopies,
                                                  int tcap, int32_t* __restrict__ t_over, int64_t t_over_cap,
-                                                 GAcc ga) {
+                                                 int thash_ok, GAcc ga) {
   extern __shared__ uint64_t gsm_k4[];
   gacc_init(ga, gsm_k4);
   constexpr int TEAMS = 256 / TSIZE;
@@ -323,6 +332,9 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
   uint32_t* cell = (uint32_t*)(scratch + SCR);
   int32_t* Tid_l = (int32_t*)(cell + mcopies * LL);
   uint8_t* Tty_l = (uint8_t*)(Tid_l + TCAP);
+  constexpr int HS = K4Hash<TSIZE>::value;
+  constexpr int HLOG = HS > 1 ? 31 - __builtin_clz((unsigned)(HS > 1 ? HS : 2)) : 1;
+  int32_t* Th = HS ? (int32_t*)(Tty_l + TCAP) : nullptr;  // TCAP is a multiple of 4
   for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
     const int32_t e = list[w];
     const int32_t i = ei[e], j = ej[e];
@@ -346,6 +358,10 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
     uint8_t* Tty = big ? (uint8_t*)(t_over + (int64_t)gridDim.x * t_over_cap) + (int64_t)blockIdx.x * t_over_cap
                        : Tty_l;
     for (int x = tid; x < mcopies * LL; x += TSIZE) cell[x] = 0u;
+    // an LDS T+ of a workgroup team also goes into the LDS hash
+    const bool use_hash = HS && !big && thash_ok;
+    if (use_hash)
+      for (int x = tid; x < HS; x += TSIZE) Th[x] = -1;
     // ---- T+, in id order: U scanned ids per lane, searched together
     int32_t nT = 0;
     int top = 1;
@@ -389,8 +405,13 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
           __syncthreads();
         }
         if (found) {
+          const int tk = ty[kv[k]];
           Tid[nT + before] = kv[k];
-          Tty[nT + before] = ty[kv[k]];
+          Tty[nT + before] = (uint8_t)tk;
+          if (use_hash) {
+            uint32_t h = ((uint32_t)kv[k] * 2654435761u) >> (32 - HLOG);
+            while (atomicCAS(&Th[h], -1, (kv[k] << 4) | tk) != -1) h = (h + 1) & (HS - 1);
+          }
         }
         nT += total;
       }
@@ -451,19 +472,54 @@ __global__ void __launch_bounds__(256) k_glob_k4(int64_t count, const int32_t* _
             r[k] = v[k] < tot ? out_col[o_start + (v[k] - o_excl)] : -1;
             p[k] = 0;
           }
-          // lower bound in the sorted T+, the same steps for all U pairs
-          for (int step = ttop; step > 0; step >>= 1) {
-            int32_t tv[U];
+          if (use_hash) {
+            // the home slot and the next one settle almost every lookup
+            uint32_t h[U];
+            int32_t sv[U], sw[U];
 #pragma unroll
-            for (int k = 0; k < U; ++k) tv[k] = p[k] + step <= nT ? Tid[p[k] + step - 1] : INT32_MAX;
+            for (int k = 0; k < U; ++k) {
+              h[k] = ((uint32_t)(r[k] >= 0 ? r[k] : 0) * 2654435761u) >> (32 - HLOG);
+              sv[k] = r[k] >= 0 ? Th[h[k]] : -1;
+              sw[k] = r[k] >= 0 ? Th[(h[k] + 1) & (HS - 1)] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+              int cellv = -1;
+              if (sv[k] != -1 && (sv[k] >> 4) == r[k]) {
+                cellv = rtk[k] * L + (sv[k] & 15);
+              } else if (sv[k] != -1 && sw[k] != -1) {
+                if ((sw[k] >> 4) == r[k]) {
+                  cellv = rtk[k] * L + (sw[k] & 15);
+                } else {
+                  uint32_t hh = (h[k] + 2) & (HS - 1);
+                  int32_t x = Th[hh];
+                  while (x != -1) {
+                    if ((x >> 4) == r[k]) {
+                      cellv = rtk[k] * L + (x & 15);
+                      break;
+                    }
+                    hh = (hh + 1) & (HS - 1);
+                    x = Th[hh];
+                  }
+                }
+              }
+              if (cellv >= 0) atomicAdd(&cell[(lane() % mcopies) * LL + cellv], 1u);
+            }
+          } else {
+            // lower bound in the sorted T+, the same steps for all U pairs
+            for (int step = ttop; step > 0; step >>= 1) {
+              int32_t tv[U];
+#pragma unroll
+              for (int k = 0; k < U; ++k) tv[k] = p[k] + step <= nT ? Tid[p[k] + step - 1] : INT32_MAX;
+#pragma unroll
+              for (int k = 0; k < U; ++k)
+                if (tv[k] < r[k]) p[k] += step;
+            }
 #pragma unroll
             for (int k = 0; k < U; ++k)
-              if (tv[k] < r[k]) p[k] += step;
+              if (r[k] >= 0 && p[k] < nT && Tid[p[k]] == r[k])
+                atomicAdd(&cell[(lane() % mcopies) * LL + rtk[k] * L + Tty[p[k]]], 1u);
           }
-#pragma unroll
-          for (int k = 0; k < U; ++k)
-            if (r[k] >= 0 && p[k] < nT && Tid[p[k]] == r[k])
-              atomicAdd(&cell[(lane() % mcopies) * LL + rtk[k] * L + Tty[p[k]]], 1u);
         }
         if (TSIZE > TG_WAVE) __syncthreads();
       }
