@@ -34,8 +34,12 @@
  *
  * Memory: pointers documented as "device" must point to device memory of the
  * current HIP device (e.g. torch tensors); "host" pointers to host memory.
- * The caller owns every input and output buffer.  Scratch memory is allocated
- * and released by the library, stream-ordered on the caller's stream.
+ * The caller owns every input and output buffer.  Scratch memory belongs to
+ * the library: a per-device workspace that one call at a time holds and that
+ * later calls reuse (grown to the last call's need, kept until the process
+ * ends; a call on another stream first waits for the previous holder's
+ * work), with any excess and concurrent calls served stream-ordered on the
+ * caller's stream from the default pool.
  *
  * Streams and errors: all device work is enqueued on `stream`.  Argument
  * errors are reported before anything is enqueued.  Device-detected problems
