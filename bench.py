@@ -89,20 +89,36 @@ def graph_stats(g):
     return dict(n=n, m=len(ei), nnz=len(ci), deg=d, ei=ei, ej=ej)
 
 
-def combine_bytes(st, L, tau_sum):
+# bytes of the common-neighbour lists the library keeps (12 B per entry of
+# the bound, the shorter row's length, summed over the edges)
+TLIST_BUDGET = 16 << 30
+
+
+def keeps_lists(st):
+    d = st["deg"]
+    return 12 * int(np.minimum(d[st["ei"]], d[st["ej"]]).sum()) <= TLIST_BUDGET
+
+
+def combine_bytes(st, L, tau_sum, lists):
     """Algorithmic bytes of the per-edge combine kernel (one launch = every
-    edge): edge endpoints (8 B), both CSR rows read once (4 B per id), their
-    row offsets (16 B), typed degree and node tables of both endpoints
-    (2 x (4L + 16 L^2) B), the edge's own typed triangle counts (4L B) and
-    typed 4-cycle counts (8P B), per member of T_ij its type (1 B), the typed
-    triangle counts of (i,k) and (j,k) and the typed degree of k (12L B), and
-    the written row (8R B)."""
+    edge): edge endpoints (8 B), row offsets of both ends (16 B), typed
+    degree and node tables of both endpoints (2 x (4L + 16 L^2) B), the
+    edge's own typed triangle counts (4L B) and typed 4-cycle counts (8P B),
+    per member of T_ij its type (1 B), the typed triangle counts of (i,k) and
+    (j,k) and the typed degree of k (12L B), and the written row (8R B).
+    T_ij itself is either found by intersecting both CSR rows (4 B per id of
+    either row) or, with the lists the tau pass keeps, read from that list
+    (its offset, 8 B per edge, and 12 B per member: the id and two edge
+    ids)."""
     P = L * (L + 1) // 2
     R = 2 * L + 6 * P
     d = st["deg"]
     per_edge_fixed = 8 + 16 + 2 * (4 * L + 16 * L * L) + 4 * L + 8 * P + 8 * R
-    rows = 4 * (d[st["ei"]] + d[st["ej"]]).sum()
-    return int(st["m"] * per_edge_fixed + rows + tau_sum * (1 + 12 * L))
+    if lists:
+        tset = 8 * st["m"] + 12 * tau_sum
+    else:
+        tset = 4 * (d[st["ei"]] + d[st["ej"]]).sum()
+    return int(st["m"] * per_edge_fixed + tset + tau_sum * (1 + 12 * L))
 
 
 def cpu_baseline(g, seconds, threads):
@@ -477,7 +493,8 @@ def main():
     tri_keys = [k for k in range(K) if tg.key_decode(g.L, k)[0] == 1]
     tau_sum = 3 * int(sum(int(glob[k]) for k in tri_keys))
     st = graph_stats(g)
-    cb = combine_bytes(st, g.L, tau_sum)
+    lists = keeps_lists(st)
+    cb = combine_bytes(st, g.L, tau_sum, lists)
     comb_ms = phases.get("combine", 0.0)
     achieved = cb / (comb_ms * 1e-3) / 1e9 if comb_ms > 0 else 0.0
     rec = {
@@ -503,7 +520,8 @@ def main():
                      "kernel": "combine phase: gather kernels k_combine<16>, k_combine<64>, k_combine<256> and "
                                "their k_combine_rows launches, together every edge once",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": stored_traffic(g.name)},
+                     "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": stored_traffic(g.name),
+                     "t_ij_from": "kept lists" if lists else "row intersection"},
     }
     if not args.no_compare:
         rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)

@@ -116,6 +116,10 @@ typedef struct {
   int32_t clique_wave_max;    /* ... at most this long (<= 1024) a wavefront, longer ones a workgroup */
   int32_t clique_lds_ids;     /* tg_count_global: common higher neighbours kept in LDS by a workgroup
                                  team (<= 4096); more go to global scratch */
+  int32_t tlist_budget_mib;   /* tg_count: the typed-triangle pass keeps every edge's common-neighbour
+                                 list (12 B per entry, sized by min(d_i, d_j)) for the per-edge gather
+                                 when all lists fit in this many MiB of scratch; else (and at 0) the
+                                 gather intersects the two rows again */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */

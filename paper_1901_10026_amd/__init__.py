@@ -62,10 +62,11 @@ class Tuning(ctypes.Structure):
                 ("c4_group_kwedges", ctypes.c_int32), ("c4_chunk", ctypes.c_int32),
                 ("c4_hash_ratio", ctypes.c_int32), ("c4_slot_budget_mb", ctypes.c_int32), ("c4_slices", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32 * 9), ("clique_team_max", ctypes.c_int32),
-                ("clique_wave_max", ctypes.c_int32), ("clique_lds_ids", ctypes.c_int32)]
+                ("clique_wave_max", ctypes.c_int32), ("clique_lds_ids", ctypes.c_int32),
+                ("tlist_budget_mib", ctypes.c_int32)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
                "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
-               "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids")
+               "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids", "tlist_budget_mib")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

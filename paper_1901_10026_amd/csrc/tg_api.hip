@@ -267,9 +267,12 @@ tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, con
 // Scratch allocation, preprocessing, typed triangles and node tables: the
 // part of the pipeline shared by counting and by cost-model training.
 // Without `tables` (global counts counted once) the node tables P, U and the
-// per-edge 4-cycle counters are neither allocated nor filled.
+// per-edge 4-cycle counters are neither allocated nor filled.  When the
+// common-neighbour lists of all edges fit in `list_budget` bytes the tau
+// pass also keeps them.
 tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
-                        const uint8_t* ty, int L, Work& W, PhaseTimer* timer, bool tables = true) {
+                        const uint8_t* ty, int L, Work& W, PhaseTimer* timer, bool tables = true,
+                        int64_t list_budget = 0) {
   const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
   TG_HIP(S.get(&W.deg, n));
   TG_HIP(S.get(&W.D, n * L));
@@ -311,9 +314,37 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
 
   // ---- typed triangles per edge, node tables
   if (timer) timer->mark(TG_PHASE_TAU);
-  k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  // common-neighbour lists of the edges, so that the per-edge gather does not
+  // intersect the rows again (only when the bound on their size fits the
+  // budget)
+  W.tl_off = nullptr;
+  W.tl_k = W.tl_e = nullptr;
+  if (m > 0 && 12 * m <= list_budget) {  // every list holds at least one id
+    uint64_t* d_total;
+    TG_HIP(S.get(&d_total, 1));
+    k_fill_u64<<<1, 64, 0, st>>>(d_total, 1, 0);
+    TG_LAUNCHED("k_fill_u64");
+    k_tl_total<<<grid_for(m, 256, 2048), 256, 0, st>>>(m, W.ei, W.ej, W.deg, d_total);
+    TG_LAUNCHED("k_tl_total");
+    uint64_t total = 0;
+    TG_HIP(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (total * 12 <= (uint64_t)list_budget) {
+      int64_t* bound;
+      TG_HIP(S.get(&bound, m));
+      TG_HIP(S.get(&W.tl_off, m + 1));
+      k_tl_bound<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, bound);
+      TG_LAUNCHED("k_tl_bound");
+      if (tg_status s = scan(S, st, m, (const int64_t*)bound, W.tl_off)) return s;
+      TG_HIP(S.get(&W.tl_k, (int64_t)total));
+      TG_HIP(S.get(&W.tl_e, 2 * (int64_t)total));
+    }
+  }
+  k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.tl_off,
+                                                   W.tl_k, W.tl_e, W.s2e);
   TG_LAUNCHED("k_tau<16>");
-  k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau);
+  k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.tl_off,
+                                                  W.tl_k, W.tl_e, W.s2e);
   TG_LAUNCHED("k_tau<64>");
   if (timer) timer->mark(TG_PHASE_TABLES);
   if (tables) {
@@ -413,15 +444,16 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   }
   if (m == 0) return TG_OK;
 
+  tg_tuning tune;
+  tg_tuning_default(&tune);
+  if (opt.tuning) tune = *opt.tuning;
   Work W;
-  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once)) return s;
+  const int64_t list_budget = once ? 0 : (int64_t)std::max(0, tune.tlist_budget_mib) << 20;
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once, list_budget)) return s;
 
   // ---- schedule: edge classes and cost buckets, node tiers
   timer.mark(TG_PHASE_SCHEDULE);
   const int mode = opt.schedule == TG_SCHED_NONE ? 0 : (opt.schedule == TG_SCHED_DEGREE ? 1 : 2);
-  tg_tuning tune;
-  tg_tuning_default(&tune);
-  if (opt.tuning) tune = *opt.tuning;
   BinParams bp{mode,
                std::max(1, tune.light_max_degree),
                std::max(1, tune.heavy_min_degree),
@@ -833,8 +865,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
         k_node_stats<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, tyb, L, W.D, W.n_upper, W.n_out,
                                                      W.wedge_work, W.nbr_deg_sum);
         TG_LAUNCHED("k_node_stats");
-        k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau);
-        k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau);
+        k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
+                                                         nullptr, nullptr, nullptr, nullptr);
+        k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
+                                                        nullptr, nullptr, nullptr, nullptr);
         TG_LAUNCHED("k_tau");
       }
       const GAcc ga_all = make_gacc(gb, 0, K, 32 << 10);
@@ -882,6 +916,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e;
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
   A.c4_rows = slot_rows ? 0 : m;
@@ -1222,6 +1257,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
+  A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e;
   A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
   A.c4_wide = 1;
   A.c4_rows = 0;
@@ -1407,6 +1443,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->clique_team_max = 64;
   t->clique_wave_max = 1024;
   t->clique_lds_ids = 4096;
+  t->tlist_budget_mib = 16384;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,

@@ -133,7 +133,34 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   const int wv = tid / TG_WAVE;
 
   // ---- T_ij with the sums of tau and D over its members
+  auto add_member = [&](int32_t k, int t, int64_t ea, int64_t eb) {
+    for (int u = 0; u < L; ++u) {
+      const uint32_t va = A.tau[ea * L + u];
+      if (va) atomicAdd(&Aa[t * L + u], (AccT)va);
+      const uint32_t vb = A.tau[eb * L + u];
+      if (vb) atomicAdd(&Ab[t * L + u], (AccT)vb);
+      const uint32_t vd = A.D[(int64_t)k * L + u];
+      if (vd) atomicAdd(&Q[t * L + u], (AccT)vd);
+    }
+  };
+  auto hash_member = [&](int32_t k, int t) {
+    uint32_t h = thash_home(k, hlog);
+    while (atomicCAS(&Th[h], -1, (k << 4) | t) != -1) h = (h + 1) & ((1u << hlog) - 1);
+  };
   int32_t nT = 0;
+  if (A.tl_off) {
+    // kept by the tau pass, in id order: |T_ij| is the sum of tau(i, j)
+    for (int u = 0; u < L; ++u) nT += (int32_t)A.tau[(int64_t)e * L + u];
+    const int64_t base = A.tl_off[e];
+    for (int32_t q = tid; q < nT; q += TSIZE) {
+      const int32_t k = A.tl_k[base + q];
+      const int t = A.ty[k];
+      add_member(k, t, A.tl_e[2 * (base + q)], A.tl_e[2 * (base + q) + 1]);
+      Tid[q] = k;
+      Tty[q] = (uint8_t)t;
+      if (Th) hash_member(k, t);
+    }
+  } else
   for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
     const int32_t idx = b0 + tid;
     bool found = false;
@@ -146,15 +173,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
     int t = 0;
     if (found) {
       t = A.ty[k];
-      const int64_t ea = A.s2e[ra + idx], eb = A.s2e[rb + p];
-      for (int u = 0; u < L; ++u) {
-        const uint32_t va = A.tau[ea * L + u];
-        if (va) atomicAdd(&Aa[t * L + u], (AccT)va);
-        const uint32_t vb = A.tau[eb * L + u];
-        if (vb) atomicAdd(&Ab[t * L + u], (AccT)vb);
-        const uint32_t vd = A.D[(int64_t)k * L + u];
-        if (vd) atomicAdd(&Q[t * L + u], (AccT)vd);
-      }
+      add_member(k, t, A.s2e[ra + idx], A.s2e[rb + p]);
     }
     const uint64_t wmask = ballot(found);
     int32_t before, total;
@@ -177,10 +196,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
     if (found) {
       Tid[nT + before] = k;
       Tty[nT + before] = (uint8_t)t;
-      if (Th) {
-        uint32_t h = thash_home(k, hlog);
-        while (atomicCAS(&Th[h], -1, (k << 4) | t) != -1) h = (h + 1) & ((1u << hlog) - 1);
-      }
+      if (Th) hash_member(k, t);
     }
     nT += total;
   }

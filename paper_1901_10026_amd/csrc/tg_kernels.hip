@@ -239,7 +239,9 @@ template <int TSIZE>
 __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi, const int32_t* __restrict__ ei,
                                              const int32_t* __restrict__ ej, const int32_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
-                                             const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau) {
+                                             const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau,
+                                             const int64_t* __restrict__ tl_off, int32_t* __restrict__ tl_k,
+                                             int32_t* __restrict__ tl_e, const int32_t* __restrict__ s2e) {
   constexpr int TEAMS = 256 / TSIZE;
   const int team = threadIdx.x / TSIZE, tl = threadIdx.x % TSIZE;
   for (int64_t e = (int64_t)blockIdx.x * TEAMS + team; e < m; e += (int64_t)gridDim.x * TEAMS) {
@@ -248,18 +250,34 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
     const bool ia = di <= dj;
     const int32_t la = ia ? di : dj, lb = ia ? dj : di;
     if (la <= dlo || la > dhi) continue;
-    const int32_t* pa = ci + rp[ia ? i : j];
-    const int32_t* pb = ci + rp[ia ? j : i];
+    const int32_t ra = rp[ia ? i : j], rb = rp[ia ? j : i];
+    const int32_t* pa = ci + ra;
+    const int32_t* pb = ci + rb;
+    // with lists, the edge keeps its common neighbours in id order, with the
+    // ids of the edges from both ends to each
+    const bool keep = tl_off != nullptr;
+    const int64_t lbase = keep ? tl_off[e] : 0;
+    int32_t nkept = 0;
     uint32_t my_t = 0;
     for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
       int t = -1;
+      int32_t k = 0, p = 0;
       if (b0 + tl < la) {
-        const int32_t k = pa[b0 + tl];
-        const int32_t p = lower_bound(pb, lb, k);
+        k = pa[b0 + tl];
+        p = lower_bound(pb, lb, k);
         if (p < lb && pb[p] == k) t = ty[k];
       }
       const uint64_t wm = ballot(t >= 0);
       const uint64_t tm = (TSIZE >= TG_WAVE) ? wm : ((wm >> ((lane() / TSIZE) * TSIZE)) & ((1ull << TSIZE) - 1ull));
+      if (keep) {
+        if (t >= 0) {
+          const int64_t pos = lbase + nkept + __popcll(tm & ((1ull << tl) - 1ull));
+          tl_k[pos] = k;
+          tl_e[2 * pos] = s2e[ra + b0 + tl];
+          tl_e[2 * pos + 1] = s2e[rb + p];
+        }
+        nkept += __popcll(tm);
+      }
       if (tm) {
         for (int tt = 0; tt < L; ++tt) {
           const uint64_t b = ballot(t == tt);
@@ -269,6 +287,26 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
       }
     }
     if (tl < L) tau[e * L + tl] = my_t;   // TSIZE >= 16 >= L
+  }
+}
+
+// Sum over the edges of the bound below, added to *total.
+__global__ void __launch_bounds__(256) k_tl_total(int64_t m, const int32_t* __restrict__ ei,
+                                                  const int32_t* __restrict__ ej, const int32_t* __restrict__ deg,
+                                                  uint64_t* __restrict__ total) {
+  uint64_t s = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    s += (uint64_t)min(deg[ei[e]], deg[ej[e]]);
+  s = wave_sum_u64(s);
+  if (lane() == 0 && s) atomicAdd((unsigned long long*)total, (unsigned long long)s);
+}
+
+// Upper bound on the common-neighbour list of each edge: its shorter row's
+// length.
+__global__ void k_tl_bound(int64_t m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
+                           const int32_t* __restrict__ deg, int64_t* __restrict__ bound) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    bound[e] = min(deg[ei[e]], deg[ej[e]]);
   }
 }
 

@@ -138,3 +138,11 @@ def test_type_permutations_keep_type_frequencies():
         assert np.array_equal(np.sort(p), types)
     assert np.array_equal(perms, tg.type_permutations(types, 5, seed=9))
     assert not np.array_equal(perms, tg.type_permutations(types, 5, seed=10))
+
+
+def test_tuning_defaults_and_round_trip():
+    t = tg.Tuning.default()
+    assert t.tlist_budget_mib == 16384 and t.clique_lds_ids == 4096
+    d = t.as_dict()
+    d["tlist_budget_mib"] = 0
+    assert tg.Tuning.from_dict(d).as_dict() == d

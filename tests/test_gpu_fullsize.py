@@ -104,14 +104,16 @@ def test_schedules_agree_at_full_size(big):
 
 def test_launch_shapes_agree_at_full_size(big):
     """Hash tables for the lighter heavy nodes, small node groups and wedge
-    chunks, other team thresholds: the same counts."""
+    chunks, other team thresholds, T_ij by row intersection instead of the
+    kept lists: the same counts."""
     import torch
 
     import paper_1901_10026_amd as tg
     g, rp, ci, ty, glob, rows = big
     t = tg.Tuning.from_dict({"c4_hash_ratio": 4, "c4_footprint_mb": 32, "c4_group_kwedges": 512,
                              "c4_chunk": 256, "light_max_degree": 64, "heavy_min_degree": 1024,
-                             "combine_grid": 1024, "wg_grid": 300, "c4_slot_budget_mb": 0, "c4_slices": 8})
+                             "combine_grid": 1024, "wg_grid": 300, "c4_slot_budget_mb": 0, "c4_slices": 8,
+                             "tlist_budget_mib": 0})
     g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=t)
     torch.cuda.synchronize()
     assert torch.equal(g2.view(torch.int64), glob.view(torch.int64))

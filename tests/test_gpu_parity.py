@@ -95,6 +95,24 @@ def test_per_edge_cycle_counters():
     assert np.array_equal(g2, gg) and np.array_equal(r2, rr)
 
 
+def test_common_neighbour_lists_or_row_intersection():
+    """T_ij read from the lists the typed-triangle pass keeps (the default)
+    or found again by intersecting the two rows (no list budget): the same
+    counts, with and without rows."""
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    t = tg.Tuning.from_dict({"tlist_budget_mib": 0})
+    assert t.tlist_budget_mib == 0 and tg.Tuning.default().tlist_budget_mib > 0
+    g2, r2, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=t)
+    assert np.array_equal(g2, gg) and np.array_equal(r2, rr)
+    g3, _, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=t, per_edge=False)
+    assert np.array_equal(g3, gg)
+    # 1 MiB: above 12 B per edge, below the lists (1.4 MB), so none are kept
+    g4, r4, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=tg.Tuning.from_dict({"tlist_budget_mib": 1}))
+    assert np.array_equal(g4, gg) and np.array_equal(r4, rr)
+
+
 def test_rows_only_counting():
     import torch
 
