@@ -133,11 +133,12 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   const int wv = tid / TG_WAVE;
 
   // ---- T_ij with the sums of tau and D over its members
-  auto add_member = [&](int32_t k, int t, int64_t ea, int64_t eb) {
+  // sa, sb: the CSR slots of k in the rows of a and b
+  auto add_member = [&](int32_t k, int t, int64_t sa, int64_t sb) {
     for (int u = 0; u < L; ++u) {
-      const uint32_t va = A.tau[ea * L + u];
+      const uint32_t va = A.tau_s[sa * L + u];
       if (va) atomicAdd(&Aa[t * L + u], (AccT)va);
-      const uint32_t vb = A.tau[eb * L + u];
+      const uint32_t vb = A.tau_s[sb * L + u];
       if (vb) atomicAdd(&Ab[t * L + u], (AccT)vb);
       const uint32_t vd = A.D[(int64_t)k * L + u];
       if (vd) atomicAdd(&Q[t * L + u], (AccT)vd);
@@ -173,7 +174,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
     int t = 0;
     if (found) {
       t = A.ty[k];
-      add_member(k, t, A.s2e[ra + idx], A.s2e[rb + p]);
+      add_member(k, t, ra + idx, rb + p);
     }
     const uint64_t wmask = ballot(found);
     int32_t before, total;

@@ -51,9 +51,10 @@ struct Work {
   int32_t* es_hi;        // m     slot of each edge in its upper end's row
   int32_t* out_col;      // m
   uint32_t* tau;         // m*L
+  uint32_t* tau_s;       // nnz*L: tau of each edge again at both of its CSR slots (per-edge counting only)
   int64_t* tl_off;       // m+1, or null: start of each edge's common-neighbour list kept by the tau pass
   int32_t* tl_k;         // list entries: member ids ...
-  int32_t* tl_e;         // ... and the ids of the edges (a, k), (b, k), two per member
+  int32_t* tl_e;         // ... and the CSR slots of k in the rows of a and b, two per member
   uint64_t* Pn;          // n*L*L
   uint64_t* Un;          // n*L*L
   uint64_t* C4;          // m*P (32-bit counters when they suffice: see c4_wide)
@@ -75,6 +76,7 @@ struct EdgeArgs {
   const int32_t* out_off;
   const int32_t* out_col;
   const uint32_t* tau;
+  const uint32_t* tau_s;  // tau by CSR slot
   const int64_t* tl_off;  // common-neighbour lists of the edges (from the tau pass), or null
   const int32_t* tl_k;
   const int32_t* tl_e;

@@ -240,8 +240,9 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
                                              const int32_t* __restrict__ ej, const int32_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                              const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau,
-                                             const int64_t* __restrict__ tl_off, int32_t* __restrict__ tl_k,
-                                             int32_t* __restrict__ tl_e, const int32_t* __restrict__ s2e) {
+                                             const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
+                                             uint32_t* __restrict__ tau_s, const int64_t* __restrict__ tl_off,
+                                             int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e) {
   constexpr int TEAMS = 256 / TSIZE;
   const int team = threadIdx.x / TSIZE, tl = threadIdx.x % TSIZE;
   for (int64_t e = (int64_t)blockIdx.x * TEAMS + team; e < m; e += (int64_t)gridDim.x * TEAMS) {
@@ -253,8 +254,8 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
     const int32_t ra = rp[ia ? i : j], rb = rp[ia ? j : i];
     const int32_t* pa = ci + ra;
     const int32_t* pb = ci + rb;
-    // with lists, the edge keeps its common neighbours in id order, with the
-    // ids of the edges from both ends to each
+    // with lists, the edge keeps its common neighbours in id order, with
+    // their CSR slots in the rows of both ends
     const bool keep = tl_off != nullptr;
     const int64_t lbase = keep ? tl_off[e] : 0;
     int32_t nkept = 0;
@@ -273,8 +274,8 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
         if (t >= 0) {
           const int64_t pos = lbase + nkept + __popcll(tm & ((1ull << tl) - 1ull));
           tl_k[pos] = k;
-          tl_e[2 * pos] = s2e[ra + b0 + tl];
-          tl_e[2 * pos + 1] = s2e[rb + p];
+          tl_e[2 * pos] = ra + b0 + tl;
+          tl_e[2 * pos + 1] = rb + p;
         }
         nkept += __popcll(tm);
       }
@@ -286,7 +287,13 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
         }
       }
     }
-    if (tl < L) tau[e * L + tl] = my_t;   // TSIZE >= 16 >= L
+    if (tl < L) {  // TSIZE >= 16 >= L
+      tau[e * L + tl] = my_t;
+      if (tau_s) {
+        tau_s[(int64_t)es_lo[e] * L + tl] = my_t;
+        tau_s[(int64_t)es_hi[e] * L + tl] = my_t;
+      }
+    }
   }
 }
 
@@ -315,8 +322,8 @@ __global__ void k_tl_bound(int64_t m, const int32_t* __restrict__ ei, const int3
 // One wavefront per node i: P[i][t][u] and U[i][t][u].
 __global__ void k_node_tables(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                               const uint8_t* __restrict__ ty, int L, const uint32_t* __restrict__ D,
-                              const uint32_t* __restrict__ tau, const int32_t* __restrict__ s2e,
-                              uint64_t* __restrict__ Pn, uint64_t* __restrict__ Un) {
+                              const uint32_t* __restrict__ tau_s, uint64_t* __restrict__ Pn,
+                              uint64_t* __restrict__ Un) {
   extern __shared__ uint64_t lds_tables[];
   const int wv = threadIdx.x / TG_WAVE;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + wv;
@@ -333,11 +340,10 @@ __global__ void k_node_tables(int64_t n, const int32_t* __restrict__ rp, const i
       const int32_t s = base + b0 + ln;
       const int32_t k = ci[s];
       const int t = ty[k];
-      const int64_t e = s2e[s];
       for (int u = 0; u < L; ++u) {
         const uint32_t dv = D[(int64_t)k * L + u];
         if (dv) atomicAdd((unsigned long long*)&Pa[t * L + u], (unsigned long long)dv);
-        const uint32_t tv = tau[e * L + u];
+        const uint32_t tv = tau_s[(int64_t)s * L + u];
         if (tv) atomicAdd((unsigned long long*)&Ua[t * L + u], (unsigned long long)tv);
       }
     }
