@@ -1430,14 +1430,14 @@ void tg_tuning_default(tg_tuning* t) {
   if (!t) return;
   t->light_max_degree = 64;
   t->heavy_min_degree = 4096;
-  t->mid_log2_cost = 18;
+  t->mid_log2_cost = 16;
   t->heavy_log2_cost = 64;
-  t->combine_grid = 8192;
-  t->wg_grid = 0;
-  t->c4_footprint_mb = 192;
+  t->combine_grid = 16384;
+  t->wg_grid = 4096;
+  t->c4_footprint_mb = 1024;
   t->c4_group_kwedges = 16384;
   t->c4_chunk = 256;
-  t->c4_hash_ratio = 2;
+  t->c4_hash_ratio = 16;
   t->c4_slot_budget_mb = 16384;
   t->c4_slices = 1;
   const int v[9] = {0, 0, 1, 4, 4, 5, 5, 5, 5};
