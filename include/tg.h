@@ -205,6 +205,11 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
  *                   canonical edge in range (or listed), or NULL
  *   opt             host, or NULL for defaults
  * Canonical edge ids number the edges (i, j), i < j, in (i, j) order.
+ * The call reads small plan data back to the host while it runs (the edge
+ * bin sizes, the 4-cycle node groups, the size of the common-neighbour
+ * lists), so the calling thread waits for the preprocessing enqueued on
+ * `stream`; the counting kernels themselves are left running on return
+ * unless check, validate or phase_ms asks for a synchronisation.
  * Errors: TG_ERR_INVALID_ARG for a bad edge range, an edge_ids array that
  * is not strictly increasing inside [0, m), or no output given (nothing
  * written).
