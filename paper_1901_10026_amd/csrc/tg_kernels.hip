@@ -829,9 +829,10 @@ __device__ __forceinline__ void edge_bin(int32_t e, const int32_t* ei, const int
     const int lg = (int)fmin(floor(l2), 63.0);
     if (lg > bp.heavy_log2_cost) c = 2;
     else if (lg > bp.mid_log2_cost && c == 0) c = 1;
-    // buckets of half an octave of cost, so that edges of alike cost share
-    // wavefronts (teams of 16 lanes run four to a wavefront in lockstep)
-    fine = (int)fmin(floor(2.0 * l2), 63.0);
+    // buckets of one octave of cost, so that edges of alike cost share
+    // wavefronts (teams of 16 lanes run four to a wavefront in lockstep);
+    // half octaves and two octaves measured slower
+    fine = (int)fmin(floor(l2), 63.0);
   }
   *cls = c;
   *bucket = bp.mode == 0 ? 0 : 63 - fine;
