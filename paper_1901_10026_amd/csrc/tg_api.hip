@@ -762,9 +762,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       uint32_t* cnt_base = hashed ? hcnt : dense;
       const int64_t rows = grows[g];
       // dense groups are cleared by a fill when that is cheaper than a second
-      // walk over their wedges (a streamed byte costs about 1/256 of a walked
-      // wedge); hashed groups always by a fill of their rows
-      const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 256;
+      // walk over their wedges (a streamed byte costs about 1/128 of a walked
+      // wedge: 64, 128, 256 and 512 were measured); hashed groups always by a
+      // fill of their rows
+      const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 128;
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
       // phase 3 (once): at most a few resident waves of workgroups, so that
       // few LDS key copies are flushed
