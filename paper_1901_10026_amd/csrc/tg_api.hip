@@ -358,6 +358,14 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   return TG_OK;
 }
 
+// List budget of the default tuning: work labels measure the gather as
+// tg_count runs it by default.
+inline int64_t default_list_budget() {
+  tg_tuning t;
+  tg_tuning_default(&t);
+  return (int64_t)std::max(0, t.tlist_budget_mib) << 20;
+}
+
 // Host-side choice of LDS copies for the key sums [k0, k0 + nk) of one kernel
 // within `budget` bytes (no copies: straight global atomics).
 GAcc make_gacc(uint64_t* g, int64_t k0, int64_t nk, int64_t budget) {
@@ -1318,7 +1326,7 @@ tg_status train_impl(tg_cost_model* md, int64_t n, int64_t nnz, const int32_t* r
   keep_pool_cached();
   Scratch S(st);
   Work W;
-  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, nullptr)) return s;
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, nullptr, true, default_list_budget())) return s;
   int32_t* list;
   int64_t ns = 0;
   if (tg_status s = sample_edges(S, st, m, frac, seed, &list, &ns)) return s;
@@ -1776,7 +1784,9 @@ tg_status tg_edge_work(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
   keep_pool_cached();
   Scratch S(stream);
   Work W;
-  if (tg_status s = prepare_graph(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, nullptr)) return s;
+  if (tg_status s = prepare_graph(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, nullptr, true,
+                                  default_list_budget()))
+    return s;
   return measure_work(S, stream, n, nnz, row_ptr, col_idx, node_types, L, W, edges, count, work);
 }
 

@@ -203,10 +203,12 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   }
   tsync<TSIZE>();
 
+  // element visits: building T (three list words per member, or a search
+  // of the longer row per element of the shorter one), then its tau/D sums
   uint64_t my_work = 0;
   if (A.work && tid == 0)
-    my_work = (uint64_t)la * (uint64_t)(1 + (lb > 0 ? 32 - __clz(lb) : 0)) + (uint64_t)nT * 3u * (uint64_t)L +
-              (uint64_t)(P + L);
+    my_work = (A.tl_off ? (uint64_t)nT * 3u : (uint64_t)la * (uint64_t)(1 + (lb > 0 ? 32 - __clz(lb) : 0))) +
+              (uint64_t)nT * 3u * (uint64_t)L + (uint64_t)(P + L);
 
   // ---- typed edges inside T (4-cliques through (i, j)), each found from its
   // lower end's degree-ordered out-list; (member, out-slot) pairs are dealt
