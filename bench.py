@@ -436,7 +436,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (edges would shard by range, "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (edges would shard by range, "
               "with one all-reduce of the global key vector); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
