@@ -1444,7 +1444,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->combine_grid = 16384;
   t->wg_grid = 4096;
   t->c4_footprint_mb = 1024;
-  t->c4_group_kwedges = 16384;
+  t->c4_group_kwedges = 32768;
   t->c4_chunk = 256;
   t->c4_hash_ratio = 16;
   t->c4_slot_budget_mb = 16384;
@@ -1854,7 +1854,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
   axes.push_back({&t.combine_grid, {4096, 8192, 16384}});
   axes.push_back({&t.wg_grid, {0, 1024, 2048, 4096}});
   axes.push_back({&t.c4_footprint_mb, {64, 192, 1024}});
-  axes.push_back({&t.c4_group_kwedges, {1024, 4096, 16384}});
+  axes.push_back({&t.c4_group_kwedges, {4096, 16384, 32768, 65536}});
   axes.push_back({&t.c4_chunk, {256, 1024, 4096}});
   axes.push_back({&t.c4_hash_ratio, {0, 4, 16}});
   axes.push_back({&t.c4_slices, {1, 8}});
