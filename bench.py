@@ -497,6 +497,10 @@ def main():
     cb = combine_bytes(st, g.L, tau_sum, lists)
     comb_ms = phases.get("combine", 0.0)
     achieved = cb / (comb_ms * 1e-3) / 1e9 if comb_ms > 0 else 0.0
+    traffic = stored_traffic(g.name)
+    # the counters' HBM bytes over this run's phase time (the counters come
+    # from a separate profiled run of the same sources)
+    traffic_gbs = traffic / (comb_ms * 1e-3) / 1e9 if traffic and comb_ms > 0 else None
     rec = {
         "metric": METRIC,
         "value": g.m / (ms * 1e-3),
@@ -520,7 +524,9 @@ def main():
                      "kernel": "combine phase: gather kernels k_combine<16>, k_combine<64>, k_combine<256> and "
                                "their k_combine_rows launches, together every edge once",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": stored_traffic(g.name),
+                     "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": traffic,
+                     "traffic_gbs": traffic_gbs,
+                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs else None,
                      "t_ij_from": "kept lists" if lists else "row intersection"},
     }
     if not args.no_compare:
