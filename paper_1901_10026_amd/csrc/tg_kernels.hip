@@ -244,6 +244,11 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
                                              uint32_t* __restrict__ tau_s, const int64_t* __restrict__ tl_off,
                                              int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e) {
   constexpr int TEAMS = 256 / TSIZE;
+  // wavefront teams copy a longer row of at most STAGE ids to LDS and
+  // search it there (16 KB per workgroup; 2048 ids measured slower, the
+  // workgroups per CU halving)
+  constexpr int STAGE = TSIZE == TG_WAVE ? 1024 : 0;
+  __shared__ int32_t stage[STAGE ? TEAMS * STAGE : 1];
   const int team = threadIdx.x / TSIZE, tl = threadIdx.x % TSIZE;
   for (int64_t e = (int64_t)blockIdx.x * TEAMS + team; e < m; e += (int64_t)gridDim.x * TEAMS) {
     const int32_t i = ei[e], j = ej[e];
@@ -254,6 +259,13 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
     const int32_t ra = rp[ia ? i : j], rb = rp[ia ? j : i];
     const int32_t* pa = ci + ra;
     const int32_t* pb = ci + rb;
+    if (STAGE && lb <= STAGE) {  // the team is one wavefront
+      int32_t* sb = stage + team * STAGE;
+      wave_sync();  // the previous edge's searches are done
+      for (int32_t x = tl; x < lb; x += TSIZE) sb[x] = pb[x];
+      wave_sync();
+      pb = sb;
+    }
     // with lists, the edge keeps its common neighbours in id order, with
     // their CSR slots in the rows of both ends
     const bool keep = tl_off != nullptr;
