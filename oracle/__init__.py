@@ -61,6 +61,8 @@ def _load():
     lib.or_count_edges.argtypes = [i64, vp, vp, vp, i32, i64, vp, vp, vp, vp, i32]
     lib.or_count_all.restype = i32
     lib.or_count_all.argtypes = [i64, vp, vp, vp, i32, vp, vp, i32]
+    lib.or_count_batch.restype = i32
+    lib.or_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i32]
     _lib = lib
     return lib
 
@@ -158,3 +160,25 @@ def count_all(row_ptr, col_idx, types, L, per_edge=True, nthreads=1):
     if st != 0:
         raise ValueError(f"or_count_all failed with status {st}")
     return rows, glob
+
+
+def count_batch(node_off, slot_off, row_ptr, col_idx, types, Ls, nthreads=1):
+    """Global counts (Eq. 17) of every graph of a batch (layout as in
+    graphgen.Batch), graph-parallel over nthreads.  Returns (counts, key_off)
+    with graph g's K(L_g) counts at counts[key_off[g]:key_off[g+1]]."""
+    Ls = np.ascontiguousarray(Ls, dtype=np.uint8)
+    G = len(Ls)
+    key_off = np.zeros(G + 1, dtype=np.int64)
+    if G:
+        key_off[1:] = np.cumsum([num_keys(int(x)) for x in Ls])
+    node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+    slot_off = np.ascontiguousarray(slot_off, dtype=np.int64)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    ty = np.ascontiguousarray(types, dtype=np.uint8)
+    out = np.zeros(int(key_off[-1]), dtype=np.uint64)
+    st = _load().or_count_batch(G, node_off.ctypes.data, slot_off.ctypes.data, rp.ctypes.data, ci.ctypes.data,
+                                ty.ctypes.data, Ls.ctypes.data, key_off.ctypes.data, out.ctypes.data, int(nthreads))
+    if st != 0:
+        raise ValueError(f"or_count_batch failed with status {st}")
+    return out, key_off

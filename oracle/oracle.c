@@ -15,20 +15,22 @@
  *     counting problem of Section 4 (Definition "Local Typed Graphlet
  *     Counting").  Orbit roles (g1..g12 of Table 3) are credited as well.
  *
- *  2. or_count_edges / or_count_all: the paper's method, step by step:
- *     Algorithm 1 (mark table Psi, typed sets T_ij^t, S_i^t, S_j^t),
- *     Algorithm 2 (path-based orbits g3, g6, g7), Algorithm 3 (triangle-based
- *     orbits g8, g10, g12), Eqs. 7-10 (g4, g5, g9, g11 derived per type pair),
- *     Eqs. 11-16 (orbits to graphlets) and Eq. 17 (global counts).
+ *  2. or_count_edges / or_count_all: the same definition, written per edge
+ *     (the local counting problem of Section 4): the other two nodes of
+ *     every connected induced 4-node subgraph through edge (i, j) are
+ *     classified by their adjacency to i and j (the sets T_ij, S_i, S_j of
+ *     Section 4.1 and the rest), each configuration's shape is found from
+ *     its explicit 4-node adjacency, and non-adjacent pairs inside the
+ *     neighbourhood are counted as all pairs minus the adjacent ones.  Its
+ *     cost per edge is the sum of the degrees of the neighbours of i and j,
+ *     the bound of Theorem 2.  Global counts follow from Eq. 17.  The
+ *     paper's Eqs. 7-10 (g4, g5, g9, g11 from g6, g7, g10, g12 and the set
+ *     sizes) are not used here; tests check them against these counts.
  *
  * Readings of points the paper leaves open (each is also listed with the
  * design notes of the repository):
  *  - T_ij is the intersection of the neighbourhoods (Sections 4.1 and 4.3).
- *  - S_i excludes j (left-hand form of the S_i definition, Section 4.1), so
- *    Algorithm 1's S_i loop skips j.
- *  - "w_r <= w_k" is the strict order w_r < w_k on node ids (no self loops).
- *  - i and j are skipped wherever they would be classified (Psi never marks
- *    them, so they would otherwise look like members of I).
+ *  - S_i excludes j (left-hand form of the S_i definition, Section 4.1).
  *  - Every S-based orbit covers both the S_i and the S_j side.
  *  - The graph is undirected and simple; only node types are used.
  *  - Keys are (graphlet shape h1..h8, sorted multiset of node types); the
@@ -115,6 +117,32 @@ static inline int64_t pair_index(int t, int u) {
 
 /* ------------------------------------------------------- the definition -- */
 
+/* Shape of a connected 4-node graph with ne edges and node degrees deg[4]
+ * (h = 2..7: 4-path, 4-star, 4-cycle, tailed triangle, chordal cycle,
+ * 4-clique; Section 3.1's 4-node graphlets). */
+static int shape4(int ne, const int* deg) {
+  int maxd = 0;
+  for (int x = 0; x < 4; ++x) if (deg[x] > maxd) maxd = deg[x];
+  if (ne == 3) return (maxd == 3) ? 3 : 2;       /* star : path */
+  if (ne == 4) return (maxd == 3) ? 5 : 4;       /* tailed triangle : cycle */
+  if (ne == 5) return 6;                         /* chordal cycle */
+  return 7;                                      /* clique */
+}
+
+/* Orbit g3..g12 of Table 3 of an edge whose ends have degrees dx, dy inside a
+ * 4-node graphlet of shape h. */
+static int orbit4(int h, int dx, int dy) {
+  const int lo = dx < dy ? dx : dy, hi = dx < dy ? dy : dx;
+  switch (h) {
+    case 2: return (lo == 2 && hi == 2) ? 4 : 3;        /* 4-path: centre : end */
+    case 3: return 5;                                   /* 4-star */
+    case 4: return 6;                                   /* 4-cycle */
+    case 5: return (lo == 1) ? 7 : (hi == 3 ? 9 : 8);   /* tailed triangle: tail, tri-edge at the centre, far */
+    case 6: return (lo == 3) ? 11 : 10;                 /* chordal cycle: chord : rim */
+    default: return 12;                                 /* 4-clique */
+  }
+}
+
 /* Brute force over all 3- and 4-subsets.  adjacency is read from a CSR with
  * both directions stored.  rows: [m][R(L)] graphlet rows in canonical edge
  * order (may be NULL); orbit_rows: [m][2L+10P] (may be NULL); global: [K(L)]
@@ -182,13 +210,7 @@ int or_brute(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const ui
                   if (!((seen >> y) & 1) && ((adj[v[x]] >> v[y]) & 1)) { seen |= 1 << y; grew = 1; }
           }
           if (seen != 15) continue;
-          int maxd = 0;
-          for (int x = 0; x < 4; ++x) if (deg[x] > maxd) maxd = deg[x];
-          int h;
-          if (ne == 3) h = (maxd == 3) ? 3 : 2;       /* star : path */
-          else if (ne == 4) h = (maxd == 3) ? 5 : 4;  /* tailed triangle : cycle */
-          else if (ne == 5) h = 6;                    /* chordal cycle */
-          else h = 7;                                 /* clique */
+          const int h = shape4(ne, deg);
           int ty[4] = {types[a], types[b], types[c], types[d]};
           if (global) global[or_key(L, h, ty)]++;
           for (int x = 0; x < 4; ++x)
@@ -199,68 +221,80 @@ int or_brute(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const ui
               int64_t e = eid[v[x]][v[y]];
               int64_t p = pair_index(types[v[o[0]]], types[v[o[1]]]);
               if (rows) rows[e * R + 2 * L + (int64_t)(h - 2) * P + p]++;
-              if (orbit_rows) {
-                /* orbit of the edge inside its graphlet (Table 3) */
-                int dx = deg[x], dy = deg[y], g;
-                int lo = dx < dy ? dx : dy, hi = dx < dy ? dy : dx;
-                switch (h) {
-                  case 2: g = (lo == 2 && hi == 2) ? 4 : 3; break; /* centre : end */
-                  case 3: g = 5; break;
-                  case 4: g = 6; break;
-                  case 5: g = (lo == 1) ? 7 : (hi == 3 ? 9 : 8); break; /* tail, tri-edge, tri-centre */
-                  case 6: g = (lo == 3) ? 11 : 10; break; /* chord : rim */
-                  default: g = 12; break;
-                }
-                orbit_rows[e * RO + 2 * L + (int64_t)(g - 3) * P + p]++;
-              }
+              if (orbit_rows) orbit_rows[e * RO + 2 * L + (int64_t)(orbit4(h, deg[x], deg[y]) - 3) * P + p]++;
             }
         }
   return OR_OK;
 }
 
-/* ------------------------------------------------------ the paper's method */
+/* ------------------------------------------------ per edge, by definition */
 
-/* Mark values of the table Psi (Table 1): 0 = unmarked (I, or i / j),
- * LAMBDA1 = only in Gamma_i, LAMBDA2 = only in Gamma_j, LAMBDA3 = both. */
-enum { LAMBDA1 = 1, LAMBDA2 = 2, LAMBDA3 = 3 };
-
-/* orbit slot of the explicit counters X[g][t][t'] */
-enum { X_G3 = 0, X_G6, X_G7, X_G8, X_G10, X_G12, X_N };
+/* Per-edge counts straight from the local counting problem of Section 4:
+ * for edge (i, j), every other node k adjacent to i or j has a class
+ *   cls(k) = [k ~ i] + 2 [k ~ j]  (1: only i, the set S_i; 2: only j, S_j;
+ *                                  3: both, T_ij),
+ * and a connected induced 4-node subgraph {i, j, k, l} has either
+ *   (a) k in that neighbourhood U and l outside U, adjacent to k only
+ *       (reached through k), or
+ *   (b) both k and l in U.
+ * Each configuration is written out as a 4-node adjacency (nodes 0, 1 = i, j;
+ * 2, 3 = k, l) and classified with the same shape and orbit functions as the
+ * brute force.  Configurations of (a) and the adjacent pairs of (b) are
+ * enumerated one by one; the non-adjacent pairs of (b) are counted per
+ * (class, type) combination as all pairs minus the adjacent ones.  3-node
+ * subgraphs {i, j, k}: a triangle when cls(k) = 3, else a wedge (3-path). */
 
 typedef struct {
   int L;
-  uint8_t* psi;   /* n marks */
-  int32_t* Tset;  /* members of T_ij */
-  int32_t* Siset; /* members of S_i */
-  int32_t* Sjset; /* members of S_j */
-  uint64_t *T, *Si, *Sj; /* |T^t|, |S_i^t|, |S_j^t| */
-  uint64_t* X;    /* [X_N][L][L] ordered (type of w_k, type of w_r) */
+  uint8_t* cls;   /* n entries: class of each node for the current edge, 0 elsewhere */
+  int32_t* U;     /* members of U */
+  uint64_t* cnt;  /* [4][L]: |class c of type t| */
+  uint64_t* adjc; /* [4][L][4][L]: adjacent ordered pairs inside U by (class, type) */
 } or_work;
 
 static int work_init(or_work* w, int64_t n, int64_t maxdeg, int L) {
   memset(w, 0, sizeof(*w));
   w->L = L;
-  w->psi = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
-  w->Tset = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
-  w->Siset = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
-  w->Sjset = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
-  w->T = (uint64_t*)malloc(sizeof(uint64_t) * 3 * L);
-  w->X = (uint64_t*)malloc(sizeof(uint64_t) * X_N * L * L);
-  if (!w->psi || !w->Tset || !w->Siset || !w->Sjset || !w->T || !w->X) return OR_ERR_NOMEM;
-  w->Si = w->T + L;
-  w->Sj = w->T + 2 * L;
+  w->cls = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+  w->U = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * maxdeg + 1));
+  w->cnt = (uint64_t*)malloc(sizeof(uint64_t) * 4 * L);
+  w->adjc = (uint64_t*)malloc(sizeof(uint64_t) * 16 * L * L);
+  if (!w->cls || !w->U || !w->cnt || !w->adjc) return OR_ERR_NOMEM;
   return OR_OK;
 }
 
 static void work_free(or_work* w) {
-  free(w->psi); free(w->Tset); free(w->Siset); free(w->Sjset); free(w->T); free(w->X);
+  free(w->cls); free(w->U); free(w->cnt); free(w->adjc);
 }
 
-#define XAT(w, g, t, u) ((w)->X[((int64_t)(g) * (w)->L + (t)) * (w)->L + (u)])
-
-/* Symmetrised explicit count for the unordered type pair {t, u}. */
-static uint64_t sym(const or_work* w, int g, int t, int u) {
-  return t == u ? XAT(w, g, t, t) : XAT(w, g, t, u) + XAT(w, g, u, t);
+/* Shape and orbit of edge (0, 1) in the 4-node graph {i, j, k, l} whose
+ * other edges are: k-i iff (ck & 1), k-j iff (ck & 2), l-i iff (cl & 1),
+ * l-j iff (cl & 2), k-l iff kl.  Returns -1 if it is not connected. */
+static int classify_config(int ck, int cl, int kl, int* orbit) {
+  int adj[4][4];
+  memset(adj, 0, sizeof(adj));
+  adj[0][1] = adj[1][0] = 1;
+  adj[2][0] = adj[0][2] = ck & 1;
+  adj[2][1] = adj[1][2] = (ck >> 1) & 1;
+  adj[3][0] = adj[0][3] = cl & 1;
+  adj[3][1] = adj[1][3] = (cl >> 1) & 1;
+  adj[2][3] = adj[3][2] = kl;
+  int deg[4] = {0, 0, 0, 0}, ne = 0;
+  for (int x = 0; x < 4; ++x)
+    for (int y = x + 1; y < 4; ++y)
+      if (adj[x][y]) { ++ne; deg[x]++; deg[y]++; }
+  int seen = 1, grew = 1;
+  while (grew) {
+    grew = 0;
+    for (int x = 0; x < 4; ++x)
+      if ((seen >> x) & 1)
+        for (int y = 0; y < 4; ++y)
+          if (!((seen >> y) & 1) && adj[x][y]) { seen |= 1 << y; grew = 1; }
+  }
+  if (seen != 15) return -1;
+  const int h = shape4(ne, deg);
+  *orbit = orbit4(h, deg[0], deg[1]);
+  return h;
 }
 
 /* Counts one edge (i, j) into a graphlet row (width R) and, optionally, an
@@ -268,107 +302,77 @@ static uint64_t sym(const or_work* w, int g, int t, int u) {
 static void count_edge(or_work* w, const int32_t* row_ptr, const int32_t* col_idx, const uint8_t* phi,
                        int32_t i, int32_t j, uint64_t* row, uint64_t* orow) {
   const int L = w->L;
-  const int64_t P = (int64_t)L * (L + 1) / 2;
-  uint8_t* psi = w->psi;
-  int64_t nT = 0, nSi = 0, nSj = 0;
-  memset(w->T, 0, sizeof(uint64_t) * 3 * L);
-  memset(w->X, 0, sizeof(uint64_t) * X_N * L * L);
-
-  /* Algorithm 1: mark Gamma_i (except j) with lambda1 */
-  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s)
-    if (col_idx[s] != j) psi[col_idx[s]] = LAMBDA1;
-  /* scan Gamma_j: triangle nodes (lambda3) and 3-path nodes centred at j (lambda2) */
-  for (int32_t s = row_ptr[j]; s < row_ptr[j + 1]; ++s) {
-    int32_t k = col_idx[s];
-    if (k == i) continue;
-    if (psi[k] == LAMBDA1) { psi[k] = LAMBDA3; w->Tset[nT++] = k; w->T[phi[k]]++; }
-    else { psi[k] = LAMBDA2; w->Sjset[nSj++] = k; w->Sj[phi[k]]++; }
-  }
-  /* 3-path nodes centred at i: Gamma_i minus T_ij minus {j} */
-  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s) {
-    int32_t k = col_idx[s];
-    if (k == j || psi[k] != LAMBDA1) continue;
-    w->Siset[nSi++] = k; w->Si[phi[k]]++;
-  }
-
-  /* Algorithm 2: path-based orbits from S_i, then S_j */
-  for (int64_t a = 0; a < nSi; ++a) {
-    int32_t wk = w->Siset[a];
-    for (int32_t s = row_ptr[wk]; s < row_ptr[wk + 1]; ++s) {
-      int32_t wr = col_idx[s];
-      if (wr == i || wr == j) continue;
-      if (psi[wr] == 0) XAT(w, X_G3, phi[wk], phi[wr])++;                       /* 4-path end edge */
-      else if (psi[wr] == LAMBDA1 && wr < wk) XAT(w, X_G7, phi[wk], phi[wr])++; /* tailed-tri tail */
-    }
-  }
-  for (int64_t a = 0; a < nSj; ++a) {
-    int32_t wk = w->Sjset[a];
-    for (int32_t s = row_ptr[wk]; s < row_ptr[wk + 1]; ++s) {
-      int32_t wr = col_idx[s];
-      if (wr == i || wr == j) continue;
-      if (psi[wr] == 0) XAT(w, X_G3, phi[wk], phi[wr])++;
-      else if (psi[wr] == LAMBDA2 && wr < wk) XAT(w, X_G7, phi[wk], phi[wr])++;
-      else if (psi[wr] == LAMBDA1) XAT(w, X_G6, phi[wk], phi[wr])++;          /* 4-cycle */
-    }
-  }
-  /* Algorithm 3: triangle-based orbits from T_ij */
-  for (int64_t a = 0; a < nT; ++a) {
-    int32_t wk = w->Tset[a];
-    for (int32_t s = row_ptr[wk]; s < row_ptr[wk + 1]; ++s) {
-      int32_t wr = col_idx[s];
-      if (wr == i || wr == j) continue;
-      if (psi[wr] == LAMBDA3) { if (wr < wk) XAT(w, X_G12, phi[wk], phi[wr])++; } /* 4-clique */
-      else if (psi[wr] == LAMBDA1 || psi[wr] == LAMBDA2) XAT(w, X_G10, phi[wk], phi[wr])++; /* chordal rim */
-      else XAT(w, X_G8, phi[wk], phi[wr])++;                                   /* tailed-tri centre */
-    }
-  }
-
-  /* 3-node graphlets: typed 3-stars |S_i^t| + |S_j^t| and triangles |T^t| */
-  const int64_t R = 2 * L + 6 * P;
+  const int64_t P = (int64_t)L * (L + 1) / 2, R = 2 * L + 6 * P, RO = 2 * L + 10 * P;
+  uint8_t* cls = w->cls;
   memset(row, 0, sizeof(uint64_t) * R);
-  if (orow) memset(orow, 0, sizeof(uint64_t) * (2 * L + 10 * P));
-  for (int t = 0; t < L; ++t) {
-    row[t] = w->Si[t] + w->Sj[t];
-    row[L + t] = w->T[t];
-    if (orow) { orow[t] = row[t]; orow[L + t] = row[L + t]; }
+  if (orow) memset(orow, 0, sizeof(uint64_t) * RO);
+  memset(w->cnt, 0, sizeof(uint64_t) * 4 * L);
+  memset(w->adjc, 0, sizeof(uint64_t) * 16 * L * L);
+#define CNT(c, t) w->cnt[(c) * L + (t)]
+#define ADJC(c1, t1, c2, t2) w->adjc[(((int64_t)(c1) * L + (t1)) * 4 + (c2)) * L + (t2)]
+  /* classes of the neighbours of i and j (i and j themselves excluded) */
+  int64_t nU = 0;
+  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s)
+    if (col_idx[s] != j) cls[col_idx[s]] |= 1;
+  for (int32_t s = row_ptr[j]; s < row_ptr[j + 1]; ++s)
+    if (col_idx[s] != i) cls[col_idx[s]] |= 2;
+  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s)
+    if (col_idx[s] != j) w->U[nU++] = col_idx[s];
+  for (int32_t s = row_ptr[j]; s < row_ptr[j + 1]; ++s)
+    if (col_idx[s] != i && cls[col_idx[s]] == 2) w->U[nU++] = col_idx[s];
+  /* 3-node subgraphs */
+  for (int64_t a = 0; a < nU; ++a) {
+    const int32_t k = w->U[a];
+    const int c = cls[k];
+    CNT(c, phi[k])++;
+    const int h = c == 3 ? 1 : 0;
+    row[(int64_t)h * L + phi[k]]++;
+    if (orow) orow[(int64_t)h * L + phi[k]]++;
   }
-  /* type-pair loop: Eqs. 7-10 for t <= u, then Eqs. 11-16 */
-  for (int u = 0; u < L; ++u)
-    for (int t = 0; t <= u; ++t) {
-      const uint64_t g3 = sym(w, X_G3, t, u), g6 = sym(w, X_G6, t, u), g7 = sym(w, X_G7, t, u);
-      const uint64_t g8 = sym(w, X_G8, t, u), g10 = sym(w, X_G10, t, u), g12 = sym(w, X_G12, t, u);
-      const uint64_t Si_t = w->Si[t], Si_u = w->Si[u], Sj_t = w->Sj[t], Sj_u = w->Sj[u];
-      const uint64_t T_t = w->T[t], T_u = w->T[u];
-      uint64_t g4, g5, g9, g11;
-      if (t == u) {
-        g4 = Si_t * Sj_t - g6;                                            /* Eq. 7 */
-        g5 = choose2(Si_t) + choose2(Sj_t) - g7;                         /* Eq. 8 */
-        g9 = T_t * (Si_t + Sj_t) - g10;                                   /* Eq. 9 */
-        g11 = choose2(T_t) - g12;                                         /* Eq. 10 */
+  /* (a) l outside U and not i or j, adjacent to k in U; (b) adjacent pairs
+   * inside U, each once (from its smaller id) */
+  int orb;
+  for (int64_t a = 0; a < nU; ++a) {
+    const int32_t k = w->U[a];
+    const int ck = cls[k];
+    for (int32_t s = row_ptr[k]; s < row_ptr[k + 1]; ++s) {
+      const int32_t l = col_idx[s];
+      if (l == i || l == j) continue;
+      const int cl = cls[l];
+      if (cl == 0) {
+        const int h = classify_config(ck, 0, 1, &orb);
+        const int64_t p = pair_index(phi[k], phi[l]);
+        row[2 * L + (int64_t)(h - 2) * P + p]++;
+        if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p]++;
       } else {
-        g4 = Si_t * Sj_u + Si_u * Sj_t - g6;
-        g5 = Si_t * Si_u + Sj_t * Sj_u - g7;
-        g9 = T_t * (Si_u + Sj_u) + T_u * (Si_t + Sj_t) - g10;
-        g11 = T_t * T_u - g12;
-      }
-      const int64_t p = (int64_t)u * (u + 1) / 2 + t;
-      uint64_t* H = row + 2 * L;
-      H[0 * P + p] = g3 + g4;        /* Eq. 11: 4-path */
-      H[1 * P + p] = g5;             /* Eq. 12: 4-star */
-      H[2 * P + p] = g6;             /* Eq. 13: 4-cycle */
-      H[3 * P + p] = g7 + g8 + g9;   /* Eq. 14: tailed triangle */
-      H[4 * P + p] = g10 + g11;      /* Eq. 15: chordal cycle */
-      H[5 * P + p] = g12;            /* Eq. 16: 4-clique */
-      if (orow) {
-        uint64_t* O = orow + 2 * L;
-        const uint64_t g[10] = {g3, g4, g5, g6, g7, g8, g9, g10, g11, g12};
-        for (int q = 0; q < 10; ++q) O[q * P + p] = g[q];
+        ADJC(ck, phi[k], cl, phi[l])++;  /* every adjacent pair twice, once per order */
+        if (l < k) continue;
+        const int h = classify_config(ck, cl, 1, &orb);
+        const int64_t p = pair_index(phi[k], phi[l]);
+        row[2 * L + (int64_t)(h - 2) * P + p]++;
+        if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p]++;
       }
     }
-
-  /* reset Psi on Gamma_i and Gamma_j */
-  for (int32_t s = row_ptr[i]; s < row_ptr[i + 1]; ++s) psi[col_idx[s]] = 0;
-  for (int32_t s = row_ptr[j]; s < row_ptr[j + 1]; ++s) psi[col_idx[s]] = 0;
+  }
+  /* (b) non-adjacent pairs of U, per unordered (class, type) combination */
+  for (int c1 = 1; c1 <= 3; ++c1)
+    for (int t1 = 0; t1 < L; ++t1)
+      for (int c2 = c1; c2 <= 3; ++c2)
+        for (int t2 = (c2 == c1 ? t1 : 0); t2 < L; ++t2) {
+          const int same = c1 == c2 && t1 == t2;
+          const uint64_t all = same ? choose2(CNT(c1, t1)) : CNT(c1, t1) * CNT(c2, t2);
+          const uint64_t adjacent = same ? ADJC(c1, t1, c2, t2) / 2 : ADJC(c1, t1, c2, t2);
+          const uint64_t v = all - adjacent;
+          if (!v) continue;
+          const int h = classify_config(c1, c2, 0, &orb);
+          const int64_t p = pair_index(t1, t2);
+          row[2 * L + (int64_t)(h - 2) * P + p] += v;
+          if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p] += v;
+        }
+#undef CNT
+#undef ADJC
+  /* reset the classes */
+  for (int64_t a = 0; a < nU; ++a) cls[w->U[a]] = 0;
 }
 
 static int64_t max_degree(int64_t n, const int32_t* row_ptr) {
@@ -456,4 +460,25 @@ int or_count_all(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, cons
   free(ei); free(ej);
   if (!rows) free(r);
   return st;
+}
+
+/* Global counts of many independent graphs (the batch workload): graph g has
+ * nodes [node_off[g], node_off[g+1]), its row pointer (n_g + 1 entries from
+ * 0) at row_ptr + node_off[g] + g, local column ids at col_idx + slot_off[g],
+ * L_g = Ls[g] types, and its K(L_g) counts go to global + key_off[g].  Each
+ * graph is counted by or_count_all; graphs are spread over nthreads. */
+int or_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr,
+                   const int32_t* col_idx, const uint8_t* types, const uint8_t* Ls, const int64_t* key_off,
+                   uint64_t* global, int nthreads) {
+  if (G < 0) return OR_ERR_ARG;
+  int status = OR_OK;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(min : status)
+  for (int64_t g = 0; g < G; ++g) {
+    const int64_t n0 = node_off[g];
+    const int st = or_count_all(node_off[g + 1] - n0, row_ptr + n0 + g, col_idx + slot_off[g], types + n0, Ls[g],
+                                NULL, global + key_off[g], 1);
+    if (st != OR_OK) status = st;
+  }
+  return status;
 }

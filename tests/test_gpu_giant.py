@@ -1,9 +1,11 @@
-"""Skewed giant graph (Chung-Lu, 20M nodes, about 274M edges, maximum degree
-about 294k, L=8 Zipf types).  Its per-edge rows do not fit in memory and a
-full count needs about 1.1e14 4-clique probes, so the call counts rows only
-for a stratified edge sample (global_counts=False): the 4-cycle pass covers
-the whole graph, the per-edge step only the sample, and every sampled row
-must equal the oracle's."""
+"""Skewed giant graph (Chung-Lu, 20M nodes, L=8 Zipf types).  Its per-edge
+rows do not fit in memory, so the call counts rows only for an edge sample
+(global_counts=False): the 4-cycle pass covers the whole graph, the
+per-edge step only the sample, and every sampled row must equal the
+oracle's.  The sample is stratified by degree product and also holds the
+heaviest edges of the graph (the largest d_i * d_j): hub-hub edges with the
+longest common-neighbour sets, which take the workgroup teams and the
+global-scratch path of T_ij."""
 import numpy as np
 import pytest
 
@@ -14,10 +16,11 @@ from _gpu import note, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def sample_edges(d, s, ei, ej, per_decile=6, heaviest=3, budget=4e8, seed=11):
+def sample_edges(d, s, ei, ej, per_decile=6, heaviest=3, budget=4e8, top=20, top_budget=1.2e9, seed=11):
     """Stratified by degree-product decile, uniform within each decile among
-    edges whose oracle cost (s_i + s_j) fits the budget, plus the heaviest
-    such edges."""
+    edges whose oracle cost (s_i + s_j element visits) fits the budget, plus
+    the heaviest such edges, plus the `top` edges of largest d_i * d_j whose
+    cost fits top_budget."""
     cost = d[ei] * d[ej]
     ocost = s[ei] + s[ej]
     order = np.argsort(cost, kind="stable")
@@ -28,6 +31,8 @@ def sample_edges(d, s, ei, ej, per_decile=6, heaviest=3, budget=4e8, seed=11):
         picks.extend(rng.choice(ok, size=min(per_decile, len(ok)), replace=False))
     ok = order[ocost[order] <= budget]
     picks.extend(ok[-heaviest:])
+    ok = order[ocost[order] <= top_budget]
+    picks.extend(ok[-top:])
     return np.unique(np.array(picks, dtype=np.int64))
 
 
@@ -43,7 +48,9 @@ def test_giant_sampled_rows():
     s = cs[g.row_ptr[1:]] - cs[g.row_ptr[:-1]]  # neighbour degree sums
     del cs
     ids = sample_edges(d, s, ei, ej)
-    note(f"sampled {len(ids)} edges")
+    prod = d[ei[ids]] * d[ej[ids]]
+    note(f"sampled {len(ids)} edges, largest d_i*d_j {prod.max():.3e} (graph: {(d[ei] * d[ej]).max():.3e}), "
+         f"largest oracle cost {(s[ei[ids]] + s[ej[ids]]).max():.3e}")
     rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
     dev_ids = torch.from_numpy(ids).to(rp.device)
     ph = {}
