@@ -28,25 +28,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Sources whose change invalidates a stored HBM-traffic measurement of the
-# combine phase (the kernel itself, its device helpers and its launch code).
-_COMBINE_SOURCES = ("paper_1901_10026_amd/csrc/tg_combine.hip", "paper_1901_10026_amd/csrc/tg_device.h",
-                    "paper_1901_10026_amd/csrc/tg_internal.h", "paper_1901_10026_amd/csrc/tg_api.hip")
-_TRAFFIC_FILE = "profiles/combine_cl-1m_hbm_traffic.txt"
+# Sources whose change invalidates a stored traffic measurement: the device
+# code of tg_count's kernels and their helpers (the host launch code in
+# tg_api.hip is not hashed).
+_KERNEL_SOURCES = ("paper_1901_10026_amd/csrc/tg_combine.hip", "paper_1901_10026_amd/csrc/tg_clique.hip",
+                   "paper_1901_10026_amd/csrc/tg_kernels.hip", "paper_1901_10026_amd/csrc/tg_device.h",
+                   "paper_1901_10026_amd/csrc/tg_internal.h")
+_TRAFFIC_FILE = "profiles/tg_count_cl-1m_l2_traffic.txt"
+# kernels of each timed phase of tg_count (rocprofv3 kernel-name prefixes)
+PHASE_KERNELS = {
+    "cycles": ("k_c4_hash", "k_c4_group", "k_c4_slot_wedges", "k_c4_fold", "k_fill_u32", "k_fill_u64"),
+    "cliques": ("k_k4_low", "k_k4_tier", "k_k4_zero", "k_max_tsum_all"),
+    "combine": ("k_combine",),
+}
 
 
-def combine_source_hash():
+def kernel_source_hash():
     h = hashlib.sha256()
-    for rel in _COMBINE_SOURCES:
+    for rel in _KERNEL_SOURCES:
         with open(os.path.join(_ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 def stored_traffic(workload):
-    """HBM bytes per combine phase from the committed rocprofv3 counter
-    summary, or None when it is absent, is for another workload, or was
-    taken on different kernel sources."""
+    """L2-egress bytes per call of each phase (FETCH_SIZE and WRITE_SIZE
+    counters, scaled by a plain copy) from the committed rocprofv3 summary,
+    as {phase: bytes}; None when it is absent, is for another workload, or
+    was taken on different kernel sources."""
     path = os.path.join(_ROOT, _TRAFFIC_FILE)
     if workload != "cl-1m" or not os.path.exists(path):
         return None
@@ -56,12 +65,88 @@ def stored_traffic(workload):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != combine_source_hash():
+    if vals.get("source_sha256") != kernel_source_hash():
         return None
-    try:
-        return int(float(vals["traffic_bytes_per_phase"]))
-    except (KeyError, ValueError):
-        return None
+    out = {}
+    for ph in PHASE_KERNELS:
+        try:
+            out[ph] = int(float(vals[f"traffic_bytes.{ph}"]))
+        except (KeyError, ValueError):
+            pass
+    return out or None
+
+
+def _kernel_name(full):
+    """'void tg::k_x<1, int>(args...)' -> 'k_x<1, int>'."""
+    name = full[5:] if full.startswith("void ") else full
+    name = name.replace("tg::", "").replace("(anonymous namespace)::", "")
+    return name.split("(", 1)[0].strip()
+
+
+def _read_counter_csv(path, counter):
+    """Per kernel-name (template arguments cut) sums of one rocprofv3 counter
+    (KiB) and dispatch counts, from its counter_collection.csv."""
+    import csv
+    sums, calls = {}, {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = _kernel_name(row["Kernel_Name"])
+            sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+            calls[name] = calls.get(name, 0) + 1
+    return sums, calls
+
+
+def summarize_trace(stats_csv, calls_per_run):
+    """Prints a per-kernel summary of a rocprofv3 --kernel-trace --stats run
+    (its kernel_stats.csv): calls, total and per-tg_count-call milliseconds,
+    and the phase totals."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    print(f"{'kernel':60s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} {'ms_per_call':>11s} {'pct':>6s}")
+    per_phase = {ph: 0.0 for ph in PHASE_KERNELS}
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = _kernel_name(r["Name"])
+        t = float(r["TotalDurationNs"]) / 1e6
+        print(f"{name[:60]:60s} {int(r['Calls']):6d} {t:10.3f} {float(r['AverageNs']) / 1e3:10.1f} "
+              f"{t / calls_per_run:11.3f} {100 * t * 1e6 / total:6.2f}")
+        for ph, prefixes in PHASE_KERNELS.items():
+            if any(name.startswith(pf) for pf in prefixes):
+                per_phase[ph] += t / calls_per_run
+    for ph, t in per_phase.items():
+        print(f"# phase {ph} (kernels {', '.join(PHASE_KERNELS[ph])}): {t:.3f} ms per tg_count call")
+
+
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, calls_per_run):
+    """Prints the L2-egress summary from four rocprofv3 --pmc runs (FETCH_SIZE
+    and WRITE_SIZE of tg_count, then of a plain device copy of copy_bytes
+    bytes done 3 times), per kernel and per phase, with the source hash."""
+    f, fc = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    w, _ = _read_counter_csv(write_csv, "WRITE_SIZE")
+    cf, cfc = _read_counter_csv(copy_fetch_csv, "FETCH_SIZE")
+    cw, cwc = _read_counter_csv(copy_write_csv, "WRITE_SIZE")
+    ck = max(cf, key=lambda k: cf[k])
+    fetch_scale = copy_bytes / (cf[ck] / cfc[ck] * 1024.0)
+    write_scale = copy_bytes / (cw[ck] / cwc[ck] * 1024.0)
+    print(f"# copy kernel {ck}: FETCH_SIZE {cf[ck] / cfc[ck]:.1f} KiB and WRITE_SIZE {cw[ck] / cwc[ck]:.1f} KiB "
+          f"per copy of {copy_bytes} bytes")
+    print(f"# scale factors (bytes moved / counter bytes): fetch {fetch_scale:.4f}, write {write_scale:.4f}")
+    print("# L2 egress (requests leaving L2, MALL hits included), per call of tg_count")
+    print(f"{'kernel':60s} {'calls':>6s} {'FETCH_KiB':>14s} {'WRITE_KiB':>14s} {'scaled_GB':>10s}")
+    per_phase = {ph: 0.0 for ph in PHASE_KERNELS}
+    for k in sorted(f, key=lambda k: -(f[k] * fetch_scale + w.get(k, 0.0) * write_scale)):
+        fk, wk = f[k] / calls_per_run, w.get(k, 0.0) / calls_per_run
+        b = (fk * fetch_scale + wk * write_scale) * 1024.0
+        print(f"{k[:60]:60s} {fc[k] / calls_per_run:6.0f} {fk:14.1f} {wk:14.1f} {b / 1e9:10.2f}")
+        for ph, prefixes in PHASE_KERNELS.items():
+            if any(k.startswith(pf) for pf in prefixes):
+                per_phase[ph] += b
+    for ph, b in per_phase.items():
+        print(f"# phase {ph}: kernels {', '.join(PHASE_KERNELS[ph])}")
+        print(f"traffic_bytes.{ph}: {int(b)}")
+    print(f"source_sha256: {kernel_source_hash()}")
 
 
 def copy_calibration(mib):
@@ -78,7 +163,9 @@ def copy_calibration(mib):
 
 
 def graph_stats(g):
-    """Per-edge structural quantities used for algorithmic byte counts."""
+    """Per-edge structural quantities used for algorithmic byte counts:
+    canonical edges, degrees, and out-degrees d+ in the degree order (u
+    before v when (d_u, u) < (d_v, v))."""
     rp = g.row_ptr.astype(np.int64)
     ci = g.col_idx.astype(np.int64)
     n = g.n
@@ -86,7 +173,28 @@ def graph_stats(g):
     src = np.repeat(np.arange(n, dtype=np.int64), d)
     up = ci > src
     ei, ej = src[up], ci[up]
-    return dict(n=n, m=len(ei), nnz=len(ci), deg=d, ei=ei, ej=ej)
+    rank = np.empty(n, dtype=np.int64)
+    rank[np.lexsort((np.arange(n), d))] = np.arange(n)
+    higher = rank[ci] > rank[src]
+    dplus = np.bincount(src[higher], minlength=n).astype(np.int64)
+    return dict(n=n, m=len(ei), nnz=len(ci), deg=d, ei=ei, ej=ej, src=src, col=ci, rank=rank, dplus=dplus,
+                higher=higher)
+
+
+def cycle_wedges(st):
+    """Wedges x-u-w of the 4-cycle pass, x the highest-ranked node: scanned
+    (every w of u's row, for every higher neighbour x of u: sum of
+    d_u d+_u) and oriented (w below x as well)."""
+    d, dplus = st["deg"], st["dplus"]
+    scanned = int((d * dplus).sum())
+    # slot (u, x) with x above u: the w of u's row below x are the slots of
+    # u's row that sort before x by rank
+    src, rank = st["src"], st["rank"]
+    order = np.lexsort((rank[st["col"]], src))
+    rp = np.concatenate([[0], np.cumsum(d)])
+    pos = np.arange(len(order), dtype=np.int64) - rp[src[order]]
+    oriented = int(pos[st["higher"][order]].sum())
+    return scanned, oriented
 
 
 # bytes of the common-neighbour lists the library keeps (12 B per entry of
@@ -99,17 +207,21 @@ def keeps_lists(st):
     return 12 * int(np.minimum(d[st["ei"]], d[st["ej"]]).sum()) <= TLIST_BUDGET
 
 
-def combine_bytes(st, L, tau_sum, lists):
-    """Algorithmic bytes of the per-edge combine kernel (one launch = every
-    edge): edge endpoints (8 B), row offsets of both ends (16 B), typed
-    degree and node tables of both endpoints (2 x (4L + 16 L^2) B), the
-    edge's own typed triangle counts (4L B) and typed 4-cycle counts (8P B),
-    per member of T_ij its type (1 B), the typed triangle counts of (i,k) and
-    (j,k) and the typed degree of k (12L B), and the written row (8R B).
-    T_ij itself is either found by intersecting both CSR rows (4 B per id of
-    either row) or, with the lists the tau pass keeps, read from that list
-    (its offset, 8 B per edge, and 12 B per member: the id and two edge
-    ids)."""
+def combine_bytes(st, L, tau_sum, lists, k4_width=0, probes=0):
+    """Algorithmic bytes of the per-edge combine phase (gather and row
+    kernels, every edge once): edge endpoints (8 B), row offsets of both ends
+    (16 B), typed degree and node tables of both endpoints (2 x (4L + 16 L^2)
+    B), the edge's own typed triangle counts (4L B) and typed 4-cycle counts
+    (8P B), per member of T_ij its type (1 B), the typed triangle counts of
+    (i,k) and (j,k) and the typed degree of k (12L B), and the written row
+    (8R B).  T_ij itself is either found by intersecting both CSR rows (4 B
+    per id of either row) or, with the lists the tau pass keeps, read from
+    that list (its offset, 8 B per edge, and 12 B per member: the id and two
+    slots).  The typed 4-cliques of the edge are either read from the clique
+    pass's counters (k4_width B for each of the P type pairs) or, with
+    k4_width = 0, found by out-list probes: the out-list offsets of every
+    member (8 B) and 4 B per probe (`probes` = sum over edges of the
+    out-degrees of T_ij's members)."""
     P = L * (L + 1) // 2
     R = 2 * L + 6 * P
     d = st["deg"]
@@ -118,7 +230,55 @@ def combine_bytes(st, L, tau_sum, lists):
         tset = 8 * st["m"] + 12 * tau_sum
     else:
         tset = 4 * (d[st["ei"]] + d[st["ej"]]).sum()
-    return int(st["m"] * per_edge_fixed + tset + tau_sum * (1 + 12 * L))
+    if k4_width:
+        cliques = st["m"] * P * k4_width
+    else:
+        cliques = 8 * tau_sum + 4 * probes
+    return int(st["m"] * per_edge_fixed + tset + tau_sum * (1 + 12 * L) + cliques)
+
+
+def clique_probes(st, tri):
+    """Out-list probes of the per-edge 4-clique search: the out-degrees of
+    T_ij's members summed over the edges, i.e. sum over nodes k of d+_k
+    times the number of triangles at k (tri)."""
+    return int((st["dplus"] * np.asarray(tri, dtype=np.int64)).sum())
+
+
+def cycles_bytes(st, L, scanned, oriented, c4_width):
+    """Algorithmic bytes of the typed 4-cycle phase: per scanned wedge the
+    far end's id and degree in the counting and in the crediting walk (16 B),
+    per oriented wedge one 16-bit count update (4 B), a read of the far end's
+    count row (16-bit per type, 2L B) and its type (1 B), and per edge the
+    fold of its two slot rows into one (3 P counters of c4_width B).  The
+    credit atomics, whose number depends on the cycles found, are left out:
+    a lower bound."""
+    P = L * (L + 1) // 2
+    return int(16 * scanned + oriented * (4 + 2 * L + 1) + 3 * st["m"] * P * c4_width)
+
+
+def clique_bytes(st, L, k4_width):
+    """Algorithmic bytes of the clique pass: per node its out-list ids and
+    types (5 B each), per member b of a node's out-list b's out-list offsets
+    (8 B) and out-list, read in both passes (8 d+_b B): sum over b of
+    d-_b (8 + 8 d+_b) with d-_b = d_b - d+_b lower neighbours, and the
+    per-edge counters cleared and flushed (2 P k4_width B per edge).  The
+    credits of the edges inside each out-list (data-dependent) are left out:
+    a lower bound."""
+    P = L * (L + 1) // 2
+    d, dplus = st["deg"], st["dplus"]
+    dminus = d - dplus
+    return int(5 * st["m"] + (dminus * (8 + 8 * dplus)).sum() + 2 * st["m"] * P * k4_width)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(g, seconds, threads):
@@ -137,7 +297,7 @@ def cpu_baseline(g, seconds, threads):
                            st["ej"][idx].astype(np.int32), nthreads=threads)
         t_used += time.perf_counter() - t0
         done += batch
-    return dict(value=done / t_used, unit="edges/s", cores=threads, kind="oracle",
+    return dict(value=done / t_used, unit="edges/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample=f"{done} edges drawn uniformly (seed 12345) from the same graph, counted by the oracle's "
                        f"per-edge method (all rows) in {t_used:.1f} s on {threads} host threads")
 
@@ -411,6 +571,62 @@ def batch_leg(tg, dev, steps=3):
             "graphs_per_s": b.G / (ms * 1e-3), "edges_per_s": m / (ms * 1e-3), "tuning": tuning.as_dict()}
 
 
+def phase_rooflines(tg, g, out_e, tau_sum, phases):
+    """Roofline objects of the three largest phases of tg_count (4-cycles,
+    4-cliques, per-edge combine): algorithmic bytes (the byte models above,
+    with the launch decisions the library takes on this graph) over the
+    phase time measured with HIP events on the call's stream, against the
+    HBM peak; `traffic` is the committed counter summary's L2-egress bytes
+    for the phase's kernels when it matches the kernel sources."""
+    import torch
+    L = g.L
+    P = L * (L + 1) // 2
+    st = graph_stats(g)
+    lists = keeps_lists(st)
+    tuning = tg.Tuning.default()
+    pass_used = bool(tuning.clique_pass) and int(st["dplus"].max()) <= 4096
+    # |T_e| per edge from the rows, for the widest clique counter and the
+    # probe count of the out-list path
+    tsz = out_e.view(torch.int64)[:, L:2 * L].sum(1)
+    max_t = int(tsz.max().item()) if tsz.numel() else 0
+    k4_width = (8 if max_t * max(max_t - 1, 0) // 2 >= (1 << 32) else 4) if pass_used else 0
+    probes = 0
+    if not pass_used:
+        tri2 = torch.zeros(g.n, dtype=torch.int64, device=out_e.device)
+        tri2.index_add_(0, torch.from_numpy(st["ei"]).to(out_e.device), tsz)
+        tri2.index_add_(0, torch.from_numpy(st["ej"]).to(out_e.device), tsz)
+        probes = clique_probes(st, (tri2 // 2).cpu().numpy())
+    dmax = int(st["deg"].max())
+    c4_width = 8 if (dmax - 1) * (dmax - 1) >= (1 << 32) else 4
+    scanned, oriented = cycle_wedges(st)
+    models = {
+        "cycles": (cycles_bytes(st, L, scanned, oriented, c4_width),
+                   "typed 4-cycle phase: k_c4_hash tiers, k_c4_group count/credit/clear, k_c4_fold",
+                   f"{scanned} scanned and {oriented} oriented wedges; credits left out"),
+        "cliques": (clique_bytes(st, L, k4_width) if pass_used else 0,
+                    "typed 4-clique pass: k_k4_low over every node with 3 or more higher-ranked neighbours",
+                    "out-lists of every node's out-list members read twice; credits left out"),
+        "combine": (combine_bytes(st, L, tau_sum, lists, k4_width=k4_width, probes=probes),
+                    "per-edge combine: gather kernels k_combine<16|64|256> and their k_combine_rows launches",
+                    f"T_ij from {'kept lists' if lists else 'row intersection'}, 4-cliques from "
+                    f"{'the clique pass' if pass_used else f'{probes} out-list probes'}"),
+    }
+    traffic = stored_traffic(g.name) or {}
+    out = {}
+    for ph, (b, kern, note) in models.items():
+        ms = phases.get(ph, 0.0)
+        if ms <= 0 or b <= 0:
+            continue
+        achieved = b / (ms * 1e-3) / 1e9
+        tr = traffic.get(ph)
+        out[ph] = {"bound": "hbm", "kernel": kern, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": b, "phase_ms": ms, "model": note,
+                   "traffic": tr, "traffic_source": "L2 egress: FETCH_SIZE and WRITE_SIZE scaled by a plain copy "
+                                                    "(MALL hits included), from " + _TRAFFIC_FILE,
+                   "traffic_gbs": tr / (ms * 1e-3) / 1e9 if tr else None}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,7 +650,21 @@ def main():
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                             "COPY_WRITE_CSV"),
+                    help="only print the L2-egress summary of rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the "
+                         "benchmark step and of --copy-calibration (counter_collection.csv files) and exit")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="only print the per-kernel summary of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy (--summarize-counters)")
+    ap.add_argument("--calls", type=int, default=1, help="tg_count calls in the profiled run (--summarize-counters)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.calls)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, copy_bytes=args.copy_mib << 20, calls_per_run=args.calls)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (edges would shard by range, "
               "with one all-reduce of the global key vector); use --gpus 1", file=sys.stderr)
@@ -492,15 +722,8 @@ def main():
     # |T_ij| summed over edges = 3 x number of triangles
     tri_keys = [k for k in range(K) if tg.key_decode(g.L, k)[0] == 1]
     tau_sum = 3 * int(sum(int(glob[k]) for k in tri_keys))
-    st = graph_stats(g)
-    lists = keeps_lists(st)
-    cb = combine_bytes(st, g.L, tau_sum, lists)
-    comb_ms = phases.get("combine", 0.0)
-    achieved = cb / (comb_ms * 1e-3) / 1e9 if comb_ms > 0 else 0.0
-    traffic = stored_traffic(g.name)
-    # the counters' HBM bytes over this run's phase time (the counters come
-    # from a separate profiled run of the same sources)
-    traffic_gbs = traffic / (comb_ms * 1e-3) / 1e9 if traffic and comb_ms > 0 else None
+    rooflines = phase_rooflines(tg, g, out_e, tau_sum, phases)
+    main_phase = max(rooflines, key=lambda ph: rooflines[ph]["phase_ms"])
     rec = {
         "metric": METRIC,
         "value": g.m / (ms * 1e-3),
@@ -520,14 +743,8 @@ def main():
         "typed_graphlets_per_s": total_graphlets / (ms * 1e-3),
         "typed_graphlets": total_graphlets,
         "phase_ms": phases,
-        "roofline": {"bound": "hbm",
-                     "kernel": "combine phase: gather kernels k_combine<16>, k_combine<64>, k_combine<256> and "
-                               "their k_combine_rows launches, together every edge once",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": cb, "phase_ms": comb_ms, "traffic": traffic,
-                     "traffic_gbs": traffic_gbs,
-                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs else None,
-                     "t_ij_from": "kept lists" if lists else "row intersection"},
+        "roofline": rooflines[main_phase],
+        "roofline_phases": {ph: r for ph, r in rooflines.items() if ph != main_phase},
     }
     if not args.no_compare:
         rec["schedules"] = compare_schedules(tg, g, rp, ci, ty, out_g, out_e)

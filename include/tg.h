@@ -37,9 +37,9 @@
  * The caller owns every input and output buffer.  Scratch memory belongs to
  * the library: a per-device workspace that one call at a time holds and that
  * later calls reuse (grown to the last call's need, kept until the process
- * ends; a call on another stream first waits for the previous holder's
- * work), with any excess and concurrent calls served stream-ordered on the
- * caller's stream from the default pool.
+ * ends or tg_release_scratch frees it; a call on another stream first waits
+ * for the previous holder's work), with any excess and concurrent calls
+ * served stream-ordered on the caller's stream from the default pool.
  *
  * Streams and errors: all device work is enqueued on `stream`.  Argument
  * errors are reported before anything is enqueued.  Device-detected problems
@@ -120,6 +120,14 @@ typedef struct {
                                  list (12 B per entry, sized by min(d_i, d_j)) for the per-edge gather
                                  when all lists fit in this many MiB of scratch; else (and at 0) the
                                  gather intersects the two rows again */
+  int32_t clique_pass;        /* tg_count: 1 = count every edge's typed 4-cliques in one pass over the
+                                 graph, each clique once from its lowest node in degree order, when the
+                                 per-edge step covers at least an eighth of the edges and no node has
+                                 more than 4096 higher-ranked neighbours; 0 = the per-edge gather finds
+                                 them from out-lists instead */
+  int32_t clique_pass_grid;   /* tg_count: workgroups of the clique pass for nodes with more than 256
+                                 higher-ranked neighbours, each with a global scratch slice
+                                 (0 = two per compute unit) */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */
@@ -154,6 +162,7 @@ enum {
   TG_PHASE_TABLES,       /* per-node sums of typed degrees and triangle counts */
   TG_PHASE_SCHEDULE,     /* edge classes and cost buckets, node tiers */
   TG_PHASE_CYCLES,       /* typed 4-cycles through every edge */
+  TG_PHASE_CLIQUES,      /* typed 4-cliques, each from its lowest node (when that pass runs) */
   TG_PHASE_COMBINE,      /* per-edge orbits, graphlets, rows and global sums */
   TG_PHASE_FINALIZE,     /* division of global sums by shape edge counts */
   TG_NUM_PHASES
@@ -345,8 +354,16 @@ tg_status tg_rows_sparse(int64_t E, int L, const uint64_t* rows, const int32_t* 
  *   global_counts   device, uint64[key_off[G]]
  * The call reads the graph sizes back to the host (one synchronisation),
  * buckets graphs by size, and replays a cached HIP graph of one persistent
- * launch per bucket.  Same conventions and errors as tg_count; only `check`
- * and `tuning` of opt are used. */
+ * launch per bucket.  Only `check`, `validate` and `tuning` of opt are used.
+ * Errors: TG_ERR_INVALID_ARG for a graph with more than 512 nodes or a
+ * key_off that does not match tg_num_keys(L_g), TG_ERR_UNSUPPORTED_L for
+ * L_g outside [1, 8] (these are always checked, with one synchronisation);
+ * with validate set, a device check of every graph (row pointers, column
+ * ids below n_g, no self loops, strictly increasing rows, both directions
+ * stored, types below L_g; a second synchronisation) reports
+ * TG_ERR_INVALID_GRAPH or TG_ERR_TYPE_RANGE.  Without validate these
+ * properties are assumed, and inputs that break them give unspecified
+ * counts. */
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
                          const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
                          const int64_t* key_off, uint64_t* global_counts, const tg_options* opt,
@@ -419,6 +436,14 @@ tg_status tg_autotune_batch(int64_t G, const int64_t* node_off, const int64_t* s
                             const int32_t* col_idx_local, const uint8_t* node_types, const uint8_t* L_per_graph,
                             const int64_t* key_off, uint64_t* global_counts, tg_tuning* tuning, float* best_ms,
                             hipStream_t stream);
+
+/* Frees the scratch workspace that the counting calls keep on the current
+ * device (after the work of its last holder has finished) and returns the
+ * memory cached by the device's default stream-ordered pool to the system;
+ * later calls allocate again.  Synchronises the device.  Errors:
+ * TG_ERR_INVALID_ARG while a call on another thread holds the workspace,
+ * TG_ERR_HIP. */
+tg_status tg_release_scratch(void);
 
 /* Human-readable name of a status code (static string). */
 const char* tg_status_string(tg_status s);

@@ -63,10 +63,12 @@ class Tuning(ctypes.Structure):
                 ("c4_hash_ratio", ctypes.c_int32), ("c4_slot_budget_mb", ctypes.c_int32), ("c4_slices", ctypes.c_int32),
                 ("batch_variant", ctypes.c_int32 * 9), ("clique_team_max", ctypes.c_int32),
                 ("clique_wave_max", ctypes.c_int32), ("clique_lds_ids", ctypes.c_int32),
-                ("tlist_budget_mib", ctypes.c_int32)]
+                ("tlist_budget_mib", ctypes.c_int32), ("clique_pass", ctypes.c_int32),
+                ("clique_pass_grid", ctypes.c_int32)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
                "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
-               "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids", "tlist_budget_mib")
+               "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids", "tlist_budget_mib",
+               "clique_pass", "clique_pass_grid")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
@@ -99,7 +101,7 @@ class _Options(ctypes.Structure):
                 ("edge_orbits", ctypes.c_void_p)]
 
 
-PHASES = ("prep", "tau", "tables", "schedule", "cycles", "combine", "finalize")
+PHASES = ("prep", "tau", "tables", "schedule", "cycles", "cliques", "combine", "finalize")
 
 
 def lib():
@@ -109,6 +111,10 @@ def lib():
     if not os.path.exists(_LIB):
         raise RuntimeError(f"libtg.so is not built ({_LIB}); run paper_1901_10026_amd.build() or "
                            "__graft_entry__.build() first")
+    # torch (which provides the device memory and streams) is loaded before
+    # the library, so that its HIP runtime comes up first whatever the
+    # caller touches first
+    import torch  # noqa: F401
     L = ctypes.CDLL(_LIB)
     vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
     L.tg_options_default.restype = None
@@ -173,6 +179,8 @@ def lib():
     L.tg_cost_model_save.argtypes = [vp, ctypes.c_char_p]
     L.tg_cost_model_load.restype = i32
     L.tg_cost_model_load.argtypes = [vp, ctypes.c_char_p]
+    L.tg_release_scratch.restype = i32
+    L.tg_release_scratch.argtypes = []
     L.tg_status_string.restype = ctypes.c_char_p
     L.tg_status_string.argtypes = [i32]
     L.tg_last_error.restype = ctypes.c_char_p
@@ -488,8 +496,14 @@ def key_offsets(L_per_graph):
     return off
 
 
+def release_scratch():
+    """Frees the library's scratch workspace on the current device and trims
+    the device's default memory pool (tg_release_scratch)."""
+    _check(lib().tg_release_scratch())
+
+
 def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_off, *, out=None, check=True,
-                tuning=None):
+                tuning=None, validate=False):
     """Global typed-graphlet counts of many small graphs with tg_count_batch.
 
     All arguments are device tensors (int64 offsets, int32 CSR with local ids,
@@ -504,6 +518,7 @@ def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_of
     opt = _Options()
     lib().tg_options_default(ctypes.byref(opt))
     opt.check = 1 if check else 0
+    opt.validate = 1 if validate else 0
     opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
     st = lib().tg_count_batch(G, node_off.data_ptr(), slot_off.data_ptr(), row_ptr.data_ptr(), col_idx.data_ptr(),
                               types.data_ptr(), L_per_graph.data_ptr(), key_off.data_ptr(), g.data_ptr(),

@@ -141,6 +141,33 @@ struct Scratch {
     return hipSuccess;
   }
 };
+// Frees the current device's workspace once its last holder's work is done
+// and trims the default pool.  Fails while a call holds the workspace.
+tg_status release_scratch() {
+  Workspace* w = device_workspace();
+  if (!w) return fail(TG_ERR_HIP, "no current device");
+  bool expect = false;
+  if (!w->busy.compare_exchange_strong(expect, true))
+    return fail(TG_ERR_INVALID_ARG, "a call on another thread holds the scratch workspace");
+  hipError_t e = hipSuccess;
+  if (w->done) e = hipEventSynchronize(w->done);
+  if (e == hipSuccess && w->base) e = hipFree(w->base);
+  if (e == hipSuccess) {
+    w->base = nullptr;
+    w->cap = 0;
+    w->want = 0;
+    int dev = 0;
+    hipMemPool_t pool;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipDeviceGetDefaultMemPool(&pool, dev);
+    if (e == hipSuccess) e = hipMemPoolTrimTo(pool, 0);
+  }
+  w->busy.store(false);
+  if (e != hipSuccess) return fail(TG_ERR_HIP, std::string("releasing scratch: ") + hipGetErrorString(e));
+  return TG_OK;
+}
+
 void keep_pool_cached() {
   static bool done[64] = {};
   int dev = 0;
@@ -217,18 +244,18 @@ tg_status scan(Scratch& S, hipStream_t st, int64_t n, const T* in, T* out) {
 
 // Gather and row kernels over list[0, count) of one edge class, in batches
 // whose accumulators fit ea (ea_budget bytes).
-template <int TSIZE, class AccT>
+template <int TSIZE, class AccT, bool PROBE>
 tg_status combine_class(hipStream_t st, const EdgeArgs& A, int64_t count, const int32_t* list, unsigned grid,
                         int32_t* t_over, int64_t t_cap, int64_t K, void* ea, int64_t ea_budget,
                         unsigned rows_grid) {
   const int64_t per = 4ll * A.L * A.L * (int64_t)sizeof(AccT);
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ea_budget / per));
-  const size_t lds = combine_lds_bytes<TSIZE, AccT>(A.L);
+  const size_t lds = combine_lds_bytes<TSIZE, AccT, PROBE>(A.L);
   const size_t rlds = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     const int64_t c = std::min(chunk, count - c0);
     const unsigned g = std::min(grid, grid_for(c, 256 / TSIZE));
-    k_combine<TSIZE, AccT><<<g, 256, lds, st>>>(A, c, list + c0, reinterpret_cast<AccT*>(ea), t_over, t_cap);
+    k_combine<TSIZE, AccT, PROBE><<<g, 256, lds, st>>>(A, c, list + c0, reinterpret_cast<AccT*>(ea), t_over, t_cap);
     TG_LAUNCHED("k_combine");
     k_combine_rows<AccT><<<grid_for(c, 16, rows_grid), 256, rlds, st>>>(A, c, list + c0,
                                                                          reinterpret_cast<const AccT*>(ea), (int)K);
@@ -272,7 +299,7 @@ tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, con
 // pass also keeps them.
 tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                         const uint8_t* ty, int L, Work& W, PhaseTimer* timer, bool tables = true,
-                        int64_t list_budget = 0) {
+                        int64_t list_budget = 0, bool out_eids = false) {
   const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
   TG_HIP(S.get(&W.deg, n));
   TG_HIP(S.get(&W.D, n * L));
@@ -288,6 +315,8 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   TG_HIP(S.get(&W.es_lo, m));
   TG_HIP(S.get(&W.es_hi, m));
   TG_HIP(S.get(&W.out_col, m));
+  W.out_eid = nullptr;
+  if (out_eids) TG_HIP(S.get(&W.out_eid, m));
   TG_HIP(S.get(&W.tau, m * L));
   W.Pn = W.Un = W.C4 = nullptr;
   W.tau_s = nullptr;
@@ -311,7 +340,7 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
   if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
   k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
-                                               W.s2e, W.es_lo, W.es_hi, W.out_col);
+                                               W.s2e, W.es_lo, W.es_hi, W.out_col, W.out_eid);
   TG_LAUNCHED("k_fill_edges");
 
   // ---- typed triangles per edge, node tables
@@ -374,6 +403,138 @@ GAcc make_gacc(uint64_t* g, int64_t k0, int64_t nk, int64_t budget) {
 }
 
 size_t gacc_bytes(const GAcc& a) { return (size_t)a.copies * a.nk * sizeof(uint64_t); }
+
+// The gather and row kernels over the three edge classes (16-lane teams,
+// wavefronts, workgroups).  PROBE: the gather finds each edge's 4-cliques
+// from out-lists (else the clique pass has counted them).
+template <bool PROBE>
+tg_status combine_classes(Scratch& S, hipStream_t st, const EdgeArgs& A, const Work& W, const int64_t* class_begin,
+                          const int64_t* class_count, int64_t K, void* ea, int64_t ea_budget, const tg_tuning& tune,
+                          int cus, int64_t max_t_heavy) {
+  const int L = A.L;
+  // workgroups that fit the device at once for a launch of `kernel` with
+  // `lds` bytes (the default caps)
+  auto resident = [&](const void* kernel, size_t lds) -> int64_t {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess) per_cu = 1;
+    return (int64_t)std::max(1, cus) * std::max(1, per_cu);
+  };
+  const unsigned rows_grid = tune.combine_grid > 0 ? (unsigned)tune.combine_grid : 8192u;
+  if (class_count[0] > 0) {
+    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
+                                              : resident((const void*)k_combine<16, uint32_t, PROBE>,
+                                                         combine_lds_bytes<16, uint32_t, PROBE>(L));
+    if (tg_status s2 = combine_class<16, uint32_t, PROBE>(st, A, class_count[0], W.elist + class_begin[0],
+                                                   grid_for(class_count[0], 16, cap), nullptr, 0, K, ea, ea_budget,
+                                                   rows_grid))
+      return s2;
+  }
+  if (class_count[1] > 0) {
+    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
+                                              : resident((const void*)k_combine<64, uint32_t, PROBE>,
+                                                         combine_lds_bytes<64, uint32_t, PROBE>(L));
+    if (tg_status s2 = combine_class<64, uint32_t, PROBE>(st, A, class_count[1], W.elist + class_begin[1],
+                                                   grid_for(class_count[1], 4, cap), nullptr, 0, K, ea, ea_budget,
+                                                   rows_grid))
+      return s2;
+  }
+  if (class_count[2] > 0) {
+    // default: one workgroup per resident slot (CUs x workgroups per CU at
+    // this launch's LDS), so that no second partial wave of workgroups runs
+    const int64_t cap = tune.wg_grid > 0 ? tune.wg_grid
+                                         : resident((const void*)k_combine<256, uint64_t, PROBE>,
+                                                    combine_lds_bytes<256, uint64_t, PROBE>(L));
+    const unsigned grid = grid_for(class_count[2], 1, cap);
+    int32_t* t_over = nullptr;
+    int64_t t_cap = 0;
+    if (PROBE && max_t_heavy > TG_T_WG_CAP) {
+      t_cap = max_t_heavy;
+      TG_HIP(S.get(&t_over, over_scratch_ints(grid, t_cap)));
+    }
+    if (tg_status s2 = combine_class<256, uint64_t, PROBE>(st, A, class_count[2], W.elist + class_begin[2], grid, t_over,
+                                                    t_cap, K, ea, ea_budget, rows_grid))
+      return s2;
+  }
+
+  return TG_OK;
+}
+
+// Node plan of the clique pass (tg_clique.hip): tier sizes, the largest
+// out-degree, and the nodes listed by tier (tiers 3-6 in decreasing
+// out-degree order).  ok = false when a node has more out-neighbours than
+// the pass supports (nothing listed then).
+struct K4Plan {
+  bool ok = false;
+  int64_t count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t start[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t dmax = 0;
+  int32_t* list = nullptr;
+};
+
+tg_status k4_plan(Scratch& S, hipStream_t st, int64_t n, const int32_t* out_off, K4Plan& plan) {
+  int32_t* c;
+  TG_HIP(S.get(&c, 32));
+  k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(c), 32, 0u);
+  TG_LAUNCHED("k_fill_u32");
+  k_k4_tier_count<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, out_off, c, c + 8);
+  TG_LAUNCHED("k_k4_tier_count");
+  int32_t h[9];
+  TG_HIP(hipMemcpyAsync(h, c, sizeof(h), hipMemcpyDeviceToHost, st));
+  TG_HIP(hipStreamSynchronize(st));
+  plan.dmax = h[8];
+  if (h[7] > 0) return TG_OK;  // out-degree above TG_K4_LDS_IDS
+  int64_t acc = 0;
+  int32_t cur[8];
+  for (int t = 0; t < 8; ++t) {
+    plan.count[t] = t == 0 ? 0 : h[t];
+    plan.start[t] = acc;
+    cur[t] = (int32_t)acc;
+    acc += plan.count[t];
+  }
+  TG_HIP(S.get(&plan.list, std::max<int64_t>(1, acc)));
+  TG_HIP(hipMemcpyAsync(c + 16, cur, sizeof(cur), hipMemcpyHostToDevice, st));
+  k_k4_tier_scatter<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, out_off, c + 16, plan.list);
+  TG_LAUNCHED("k_k4_tier_scatter");
+  plan.ok = true;
+  return TG_OK;
+}
+
+// Launches the clique pass over the planned nodes.  Each tier takes a
+// wavefront team per node with LDS rows when they fit in 64 KiB per
+// workgroup, else a workgroup team with LDS rows, else a workgroup team
+// with rows in global scratch.
+template <bool GLOB>
+tg_status k4_launch(Scratch& S, hipStream_t st, const K4Args& K, const K4Plan& plan, int cus, int grid_big,
+                    GAcc ga) {
+  const int L = K.L;
+  const size_t gb = GLOB ? gacc_bytes(ga) : 0;
+  auto run = [&](int64_t cnt, const int32_t* list, int dcap) -> tg_status {
+    if (cnt <= 0) return TG_OK;
+    const size_t l64 = 4 * (size_t)k4_team_lds<64, false>(dcap, L);
+    const size_t l256 = (size_t)k4_team_lds<256, false>(dcap, L);
+    if (dcap <= 64 && l64 + gb <= (64u << 10)) {
+      k_k4_low<64, false, GLOB><<<grid_for(cnt, 4, 8192), 256, l64 + gb, st>>>(K, cnt, list, dcap, nullptr, 0, ga);
+      TG_LAUNCHED("k_k4_low<64>");
+    } else if (l256 + gb <= (64u << 10)) {
+      k_k4_low<256, false, GLOB><<<grid_for(cnt, 1, 4096), 256, l256 + gb, st>>>(K, cnt, list, dcap, nullptr, 0, ga);
+      TG_LAUNCHED("k_k4_low<256>");
+    } else {
+      const int64_t grid = std::min<int64_t>(cnt, grid_big > 0 ? grid_big : 2 * (int64_t)cus);
+      const int64_t stride = k4_gscr_bytes(dcap, L);
+      char* g;
+      TG_HIP(S.get(&g, grid * stride));
+      k_k4_low<256, true, GLOB><<<(unsigned)grid, 256, (size_t)k4_team_lds<256, true>(dcap, L) + gb, st>>>(
+          K, cnt, list, dcap, g, stride, ga);
+      TG_LAUNCHED("k_k4_low<256, global rows>");
+    }
+    return TG_OK;
+  };
+  if (tg_status s = run(plan.count[1], plan.list + plan.start[1], 64)) return s;
+  if (tg_status s = run(plan.count[2], plan.list + plan.start[2], 256)) return s;
+  const int64_t big = plan.count[3] + plan.count[4] + plan.count[5] + plan.count[6];
+  if (tg_status s = run(big, plan.list + plan.start[3], std::max(257, plan.dmax))) return s;
+  return TG_OK;
+}
 
 // once: global counts only, every instance counted a fixed number of times
 // (tg_count_global); otherwise per-edge counting with Eq. 17 (tg_count).
@@ -459,7 +620,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (opt.tuning) tune = *opt.tuning;
   Work W;
   const int64_t list_budget = once ? 0 : (int64_t)std::max(0, tune.tlist_budget_mib) << 20;
-  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once, list_budget)) return s;
+  // 4-cliques of every edge in one pass over the graph (when the per-edge
+  // step covers enough of the edges for a whole-graph pass to pay)
+  const bool want_k4_pass = !once && tune.clique_pass != 0 && sel_count * 8 >= m;
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once, list_budget, want_k4_pass))
+    return s;
 
   // ---- schedule: edge classes and cost buckets, node tiers
   timer.mark(TG_PHASE_SCHEDULE);
@@ -837,26 +1002,80 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     TG_LAUNCHED("k_c4_fold");
   }
 
+  int dev = 0, cus = 0;
+  TG_HIP(hipGetDevice(&dev));
+  TG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+
+  // ---- typed 4-cliques of every edge, each clique once from its lowest node
+  timer.mark(TG_PHASE_CLIQUES);
+  uint32_t* K4n = nullptr;
+  uint64_t* K4w = nullptr;
+  bool k4_glob_done = false;
+  if (once && tune.clique_pass != 0) {
+    // global counts: every clique adds one to its key, per type vector
+    K4Plan plan;
+    if (tg_status s2 = k4_plan(S, st, n, W.out_off, plan)) return s2;
+    for (int64_t b = 0; plan.ok && b < nty; ++b) {
+      const K4Args K{W.deg, ty + b * n, L, W.out_off, W.out_col, nullptr, m, nullptr, nullptr};
+      const GAcc ga_k4 = make_gacc(global_counts + b * nkeys(L), 2 * C3k + 5 * C4k, C4k, 16 << 10);
+      if (tg_status s2 = k4_launch<true>(S, st, K, plan, cus, tune.clique_pass_grid, ga_k4)) return s2;
+    }
+    k4_glob_done = plan.ok;
+  }
+  if (W.out_eid) {
+    K4Plan plan;
+    if (tg_status s2 = k4_plan(S, st, n, W.out_off, plan)) return s2;
+    if (plan.ok) {
+      // a count on edge e is at most C(|T_e|, 2)
+      uint32_t* d_mt;
+      TG_HIP(S.get(&d_mt, 1));
+      k_fill_u32<<<1, 64, 0, st>>>(d_mt, 1, 0u);
+      k_max_tsum_all<<<grid_for(m, 256, 4096), 256, 0, st>>>(m, W.tau, L, d_mt);
+      TG_LAUNCHED("k_max_tsum_all");
+      uint32_t mt = 0;
+      TG_HIP(hipMemcpyAsync(&mt, d_mt, sizeof(mt), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+      const bool k4_wide = (uint64_t)mt * (mt > 0 ? mt - 1 : 0) / 2 >= (1ull << 32);
+      K4Args K{W.deg, ty, L, W.out_off, W.out_col, W.out_eid, m, nullptr, nullptr};
+      if (k4_wide) {
+        TG_HIP(S.get(&K4w, m * P));
+        k_fill_u64<<<grid_for(m * P, 256, 16384), 256, 0, st>>>(K4w, m * P, 0);
+        K.K4w = K4w;
+      } else {
+        TG_HIP(S.get(&K4n, m * P));
+        k_fill_u32<<<grid_for(m * P, 256, 16384), 256, 0, st>>>(K4n, m * P, 0u);
+        K.K4n = K4n;
+      }
+      TG_LAUNCHED("k_fill");
+      if (tg_status s2 = k4_launch<false>(S, st, K, plan, cus, tune.clique_pass_grid, GAcc{})) return s2;
+    }
+  }
+
   if (once) {
     // ---- the other shapes, each instance a fixed number of times
     timer.mark(TG_PHASE_COMBINE);
     // 4-cliques: edges in three classes by intersection length (|T_ij| does
     // not depend on the types, so neither do the classes)
+    // (none when the clique pass has added every 4-clique already)
     int32_t* kc = cnt + 280;
-    TG_HIP(hipMemsetAsync(kc, 0, 8 * sizeof(int32_t), st));
+    int32_t hk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t kcur[4] = {0, 0, 0, 0};
     const int team_max = std::min(64, std::max(0, tune.clique_team_max));
-    const int2 lim = make_int2(team_max, std::min(1024, std::max(team_max, tune.clique_wave_max)));
     const int tcap = std::min(K4Cap<256>::value, std::max(0, tune.clique_lds_ids));
-    k_k4_class_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim, kc);
-    TG_LAUNCHED("k_k4_class_count");
-    int32_t hk[8];
-    TG_HIP(hipMemcpyAsync(hk, kc, sizeof(hk), hipMemcpyDeviceToHost, st));
-    TG_HIP(hipStreamSynchronize(st));
-    const int32_t kcur[4] = {0, hk[0], hk[0] + hk[1], 0};
-    TG_HIP(hipMemcpyAsync(kc + 4, kcur, 3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    k_k4_class_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim,
-                                                               kc + 4, W.elist);
-    TG_LAUNCHED("k_k4_class_scatter");
+    if (!k4_glob_done) {
+      TG_HIP(hipMemsetAsync(kc, 0, 8 * sizeof(int32_t), st));
+      const int2 lim = make_int2(team_max, std::min(1024, std::max(team_max, tune.clique_wave_max)));
+      k_k4_class_count<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim, kc);
+      TG_LAUNCHED("k_k4_class_count");
+      TG_HIP(hipMemcpyAsync(hk, kc, sizeof(hk), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+      kcur[1] = hk[0];
+      kcur[2] = hk[0] + hk[1];
+      TG_HIP(hipMemcpyAsync(kc + 4, kcur, 3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      k_k4_class_scatter<<<grid_for(m, 256, 8192), 256, 0, st>>>(m, W.ei, W.ej, W.deg, W.out_off, W.tau, L, lim,
+                                                                 kc + 4, W.elist);
+      TG_LAUNCHED("k_k4_class_scatter");
+    }
     // lane-spread copies of each edge's L x L clique cells: about 2 KiB per team
     const int mcop = (int)std::max<int64_t>(1, std::min<int64_t>(8, 512 / (LL)));
     const unsigned grid_wg = grid_for(hk[2], 1, 2048);
@@ -937,6 +1156,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.gacc_in_lds = (global_counts && K <= TG_GACC_MAX_KEYS) ? 1 : 0;
   A.work = nullptr;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
+  A.K4n = K4n;
+  A.K4w = K4w;
+  A.m = m;
+  const bool probe = !K4n && !K4w;
   // gathered accumulators of one batch of edges (reused by every class and
   // batch: all launches are ordered on st)
   const int64_t ea_budget = 4ll << 30;
@@ -948,51 +1171,12 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     need = std::min(need, ea_budget);
     if (need > 0) TG_HIP(S.get(reinterpret_cast<uint64_t**>(&ea), (need + 7) / 8));
   }
-  // workgroups that fit the device at once for a launch of `kernel` with
-  // `lds` bytes (the default caps)
-  int dev = 0, cus = 0;
-  TG_HIP(hipGetDevice(&dev));
-  TG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  auto resident = [&](const void* kernel, size_t lds) -> int64_t {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess) per_cu = 1;
-    return (int64_t)std::max(1, cus) * std::max(1, per_cu);
-  };
-  const unsigned rows_grid = tune.combine_grid > 0 ? (unsigned)tune.combine_grid : 8192u;
-  if (class_count[0] > 0) {
-    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
-                                              : resident((const void*)k_combine<16, uint32_t>,
-                                                         combine_lds_bytes<16, uint32_t>(L));
-    if (tg_status s2 = combine_class<16, uint32_t>(st, A, class_count[0], W.elist + class_begin[0],
-                                                   grid_for(class_count[0], 16, cap), nullptr, 0, K, ea, ea_budget,
-                                                   rows_grid))
-      return s2;
-  }
-  if (class_count[1] > 0) {
-    const int64_t cap = tune.combine_grid > 0 ? tune.combine_grid
-                                              : resident((const void*)k_combine<64, uint32_t>,
-                                                         combine_lds_bytes<64, uint32_t>(L));
-    if (tg_status s2 = combine_class<64, uint32_t>(st, A, class_count[1], W.elist + class_begin[1],
-                                                   grid_for(class_count[1], 4, cap), nullptr, 0, K, ea, ea_budget,
-                                                   rows_grid))
-      return s2;
-  }
-  if (class_count[2] > 0) {
-    // default: one workgroup per resident slot (CUs x workgroups per CU at
-    // this launch's LDS), so that no second partial wave of workgroups runs
-    const int64_t cap = tune.wg_grid > 0 ? tune.wg_grid
-                                         : resident((const void*)k_combine<256, uint64_t>,
-                                                    combine_lds_bytes<256, uint64_t>(L));
-    const unsigned grid = grid_for(class_count[2], 1, cap);
-    int32_t* t_over = nullptr;
-    int64_t t_cap = 0;
-    if (max_t_heavy > TG_T_WG_CAP) {
-      t_cap = max_t_heavy;
-      TG_HIP(S.get(&t_over, over_scratch_ints(grid, t_cap)));
-    }
-    if (tg_status s2 = combine_class<256, uint64_t>(st, A, class_count[2], W.elist + class_begin[2], grid, t_over,
-                                                    t_cap, K, ea, ea_budget, rows_grid))
-      return s2;
+  {
+    tg_status s2 = probe ? combine_classes<true>(S, st, A, W, class_begin, class_count, K, ea, ea_budget, tune, cus,
+                                                 max_t_heavy)
+                         : combine_classes<false>(S, st, A, W, class_begin, class_count, K, ea, ea_budget, tune, cus,
+                                                  max_t_heavy);
+    if (s2 != TG_OK) return s2;
   }
 
   // ---- Eq. 17 and outputs
@@ -1108,6 +1292,16 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
   if (h[80] & 1) return fail(TG_ERR_INVALID_ARG, "a graph has more than 512 nodes or a negative size");
   if (h[80] & 2) return fail(TG_ERR_UNSUPPORTED_L, "a graph's L is outside [1, 8]");
   if (h[80] & 4) return fail(TG_ERR_INVALID_ARG, "key_off does not match tg_num_keys(L_g)");
+  if (opt.validate) {
+    k_batch_validate<<<grid_for(G, 4, 4096), 256, 0, st>>>(G, node_off, slot_off, rp, ci, ty, Lg, ctr + 80);
+    TG_LAUNCHED("k_batch_validate");
+    TG_HIP(hipMemcpyAsync(&h[80], ctr + 80, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    if (h[80] & 16)
+      return fail(TG_ERR_INVALID_GRAPH, "a graph's CSR is invalid (row pointers, column range, self loop, unsorted "
+                                        "or duplicate row, or an edge stored in one direction only)");
+    if (h[80] & 8) return fail(TG_ERR_TYPE_RANGE, "a node type is >= its graph's L");
+  }
   // list order: size class W from 8 down to 0, largest first inside a class
   int32_t cur[128];
   memset(cur, 0, sizeof(cur));
@@ -1278,6 +1472,9 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.gacc_in_lds = 0;
   A.work = work_by_edge;
   A.thash_ok = n < (1ll << 27) ? 1 : 0;
+  A.K4n = nullptr;
+  A.K4w = nullptr;
+  A.m = m;
   const unsigned grid = grid_for(count, 1, 1024);
   int32_t* t_over = nullptr;
   int64_t t_cap = 0;
@@ -1285,8 +1482,29 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
     t_cap = h_tmax;
     TG_HIP(S.get(&t_over, over_scratch_ints(grid, t_cap)));
   }
-  const size_t lds = combine_lds_bytes<256, uint64_t>(L);
-  k_combine<256, uint64_t><<<grid, 256, lds, st>>>(A, count, list, nullptr, t_over, t_cap);
+  // the gather as tg_count runs it by default: without the 4-clique probes
+  // when the clique pass covers the graph
+  tg_tuning dflt;
+  tg_tuning_default(&dflt);
+  bool probe = dflt.clique_pass == 0;
+  if (!probe) {
+    int32_t* c;
+    TG_HIP(S.get(&c, 16));
+    k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(c), 16, 0u);
+    k_k4_tier_count<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, W.out_off, c, c + 8);
+    TG_LAUNCHED("k_k4_tier_count");
+    int32_t h[8];
+    TG_HIP(hipMemcpyAsync(h, c, sizeof(h), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    probe = h[7] > 0;
+  }
+  if (probe) {
+    k_combine<256, uint64_t, true><<<grid, 256, combine_lds_bytes<256, uint64_t, true>(L), st>>>(
+        A, count, list, nullptr, t_over, t_cap);
+  } else {
+    k_combine<256, uint64_t, false><<<grid, 256, combine_lds_bytes<256, uint64_t, false>(L), st>>>(
+        A, count, list, nullptr, nullptr, 0);
+  }
   TG_LAUNCHED("k_combine<256>");
   return TG_OK;
 }
@@ -1455,6 +1673,8 @@ void tg_tuning_default(tg_tuning* t) {
   t->clique_wave_max = 1024;
   t->clique_lds_ids = 4096;
   t->tlist_budget_mib = 16384;
+  t->clique_pass = 1;
+  t->clique_pass_grid = 0;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
@@ -1926,6 +2146,8 @@ tg_status tg_autotune_batch(int64_t G, const int64_t* node_off, const int64_t* s
   if (best_ms) *best_ms = best;
   return TG_OK;
 }
+
+tg_status tg_release_scratch(void) { return release_scratch(); }
 
 const char* tg_status_string(tg_status s) {
   switch (s) {

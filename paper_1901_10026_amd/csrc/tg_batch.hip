@@ -340,6 +340,56 @@ __global__ void k_batch_subcount(int64_t G, const int64_t* __restrict__ node_off
   }
 }
 
+// Optional input check (tg_options.validate), one wavefront per graph: row
+// pointers from 0 to the graph's slot count and non-decreasing, types below
+// L_g, column ids in [0, n_g) without self loops, rows strictly increasing,
+// and every slot (u, v) mirrored by (v, u).  bad: bit 8 = a type >= L_g,
+// bit 16 = a CSR violation.  Slots are only examined once the graph's row
+// pointers have passed, so that every read stays inside the graph.
+__global__ void __launch_bounds__(256) k_batch_validate(int64_t G, const int64_t* __restrict__ node_off,
+                                                        const int64_t* __restrict__ slot_off,
+                                                        const int32_t* __restrict__ rp_all,
+                                                        const int32_t* __restrict__ ci_all,
+                                                        const uint8_t* __restrict__ ty_all,
+                                                        const uint8_t* __restrict__ Lg, int32_t* __restrict__ bad) {
+  const int ln = lane();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / TG_WAVE;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / TG_WAVE;
+  for (int64_t g = wid; g < G; g += nw) {
+    const int64_t n0 = node_off[g];
+    const int64_t n = node_off[g + 1] - n0;
+    const int64_t nnz = slot_off[g + 1] - slot_off[g];
+    if (n < 0 || n > 512 || nnz < 0) continue;  // reported by k_batch_classify
+    const int32_t* rp = rp_all + n0 + g;
+    const int32_t* ci = ci_all + slot_off[g];
+    const int L = Lg[g];
+    bool rbad = false, tbad = false;
+    for (int64_t v = ln; v <= n; v += TG_WAVE) {
+      const int32_t r = rp[v];
+      if (r < 0 || r > nnz || (v == 0 && r != 0) || (v == n && r != nnz) || (v > 0 && rp[v - 1] > r)) rbad = true;
+      if (v < n && ty_all[n0 + v] >= L) tbad = true;
+    }
+    if (ballot(tbad) && ln == 0) atomicOr(bad, 8);
+    if (ballot(rbad)) {
+      if (ln == 0) atomicOr(bad, 16);
+      continue;
+    }
+    bool sbad = false;
+    for (int64_t q = ln; q < nnz; q += TG_WAVE) {
+      int32_t lo = 0, hi = (int32_t)n;  // row u: the largest u with rp[u] <= q
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= q) lo = mid; else hi = mid;
+      }
+      const int32_t u = lo, v = ci[q];
+      if (v < 0 || v >= n || v == u || (q > rp[u] && ci[q - 1] >= v)) { sbad = true; continue; }
+      const int32_t p = lower_bound(ci + rp[v], rp[v + 1] - rp[v], u);
+      if (p >= rp[v + 1] - rp[v] || ci[rp[v] + p] != u) sbad = true;
+    }
+    if (ballot(sbad) && ln == 0) atomicOr(bad, 16);
+  }
+}
+
 __global__ void k_zero_i32(int32_t* p, int n) {
   for (int q = threadIdx.x; q < n; q += blockDim.x) p[q] = 0;
 }

@@ -110,7 +110,7 @@ struct MuCopies {
   static constexpr int value = TSIZE >= 64 ? 8 : 4;
 };
 
-template <int TSIZE, class AccT>
+template <int TSIZE, class AccT, bool PROBE>
 __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_t* Tid, uint8_t* Tty,
                                             AccT* __restrict__ acc, AccT* __restrict__ out, int32_t* scratch,
                                             int tid, int32_t* Th, int hlog, bool th_global) {
@@ -119,8 +119,8 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   AccT* Aa = acc;
   AccT* Ab = acc + LL;
   AccT* Q = acc + 2 * LL;
-  AccT* Mu = acc + 3 * LL;  // MuCopies<TSIZE> copies, lane l adds to copy l % copies
-  for (int x = tid; x < (3 + MuCopies<TSIZE>::value) * LL; x += TSIZE) acc[x] = 0;
+  AccT* Mu = acc + 3 * LL;  // PROBE: MuCopies<TSIZE> copies, lane l adds to copy l % copies
+  for (int x = tid; x < (PROBE ? 3 + MuCopies<TSIZE>::value : 3) * LL; x += TSIZE) acc[x] = 0;
   if (Th)
     for (int x = tid; x < (1 << hlog); x += TSIZE) Th[x] = -1;
   tsync<TSIZE>();
@@ -157,9 +157,11 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       const int32_t k = A.tl_k[base + q];
       const int t = A.ty[k];
       add_member(k, t, A.tl_e[2 * (base + q)], A.tl_e[2 * (base + q) + 1]);
-      Tid[q] = k;
-      Tty[q] = (uint8_t)t;
-      if (Th) hash_member(k, t);
+      if (PROBE) {
+        Tid[q] = k;
+        Tty[q] = (uint8_t)t;
+        if (Th) hash_member(k, t);
+      }
     }
   } else
   for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
@@ -194,7 +196,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       }
       __syncthreads();
     }
-    if (found) {
+    if (PROBE && found) {
       Tid[nT + before] = k;
       Tty[nT + before] = (uint8_t)t;
       if (Th) hash_member(k, t);
@@ -212,9 +214,10 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
 
   // ---- typed edges inside T (4-cliques through (i, j)), each found from its
   // lower end's degree-ordered out-list; (member, out-slot) pairs are dealt
-  // to lanes through a team prefix sum
+  // to lanes through a team prefix sum.  Without PROBE the clique pass has
+  // counted them already.
   int32_t* s_excl = scratch + 8;  // TSIZE == 256 only
-  for (int32_t q0 = 0; q0 < nT; q0 += TSIZE) {
+  for (int32_t q0 = 0; PROBE && q0 < nT; q0 += TSIZE) {
     const int32_t q = q0 + tid;
     int32_t ostart = 0, ocnt = 0, tk = 0;
     if (q < nT) {
@@ -335,14 +338,16 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   }
   if (A.work && tid == 0 && my_work) atomicAdd((unsigned long long*)&A.work[e], (unsigned long long)my_work);
   tsync<TSIZE>();
-  for (int x = tid; x < LL; x += TSIZE) {
-    AccT sum = Mu[x];
-    for (int c = 1; c < MuCopies<TSIZE>::value; ++c) sum += Mu[c * LL + x];
-    Mu[x] = sum;
+  if (PROBE) {
+    for (int x = tid; x < LL; x += TSIZE) {
+      AccT sum = Mu[x];
+      for (int c = 1; c < MuCopies<TSIZE>::value; ++c) sum += Mu[c * LL + x];
+      Mu[x] = sum;
+    }
+    tsync<TSIZE>();
   }
-  tsync<TSIZE>();
   if (out)
-    for (int x = tid; x < 4 * LL; x += TSIZE) out[x] = acc[x];
+    for (int x = tid; x < (PROBE ? 4 : 3) * LL; x += TSIZE) out[x] = acc[x];
   tsync<TSIZE>();
 }
 
@@ -408,13 +413,23 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
     while ((u + 1) * (u + 2) / 2 <= p) ++u;
     const int t = p - u * (u + 1) / 2;
     auto sym = [&](auto f) -> int64_t { return t == u ? f(t, t) : f(t, u) + f(u, t); };
-    auto M = [&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y] + (int64_t)Mu[y * L + x]; };
+    // M(x, y): edges between T^x and T^y counted from both ends, i.e. the
+    // 4-cliques through (i, j) with other types {x, y}, twice when x == y
+    auto k4 = [&](int x, int y) -> int64_t {
+      const int64_t q = (int64_t)pair_index(x, y) * A.m + e;
+      return A.K4w ? (int64_t)A.K4w[q] : (int64_t)A.K4n[q];
+    };
+    const bool have_k4 = A.K4w || A.K4n;
+    auto M = [&](int x, int y) -> int64_t {
+      if (have_k4) return (x == y ? 2 : 1) * k4(x, y);
+      return (int64_t)Mu[x * L + y] + (int64_t)Mu[y * L + x];
+    };
     auto ETSi = [&](int x, int y) -> int64_t { return (int64_t)Ai[x * L + y] - Tn(x) * (pj == y) - M(x, y); };
     auto ETSj = [&](int x, int y) -> int64_t { return (int64_t)Aj[x * L + y] - Tn(x) * (pi == y) - M(x, y); };
     auto ETI = [&](int x, int y) -> int64_t {
       return (int64_t)Q[x * L + y] - Tn(x) * ((pi == y) + (pj == y)) - M(x, y) - ETSi(x, y) - ETSj(x, y);
     };
-    const int64_t g12 = sym([&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y]; });
+    const int64_t g12 = have_k4 ? k4(t, u) : sym([&](int x, int y) -> int64_t { return (int64_t)Mu[x * L + y]; });
     const int64_t g10 = sym(ETSi) + sym(ETSj);
     const int64_t g8 = sym(ETI);
     const int64_t sSiSi = sym([&](int x, int y) -> int64_t { return (int64_t)Ui[x * L + y]; })
@@ -479,19 +494,20 @@ struct THashLog2 {
 // scratch][T hash (workgroup teams)][T ids][T types].  A T_ij larger than
 // the team's capacity (workgroup teams only) is kept in this workgroup's
 // slice of a global scratch.
-template <int TSIZE, class AccT>
+template <int TSIZE, class AccT, bool PROBE>
 __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, const int32_t* __restrict__ list,
                                                  AccT* __restrict__ ea, int32_t* __restrict__ t_over,
                                                  int64_t t_over_cap) {
   extern __shared__ uint64_t smem_comb[];
   constexpr int TEAMS = 256 / TSIZE;
-  constexpr int TCAP = TeamCap<TSIZE>::value;
+  // without PROBE, T_ij is streamed into the sums and not kept
+  constexpr int TCAP = PROBE ? TeamCap<TSIZE>::value : 0;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
   const int LL = A.L * A.L;
   const int team = threadIdx.x / TSIZE, tid = threadIdx.x % TSIZE;
   // per-team region, in bytes, rounded to 8
-  constexpr int HBYTES = THashLog2<TSIZE>::value ? (4 << THashLog2<TSIZE>::value) : 0;
-  const int acc_bytes = (3 + MuCopies<TSIZE>::value) * LL * (int)sizeof(AccT);
+  constexpr int HBYTES = (PROBE && THashLog2<TSIZE>::value) ? (4 << THashLog2<TSIZE>::value) : 0;
+  const int acc_bytes = (PROBE ? 3 + MuCopies<TSIZE>::value : 3) * LL * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   char* base = (char*)smem_comb + (int64_t)team * region;
   AccT* acc = (AccT*)base;
@@ -512,25 +528,25 @@ __global__ void __launch_bounds__(256) k_combine(EdgeArgs A, int64_t count, cons
     const int32_t e = list[w];
     bool big = false;
     uint32_t tsum = 0;
-    if (TSIZE > TG_WAVE) {
+    if (PROBE && TSIZE > TG_WAVE) {
       for (int t = 0; t < A.L; ++t) tsum += A.tau[(int64_t)e * A.L + t];
       big = tsum > (uint32_t)TCAP;
     }
     // a global table sized for this T_ij (at most the block's 2^hlog_g slots)
     // keeps the probed region small
-    gather_edge<TSIZE, AccT>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
+    gather_edge<TSIZE, AccT, PROBE>(A, e, big ? Tid_g : Tid_l, big ? Tty_g : Tty_l, acc,
                              ea ? ea + w * 4 * LL : nullptr, scratch, tid, big ? Th_g : Th,
                              big ? min(hlog_g, over_hash_log2(tsum)) : THashLog2<TSIZE>::value, big);
   }
 }
 
-// LDS bytes of k_combine<TSIZE, AccT>
-template <int TSIZE, class AccT>
+// LDS bytes of k_combine<TSIZE, AccT, PROBE>
+template <int TSIZE, class AccT, bool PROBE>
 inline size_t combine_lds_bytes(int L) {
-  constexpr int TCAP = TeamCap<TSIZE>::value;
+  constexpr int TCAP = PROBE ? TeamCap<TSIZE>::value : 0;
   constexpr int SCR = TSIZE > TG_WAVE ? 8 + 3 * TSIZE : 8;
-  constexpr int HBYTES = THashLog2<TSIZE>::value ? (4 << THashLog2<TSIZE>::value) : 0;
-  const int acc_bytes = (3 + MuCopies<TSIZE>::value) * L * L * (int)sizeof(AccT);
+  constexpr int HBYTES = (PROBE && THashLog2<TSIZE>::value) ? (4 << THashLog2<TSIZE>::value) : 0;
+  const int acc_bytes = (PROBE ? 3 + MuCopies<TSIZE>::value : 3) * L * L * (int)sizeof(AccT);
   const int region = ((acc_bytes + SCR * 4 + HBYTES + TCAP * 5) + 7) & ~7;
   return (size_t)(256 / TSIZE) * region;
 }

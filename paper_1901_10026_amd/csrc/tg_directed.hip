@@ -279,7 +279,7 @@ tg_status directed3_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_
   if (tg_status s = scan(S, st, n, W.n_upper, W.upper_off)) return s;
   if (tg_status s = scan(S, st, n, W.n_out, W.out_off)) return s;
   k_fill_edges<<<grid_for(n, 4), 256, 0, st>>>(n, rp, ci, W.deg, W.n_upper, W.upper_off, W.out_off, W.ei, W.ej,
-                                               W.s2e, W.es_lo, W.es_hi, W.out_col);
+                                               W.s2e, W.es_lo, W.es_hi, W.out_col, nullptr);
   TG_LAUNCHED("k_fill_edges");
   uint32_t* Dd;
   int32_t* c2r;

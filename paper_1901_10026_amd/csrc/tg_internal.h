@@ -50,6 +50,7 @@ struct Work {
   int32_t* es_lo;        // m     slot of each edge in its lower end's row
   int32_t* es_hi;        // m     slot of each edge in its upper end's row
   int32_t* out_col;      // m
+  int32_t* out_eid;      // m     canonical edge id of each out-list slot (clique pass only), or null
   uint32_t* tau;         // m*L
   uint32_t* tau_s;       // nnz*L: tau of each edge again at both of its CSR slots (per-edge counting only)
   int64_t* tl_off;       // m+1, or null: start of each edge's common-neighbour list kept by the tau pass
@@ -96,6 +97,11 @@ struct EdgeArgs {
   int gacc_in_lds;
   uint64_t* work;         // null, or per-edge element-visit counts (added atomically, by edge id)
   int thash_ok;           // node ids fit the packed (id << 4 | type) hash slots
+  // per-edge typed 4-clique counts from the clique pass, type-pair major
+  // (K4[p * m + e]), 32- or 64-bit; both null: the gather probes out-lists
+  const uint32_t* K4n;
+  const uint64_t* K4w;
+  int64_t m;
 };
 
 // Global key sums of one kernel: keys [k0, k0 + nk) are summed in `copies`

@@ -196,7 +196,7 @@ __global__ void k_fill_edges(int64_t n, const int32_t* __restrict__ rp, const in
                              const int32_t* __restrict__ upper_off, const int32_t* __restrict__ out_off,
                              int32_t* __restrict__ ei, int32_t* __restrict__ ej, int32_t* __restrict__ s2e,
                              int32_t* __restrict__ es_lo, int32_t* __restrict__ es_hi,
-                             int32_t* __restrict__ out_col) {
+                             int32_t* __restrict__ out_col, int32_t* __restrict__ out_eid) {
   const int64_t v = (int64_t)blockIdx.x * (blockDim.x / TG_WAVE) + threadIdx.x / TG_WAVE;
   if (v >= n) return;
   const int ln = lane();
@@ -208,23 +208,27 @@ __global__ void k_fill_edges(int64_t n, const int32_t* __restrict__ rp, const in
     const int32_t s = base + b0 + ln;
     const int32_t k = valid ? ci[s] : -1;
     const int32_t dk = valid ? deg[k] : 0;
+    int32_t e = 0;
     if (valid) {
       if (k > (int32_t)v) {
-        const int32_t e = upper_off[v] + (s - first_up);
+        e = upper_off[v] + (s - first_up);
         ei[e] = (int32_t)v;
         ej[e] = k;
         s2e[s] = e;
         es_lo[e] = s;
       } else {
         const int32_t p = rp[k] + lower_bound(ci + rp[k], dk, (int32_t)v);
-        const int32_t e = upper_off[k] + (p - (rp[k + 1] - n_upper[k]));
+        e = upper_off[k] + (p - (rp[k + 1] - n_upper[k]));
         s2e[s] = e;
         es_hi[e] = s;
       }
     }
     const bool hi = valid && precedes(dv, (int32_t)v, dk, k);
     const uint64_t mask = ballot(hi);
-    if (hi) out_col[out_off[v] + acc + lanes_below(mask)] = k;
+    if (hi) {
+      out_col[out_off[v] + acc + lanes_below(mask)] = k;
+      if (out_eid) out_eid[out_off[v] + acc + lanes_below(mask)] = e;
+    }
     acc += __popcll(mask);
   }
 }
@@ -804,6 +808,7 @@ __global__ void k_c4_fold(int64_t m, int P, int64_t nslots, const int32_t* __res
 }
 
 #include "tg_combine.hip"
+#include "tg_clique.hip"
 
 // ------------------------------------------------------------- schedule --
 

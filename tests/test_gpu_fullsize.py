@@ -118,3 +118,20 @@ def test_launch_shapes_agree_at_full_size(big):
     torch.cuda.synchronize()
     assert torch.equal(g2.view(torch.int64), glob.view(torch.int64))
     assert torch.equal(r2.view(torch.int64), rows.view(torch.int64))
+
+
+def test_clique_pass_equals_out_list_probes_at_full_size(big):
+    """4-cliques from the whole-graph pass (each clique once from its lowest
+    node, the default) and from the per-edge out-list probes of the gather:
+    the same rows; the pass also with few workgroups for its global-scratch
+    tier."""
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, glob, rows = big
+    for d in ({"clique_pass": 0}, {"clique_pass": 1, "clique_pass_grid": 7}):
+        g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=tg.Tuning.from_dict(d))
+        torch.cuda.synchronize()
+        note(f"tuning {d}: same rows")
+        assert torch.equal(g2.view(torch.int64), glob.view(torch.int64)), d
+        assert torch.equal(r2.view(torch.int64), rows.view(torch.int64)), d

@@ -62,7 +62,8 @@ def test_many_types(L):
     assert np.array_equal(gpu_global(rp, ci, ty, L), want)
 
 
-SMALL_CLASSES = {"clique_team_max": 2, "clique_wave_max": 6, "clique_lds_ids": 3}
+# the per-edge-class 4-clique kernels (no clique pass) with tiny class limits
+SMALL_CLASSES = {"clique_pass": 0, "clique_team_max": 2, "clique_wave_max": 6, "clique_lds_ids": 3}
 
 
 def test_clique_launch_classes_and_overflow():
@@ -100,6 +101,17 @@ def test_complete_graph_closed_form():
             want[oracle.key(L, shape, list(ms))] = c
     for tun in (None, tg.Tuning.from_dict(SMALL_CLASSES)):
         assert np.array_equal(gpu_global(rp, ci, ty, L, tuning=tun), want)
+    # K_400: the lowest node has 399 higher neighbours (global-scratch rows)
+    n = 400
+    rp, ci = complete(n)
+    ty = (np.arange(n) % L).astype(np.uint8)
+    got = gpu_global(rp, ci, ty, L)
+    sizes = np.bincount(ty, minlength=L)
+    for ms in itertools.combinations_with_replacement(range(L), 4):
+        c = 1
+        for t in set(ms):
+            c *= math.comb(int(sizes[t]), ms.count(t))
+        assert got[oracle.key(L, 7, list(ms))] == c
 
 
 def test_empty_and_edgeless_graphs():
@@ -129,3 +141,9 @@ def test_full_size_equals_per_edge_path():
     got2 = tg.count_global(rp, ci, ty, g.L, tuning=t)
     torch.cuda.synchronize()
     assert torch.equal(got2.view(torch.int64), want.view(torch.int64))
+    # 4-cliques from the edge classes instead of the clique pass, and the
+    # pass with few workgroups for its global-scratch tier
+    for d in ({"clique_pass": 0}, {"clique_pass_grid": 5}):
+        got3 = tg.count_global(rp, ci, ty, g.L, tuning=tg.Tuning.from_dict(d))
+        torch.cuda.synchronize()
+        assert torch.equal(got3.view(torch.int64), want.view(torch.int64)), d

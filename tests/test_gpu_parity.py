@@ -23,6 +23,8 @@ def assert_same(got_rows, got_glob, want_rows, want_glob, what):
 
 
 def test_tiny_graphs_match_brute_force():
+    import paper_1901_10026_amd as tg
+    probes = tg.Tuning.from_dict({"clique_pass": 0})
     for idx in range(200):
         g = graphgen.tiny_graph(idx)
         note(f"tiny{idx} n={g.n} m={g.m} L={g.L}")
@@ -30,6 +32,8 @@ def test_tiny_graphs_match_brute_force():
         for sched in ("none", "degree"):
             gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, schedule=sched, validate=True)
             assert_same(rr, gg, rb, gb, f"tiny{idx}/{sched}")
+        gg, rr, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L, tuning=probes)
+        assert_same(rr, gg, rb, gb, f"tiny{idx}/out-list probes")
 
 
 def test_every_graph_on_five_nodes():
@@ -226,3 +230,13 @@ def test_validation_reports_bad_graphs(case, status):
     with pytest.raises(tg.TGError) as e:
         gpu_count(rp, ci, ty, 2, validate=True)
     assert e.value.name == status, str(e.value)
+
+
+def test_release_scratch_between_calls():
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    g1, r1, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    tg.release_scratch()
+    tg.release_scratch()  # nothing held: still fine
+    g2, r2, _ = gpu_count(g.row_ptr, g.col_idx, g.types, g.L)
+    assert np.array_equal(g1, g2) and np.array_equal(r1, r2)
