@@ -369,6 +369,22 @@ tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot
                          const int64_t* key_off, uint64_t* global_counts, const tg_options* opt,
                          hipStream_t stream);
 
+/* tg_count_batch for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, such as tight serving loops or harnesses that
+ * forbid allocation): same arguments, results and errors, but its scratch
+ * (128 counters and a list of the graph ids) is a fixed array in the
+ * library's device memory, one per device, held until the process ends;
+ * the call allocates nothing and launches its kernels directly (no cached
+ * HIP graph).  At most 2,097,152 graphs per call (TG_ERR_INVALID_ARG
+ * beyond, before any device work).  Every call on one device shares that
+ * array and clears what it needs at the start: calls that overlap on one
+ * device (several threads or streams) race and must be serialised by the
+ * caller.  The first call on a device looks up the array's address. */
+tg_status tg_count_batch_noalloc(int64_t G, const int64_t* node_off, const int64_t* slot_off,
+                                 const int32_t* row_ptr_local, const int32_t* col_idx_local, const uint8_t* node_types,
+                                 const uint8_t* L_per_graph, const int64_t* key_off, uint64_t* global_counts,
+                                 const tg_options* opt, hipStream_t stream);
+
 /* ---- learned cost model (16-64-64-1 MLP, ReLU, bf16 weights, fp32
  * accumulation) that orders and bins edges for TG_SCHED_LEARNED.  A model
  * lives on the device that was current at creation. */

@@ -149,6 +149,8 @@ def lib():
     L.tg_rows_sparse.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
     L.tg_count_batch.restype = i32
     L.tg_count_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_count_batch_noalloc.restype = i32
+    L.tg_count_batch_noalloc.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_tuning_default.restype = None
     L.tg_tuning_default.argtypes = [ctypes.POINTER(Tuning)]
     L.tg_autotune.restype = i32
@@ -503,8 +505,9 @@ def release_scratch():
 
 
 def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_off, *, out=None, check=True,
-                tuning=None, validate=False):
-    """Global typed-graphlet counts of many small graphs with tg_count_batch.
+                tuning=None, validate=False, noalloc=False):
+    """Global typed-graphlet counts of many small graphs with tg_count_batch
+    (or, with noalloc, tg_count_batch_noalloc: no device allocation).
 
     All arguments are device tensors (int64 offsets, int32 CSR with local ids,
     uint8 types and L); key_off comes from key_offsets().  Returns the uint64
@@ -520,9 +523,9 @@ def count_batch(node_off, slot_off, row_ptr, col_idx, types, L_per_graph, key_of
     opt.check = 1 if check else 0
     opt.validate = 1 if validate else 0
     opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
-    st = lib().tg_count_batch(G, node_off.data_ptr(), slot_off.data_ptr(), row_ptr.data_ptr(), col_idx.data_ptr(),
-                              types.data_ptr(), L_per_graph.data_ptr(), key_off.data_ptr(), g.data_ptr(),
-                              ctypes.byref(opt), _stream_handle(torch, dev))
+    fn = lib().tg_count_batch_noalloc if noalloc else lib().tg_count_batch
+    st = fn(G, node_off.data_ptr(), slot_off.data_ptr(), row_ptr.data_ptr(), col_idx.data_ptr(), types.data_ptr(),
+            L_per_graph.data_ptr(), key_off.data_ptr(), g.data_ptr(), ctypes.byref(opt), _stream_handle(torch, dev))
     _check(st)
     return g
 

@@ -1258,15 +1258,9 @@ int variant_wmax(int v) {
   return (v >= 0 && v < 6) ? w[v] : 0;
 }
 
-tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
-                     const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off, uint64_t* out,
-                     const tg_options* opt_in, hipStream_t st) {
-  tg_options opt;
-  tg_options_default(&opt);
-  if (opt_in) opt = *opt_in;
-  tg_tuning tune;
-  tg_tuning_default(&tune);
-  if (opt.tuning) tune = *opt.tuning;
+tg_status batch_check(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
+                      const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off, uint64_t* out,
+                      const tg_tuning& tune) {
   if (G < 0 || G >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "G must be in [0, 2^31)");
   if (G == 0) return TG_OK;
   if (!node_off || !slot_off || !rp || !ci || !ty || !Lg || !key_off || !out)
@@ -1274,12 +1268,17 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
   for (int w = 0; w <= 8; ++w)
     if (variant_wmax(tune.batch_variant[w]) < std::max(1, w))
       return fail(TG_ERR_INVALID_ARG, "tuning assigns a size class to a kernel variant that is too small");
-  keep_pool_cached();
-  Scratch S(st);
-  int32_t* ctr;      // [0,72) sub-bucket counts, [80] bad flag, [96,112) queues, [120] divisibility flag
-  int32_t* list;
-  TG_HIP(S.get(&ctr, 128));
-  TG_HIP(S.get(&list, G));
+  return TG_OK;
+}
+
+// The batch pipeline on caller-provided scratch: ctr[128] ([0,72) sub-bucket
+// counts, [80] bad flag, [96,112) queues, [120] divisibility flag) and
+// list[G].  use_graph: replay the per-bucket launches from a cached HIP graph
+// (else launch them directly).
+tg_status batch_run(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
+                    const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off, uint64_t* out,
+                    const tg_options& opt, const tg_tuning& tune, int32_t* ctr, int32_t* list, bool use_graph,
+                    hipStream_t st) {
   k_zero_i32<<<1, 128, 0, st>>>(ctr, 128);
   TG_LAUNCHED("k_zero_i32");
   k_batch_classify<<<grid_for(G, 256, 4096), 256, 0, st>>>(G, node_off, Lg, key_off, ctr + 80);
@@ -1327,6 +1326,14 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
   }
   if (plan.size() > 16) return fail(TG_ERR_INTERNAL, "too many batch launches");
   BatchArgs A{node_off, slot_off, rp, ci, ty, Lg, key_off, out, ctr + 120};
+  if (!use_graph) {
+    k_zero_i32<<<1, 64, 0, st>>>(ctr + 96, 32);
+    TG_LAUNCHED("k_zero_i32");
+    for (size_t q = 0; q < plan.size(); ++q)
+      if (tg_status s2 = enqueue_batch_variant(plan[q].variant, A, plan[q].count, list + plan[q].offset,
+                                               ctr + 96 + (int)q, st))
+        return s2;
+  } else {
   // HIP graph: zero the queues and flag, then one persistent launch per bucket
   int dev = 0;
   TG_HIP(hipGetDevice(&dev));
@@ -1361,15 +1368,83 @@ tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off
     C.valid = true;
   }
   TG_HIP(hipGraphLaunch(C.exec, st));
+  }
   if (opt.check) {
     int32_t hf = 0;
     TG_HIP(hipMemcpyAsync(&hf, ctr + 120, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     TG_HIP(hipStreamSynchronize(st));
     if (hf) return fail(TG_ERR_INTERNAL, "a global sum is not a multiple of its shape's edge count");
-  } else {
-    // the scratch (lists, queues) is released stream-ordered after the graph
   }
   return TG_OK;
+}
+
+tg_status batch_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
+                     const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off, uint64_t* out,
+                     const tg_options* opt_in, hipStream_t st) {
+  tg_options opt;
+  tg_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  tg_tuning tune;
+  tg_tuning_default(&tune);
+  if (opt.tuning) tune = *opt.tuning;
+  if (tg_status s = batch_check(G, node_off, slot_off, rp, ci, ty, Lg, key_off, out, tune)) return s;
+  if (G == 0) return TG_OK;
+  keep_pool_cached();
+  Scratch S(st);  // its buffers are released stream-ordered after the launches
+  int32_t* ctr;
+  int32_t* list;
+  TG_HIP(S.get(&ctr, 128));
+  TG_HIP(S.get(&list, G));
+  return batch_run(G, node_off, slot_off, rp, ci, ty, Lg, key_off, out, opt, tune, ctr, list, true, st);
+}
+
+// ------------------------------------------------- batch, no allocation --
+//
+// Scratch of tg_count_batch_noalloc: a fixed device array (its 128 counters
+// and a list of up to TG_NOALLOC_MAX_GRAPHS graph ids), one copy per device,
+// held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+#define TG_NOALLOC_MAX_GRAPHS (1 << 21)
+static __device__ __align__(256) int32_t noalloc_scratch[128 + TG_NOALLOC_MAX_GRAPHS];
+
+std::mutex g_noalloc_mu;
+int32_t* g_noalloc_ptr[64] = {};
+
+// Device address of the current device's copy of noalloc_scratch, looked up
+// on the first call on that device.
+tg_status noalloc_scratch_ptr(int32_t** out) {
+  int dev = 0;
+  TG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(TG_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p)
+      return fail(TG_ERR_HIP, std::string("hipGetSymbolAddress(noalloc_scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = reinterpret_cast<int32_t*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return TG_OK;
+}
+
+tg_status batch_noalloc_impl(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* rp,
+                             const int32_t* ci, const uint8_t* ty, const uint8_t* Lg, const int64_t* key_off,
+                             uint64_t* out, const tg_options* opt_in, hipStream_t st) {
+  tg_options opt;
+  tg_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  tg_tuning tune;
+  tg_tuning_default(&tune);
+  if (opt.tuning) tune = *opt.tuning;
+  if (G > TG_NOALLOC_MAX_GRAPHS)
+    return fail(TG_ERR_INVALID_ARG, "tg_count_batch_noalloc takes at most " +
+                                        std::to_string(TG_NOALLOC_MAX_GRAPHS) + " graphs");
+  if (tg_status s = batch_check(G, node_off, slot_off, rp, ci, ty, Lg, key_off, out, tune)) return s;
+  if (G == 0) return TG_OK;
+  int32_t* scr = nullptr;
+  if (tg_status s = noalloc_scratch_ptr(&scr)) return s;
+  return batch_run(G, node_off, slot_off, rp, ci, ty, Lg, key_off, out, opt, tune, scr, scr + 128, false, st);
 }
 
 tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t n, const int32_t* rp, const int32_t* ci,
@@ -1684,6 +1759,20 @@ tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot
   try {
     return batch_impl(G, node_off, slot_off, row_ptr_local, col_idx_local, node_types, L_per_graph, key_off,
                       global_counts, opt, stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+tg_status tg_count_batch_noalloc(int64_t G, const int64_t* node_off, const int64_t* slot_off,
+                                 const int32_t* row_ptr_local, const int32_t* col_idx_local, const uint8_t* node_types,
+                                 const uint8_t* L_per_graph, const int64_t* key_off, uint64_t* global_counts,
+                                 const tg_options* opt, hipStream_t stream) {
+  try {
+    return batch_noalloc_impl(G, node_off, slot_off, row_ptr_local, col_idx_local, node_types, L_per_graph, key_off,
+                              global_counts, opt, stream);
   } catch (const std::exception& ex) {
     return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
   } catch (...) {
