@@ -314,6 +314,44 @@ tg_status tg_directed3_key_decode(int L, size_t key, uint8_t* arcs, uint8_t type
  * node order); TG_ERR_INVALID_ARG if the triad is not weakly connected. */
 tg_status tg_directed3_key_encode(int L, uint8_t arcs, const uint8_t types[3], size_t* key);
 
+/* Directed typed 4-node graphlets (the Directed Typed Graphlets subsection:
+ * typed out- and in-neighbour sets, one id per directed typed motif), on the
+ * same input as tg_count_directed3 (support CSR plus direction bytes).
+ * A 4-node digraph on ordered nodes 0..3 has one arc bit per ordered pair in
+ * the order (0,1) (0,2) (0,3) (1,0) (1,2) (1,3) (2,0) (2,1) (2,3) (3,0)
+ * (3,1) (3,2); its full code adds the four types, 4 bits each from bit 12;
+ * its canonical code is the smallest full code over the 24 node orderings.
+ * The keys of L types number, in increasing order, the canonical codes of
+ * the weakly connected digraphs with types below L:
+ * tg_directed4_num_keys(L) keys (199, 2818, 13770, 42802 for L = 1..4).
+ *   L             1..4 (TG_ERR_UNSUPPORTED_L otherwise)
+ *   global_counts device, uint64[tg_directed4_num_keys(L)]: the number of
+ *                 4-node sets inducing each key; or NULL
+ *   edge_rows     device, uint64[m * tg_directed4_num_keys(L)], or NULL: per
+ *                 canonical support edge (i, j), i < j, the number of
+ *                 weakly connected 4-node sets containing i and j per key
+ *   edge_info     device, int32[m * 3] receiving (i, j, c(i, j)), or NULL
+ *   opt           host or NULL: validate (also the direction bytes), check
+ *                 (global sums divisible by the key's support edges),
+ *                 phase_ms
+ * Per support edge the work is the sum of the degrees of the neighbours of
+ * i and j (the paper's per-edge enumeration bound), and the neighbourhood
+ * of each edge is held in LDS: every edge needs d_i + d_j - 2 <= 1024
+ * (TG_ERR_INVALID_ARG otherwise, found after one synchronisation).  Global
+ * counts are the row entries summed per key over the set's support edges
+ * and divided by their number. */
+tg_status tg_count_directed4(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const uint8_t* slot_dir, const uint8_t* node_types, int L, uint64_t* global_counts,
+                             uint64_t* edge_rows, int32_t* edge_info, const tg_options* opt, hipStream_t stream);
+
+/* Number of directed typed 4-node keys for L types (0 if L is outside
+ * [1, 4]). */
+size_t tg_directed4_num_keys(int L);
+
+/* Host.  Canonical digraph of a directed 4-node key: *arcs gets its 12 arc
+ * bits, types its four node types, in the canonical node order. */
+tg_status tg_directed4_key_decode(int L, size_t key, uint16_t* arcs, uint8_t types[4]);
+
 /* Sparse per-edge output (the Sparse Typed Motif Format subsection: only the
  * nonzero typed graphlet counts of each edge, with their ids).  Turns dense
  * per-edge rows into (global key, count) pairs; keys are the dense key rank

@@ -144,6 +144,12 @@ def lib():
     L.tg_directed3_key_decode.argtypes = [i32, sz, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint8)]
     L.tg_directed3_key_encode.restype = i32
     L.tg_directed3_key_encode.argtypes = [i32, ctypes.c_uint8, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(sz)]
+    L.tg_count_directed4.restype = i32
+    L.tg_count_directed4.argtypes = [i64, i64, vp, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
+    L.tg_directed4_num_keys.restype = sz
+    L.tg_directed4_num_keys.argtypes = [i32]
+    L.tg_directed4_key_decode.restype = i32
+    L.tg_directed4_key_decode.argtypes = [i32, sz, ctypes.POINTER(ctypes.c_uint16), ctypes.POINTER(ctypes.c_uint8)]
     L.tg_count_global_types.argtypes = [i64, i64, vp, vp, i64, vp, i32, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_rows_sparse.restype = i32
     L.tg_rows_sparse.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64), vp]
@@ -438,6 +444,58 @@ def count_directed3(row_ptr, col_idx, slot_dir, types, L, *, per_edge=True, info
     opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
     ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None
     st = lib().tg_count_directed3(n, nnz, row_ptr.data_ptr(), ptr(col_idx), ptr(slot_dir), ptr(types), L, ptr(g),
+                                  ptr(rows), ptr(inf), ctypes.byref(opt), _stream_handle(torch, dev))
+    _check(st)
+    if times is not None:
+        phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
+    return g, rows, inf
+
+
+def directed4_num_keys(L: int) -> int:
+    return int(lib().tg_directed4_num_keys(L))
+
+
+def directed4_key_decode(L: int, key: int):
+    """(12 arc bits, four types) of a directed 4-node key's canonical digraph."""
+    arcs = ctypes.c_uint16()
+    ty = (ctypes.c_uint8 * 4)()
+    _check(lib().tg_directed4_key_decode(L, key, ctypes.byref(arcs), ty))
+    return int(arcs.value), tuple(int(ty[q]) for q in range(4))
+
+
+def count_directed4(row_ptr, col_idx, slot_dir, types, L, *, per_edge=False, info=False, global_counts=True,
+                    validate=False, check=True, phase_ms=None):
+    """Directed typed 4-node graphlets with tg_count_directed4 (L <= 4).
+    Inputs as for count_directed3.  Returns (global uint64 [K] or None, rows
+    uint64 [m, K] or None, info int32 [m, 3] or None), K =
+    directed4_num_keys(L)."""
+    import torch
+    dev = row_ptr.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be device tensors")
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (slot_dir, torch.uint8), (types, torch.uint8)):
+        if t.dtype != dt or not t.is_contiguous() or t.device != dev:
+            raise ValueError("row_ptr/col_idx must be contiguous int32, slot_dir/types contiguous uint8, one device")
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if slot_dir.numel() != nnz:
+        raise ValueError("slot_dir needs one byte per CSR slot")
+    K = directed4_num_keys(L)
+    if K == 0:
+        raise TGError(4, "L must be in [1, 4]")
+    m = nnz // 2
+    g = torch.empty(K, dtype=torch.uint64, device=dev) if global_counts else None
+    rows = torch.empty((m, K), dtype=torch.uint64, device=dev) if per_edge else None
+    inf = torch.empty((m, 3), dtype=torch.int32, device=dev) if info else None
+    if g is None and rows is None:
+        raise ValueError("ask for global counts, rows or both")
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.validate = 1 if validate else 0
+    opt.check = 1 if check else 0
+    times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
+    opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None
+    st = lib().tg_count_directed4(n, nnz, row_ptr.data_ptr(), ptr(col_idx), ptr(slot_dir), ptr(types), L, ptr(g),
                                   ptr(rows), ptr(inf), ctypes.byref(opt), _stream_handle(torch, dev))
     _check(st)
     if times is not None:

@@ -1710,6 +1710,7 @@ tg_status tg_internal_predict_costs(const tg_cost_model* model, int64_t, const i
 // ------------------------------------------------------------------ ABI --
 
 #include "tg_directed.hip"
+#include "tg_directed4.hip"
 
 extern "C" {
 
@@ -1945,6 +1946,39 @@ tg_status tg_count_directed3(int64_t n, int64_t nnz, const int32_t* row_ptr, con
   } catch (...) {
     return fail(TG_ERR_INTERNAL, "unknown exception");
   }
+}
+
+tg_status tg_count_directed4(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                             const uint8_t* slot_dir, const uint8_t* node_types, int L, uint64_t* global_counts,
+                             uint64_t* edge_rows, int32_t* edge_info, const tg_options* opt, hipStream_t stream) {
+  try {
+    return directed4_impl(n, nnz, row_ptr, col_idx, slot_dir, node_types, L, global_counts, edge_rows, edge_info,
+                          opt, stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+size_t tg_directed4_num_keys(int L) {
+  if (L < 1 || L > dir4::kMaxL) return 0;
+  try {
+    return dir4::tables(L).canon.size();
+  } catch (...) {
+    return 0;
+  }
+}
+
+tg_status tg_directed4_key_decode(int L, size_t key, uint16_t* arcs, uint8_t types[4]) {
+  if (L < 1 || L > dir4::kMaxL) return fail(TG_ERR_UNSUPPORTED_L, "L must be in [1, 4]");
+  if (!arcs || !types) return fail(TG_ERR_INVALID_ARG, "null pointer");
+  const dir4::Tables& T = dir4::tables(L);
+  if (key >= T.canon.size()) return fail(TG_ERR_INVALID_ARG, "key out of range");
+  const int64_t c = T.canon[key];
+  *arcs = (uint16_t)(c & 0xFFF);
+  for (int q = 0; q < 4; ++q) types[q] = (uint8_t)((c >> (12 + 4 * q)) & 15);
+  return TG_OK;
 }
 
 size_t tg_directed3_num_keys(int L) {

@@ -297,6 +297,7 @@ tg_status directed3_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_
   TG_LAUNCHED("k_dir_degree");
   timer.mark(TG_PHASE_SCHEDULE);
   timer.mark(TG_PHASE_CYCLES);
+  timer.mark(TG_PHASE_CLIQUES);
   // ---- per edge
   timer.mark(TG_PHASE_COMBINE);
   uint64_t* gsum = global_counts;

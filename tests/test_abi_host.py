@@ -146,3 +146,17 @@ def test_tuning_defaults_and_round_trip():
     d = t.as_dict()
     d["tlist_budget_mib"] = 0
     assert tg.Tuning.from_dict(d).as_dict() == d
+
+
+def test_directed4_keys_match_the_oracle():
+    """The library's directed 4-node key list (host tables, no device work)
+    equals the oracle's: same count and the same canonical digraph per key."""
+    import paper_1901_10026_amd as tg
+    from oracle import directed4 as d4
+    assert tg.directed4_num_keys(0) == 0 and tg.directed4_num_keys(5) == 0
+    for L in (1, 2, 3):
+        ks = d4.keys(L)
+        assert tg.directed4_num_keys(L) == len(ks)
+        for q in list(range(0, len(ks), max(1, len(ks) // 300))) + [len(ks) - 1]:
+            arcs, ty = tg.directed4_key_decode(L, q)
+            assert arcs | sum(t << (12 + 4 * p) for p, t in enumerate(ty)) == int(ks[q])
