@@ -280,14 +280,21 @@ def chung_lu_1m(mean=None) -> Graph:
                                              types="zipf1.2+homophily0.7"))
 
 
+# Expected edge count before probability capping for the bipartite graph,
+# calibrated so that the realised count is close to 50M (50,003,127 edges,
+# maximum degree 81,476).
+BIP50M_PRECAP_M = 53_600_000
+
+
 def bipartite_50m() -> Graph:
     """Bipartite Chung-Lu user-item graph: 2M type-0 nodes (exponent 2.1,
     mean 25, max expected degree 2e4) and 500k type-1 nodes (exponent 1.8,
-    mean 100, max expected degree 1e5), 50M expected edges, only between the
-    two sides; L=2 with the side as the type; seed 31."""
-    rp, ci, parts = kpartite_cl([2_000_000, 500_000], [2.1, 1.8], [2e4, 1e5], [25.0, 100.0], 50_000_000, 31)
+    mean 100, max expected degree 1e5), about 50M edges, only between the two
+    sides; L=2 with the side as the type; seed 31."""
+    rp, ci, parts = kpartite_cl([2_000_000, 500_000], [2.1, 1.8], [2e4, 1e5], [25.0, 100.0], BIP50M_PRECAP_M, 31)
     return Graph("bip-50m", rp, ci, parts, 2, dict(model="bipartite-chung-lu", sizes=[2_000_000, 500_000],
-                                                  gamma=[2.1, 1.8], wmax=[2e4, 1e5], mean=[25, 100], seed=31))
+                                                  gamma=[2.1, 1.8], wmax=[2e4, 1e5], mean=[25, 100],
+                                                  precap_m=BIP50M_PRECAP_M, seed=31))
 
 
 def tripartite_30m() -> Graph:
@@ -300,13 +307,19 @@ def tripartite_30m() -> Graph:
                                                   gamma=2.1, wmax=2e4, seed=32))
 
 
+# Mean expected degree of the 20M-node graph, calibrated so that the
+# realised edge count after probability capping is close to 300M
+# (300,032,326 edges, maximum degree 296,629).
+CL20M_MEAN = 32.85
+
+
 def chung_lu_20m() -> Graph:
-    """Chung-Lu, n=20M, exponent 2.0, max expected degree 5e5, mean 30
-    (about 3e8 edges before probability capping), L=8 types iid Zipf(1.0),
+    """Chung-Lu, n=20M, exponent 2.0, max expected degree 5e5, mean 32.85
+    (about 3.0e8 edges after probability capping), L=8 types iid Zipf(1.0),
     seed 5."""
-    rp, ci = chung_lu(20_000_000, 2.0, 5e5, 30.0, 5)
+    rp, ci = chung_lu(20_000_000, 2.0, 5e5, CL20M_MEAN, 5)
     ty = types_zipf(20_000_000, 8, 1.0, 5)
-    return Graph("cl-20m", rp, ci, ty, 8, dict(model="chung-lu", gamma=2.0, wmax=5e5, mean=30.0, seed=5,
+    return Graph("cl-20m", rp, ci, ty, 8, dict(model="chung-lu", gamma=2.0, wmax=5e5, mean=CL20M_MEAN, seed=5,
                                               types="zipf1.0"))
 
 
