@@ -469,42 +469,108 @@ def directed_leg(tg, g, rp, ci, ty, steps=3):
             "edges_per_s": g.m / (ms * 1e-3), "phase_ms": {k: v for k, v in phases.items() if v > 0}}
 
 
-def giant_schedules_leg(tg, dev, frac=0.01, seed=31):
-    """The 20M-node skewed graph: per-edge rows of a seeded uniform edge
-    sample (rows only; its rows for all edges would not fit) under the
-    degree-product schedule and the learned one (MLP trained on a 1% edge
-    sample of the same graph), with identical rows."""
+def directed4_leg(tg, dev, steps=3):
+    """Directed typed 4-node graphlets on the 2000-node Chung-Lu graph (L = 3)
+    oriented by a seeded draw (20% of edges reciprocal): per-edge rows over
+    every directed typed 4-node key and global counts."""
+    import torch
+
+    import graphgen
+    g = graphgen.chung_lu_small()
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    ci = torch.from_numpy(g.col_idx).to(dev)
+    ty = torch.from_numpy(g.types).to(dev)
+    sd = torch.from_numpy(graphgen.orient(g.row_ptr, g.col_idx, 23, 0.2)).to(dev)
+    glob, rows, _ = tg.count_directed4(rp, ci, sd, ty, g.L, per_edge=True)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for _ in range(steps):
+        tg.count_directed4(rp, ci, sd, ty, g.L, per_edge=True)
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / steps
+    K = tg.directed4_num_keys(g.L)
+    sets = int(glob.view(torch.int64).sum().item())
+    log(f"directed 4-node (cl-2k oriented): {ms:.2f} ms, {K} keys, {sets} sets")
+    return {"workload": "cl-2k", "orientation": "seed 23, 20% reciprocal", "L": g.L, "keys": K, "ms": ms,
+            "edges_per_s": g.m / (ms * 1e-3), "directed_sets": sets,
+            "nonzero_keys": int(glob.view(torch.int64).ne(0).sum().item())}
+
+
+def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1):
+    """The 20M-node skewed graph (300M edges, L = 8) through the whole
+    per-edge path: one tg_count over every edge, with global counts from the
+    per-edge sums (Eq. 17) and per-edge rows for the first `rows_edges`
+    canonical edges, under the degree-product schedule and under the learned
+    one (MLP trained on a 1% edge sample of the same graph).  Counts and rows
+    must be identical; each call is timed with HIP events on the stream, and
+    the degree call is repeated `repeats` times for its spread."""
     import torch
 
     import graphgen
     t0 = time.time()
     g = graphgen.workload("cl-20m")
-    log(f"cl-20m: n={g.n} m={g.m} ({time.time() - t0:.0f} s to generate)")
+    gen_s = time.time() - t0
+    d = np.diff(g.row_ptr)
+    log(f"cl-20m: n={g.n} m={g.m} max_deg={int(d.max())} ({gen_s:.0f} s to generate)")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     ci = torch.from_numpy(g.col_idx).to(dev)
     ty = torch.from_numpy(g.types).to(dev)
-    rng = np.random.default_rng(seed)
-    ids = np.sort(rng.choice(g.m, size=int(g.m * frac), replace=False)).astype(np.int64)
-    d_ids = torch.from_numpy(ids).to(dev)
+    K, R = tg.num_keys(g.L), tg.edge_row_width(g.L)
+    res = {"workload": "cl-20m", "n": g.n, "m": g.m, "L": g.L, "max_degree": int(d.max()),
+           "rows_for_edges": rows_edges, "generate_s": gen_s}
+    outs = {}
+
+    def one(sched, model=None):
+        out_g = torch.empty(K, dtype=torch.uint64, device=dev)
+        out_e = torch.empty((rows_edges, R), dtype=torch.uint64, device=dev)
+        ph = {}
+        torch.cuda.synchronize()
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        tg.count(rp, ci, ty, g.L, per_edge=True, edge_range=(0, rows_edges), schedule=sched, model=model,
+                 out_global=out_g, out_edges=out_e, phase_ms=ph)
+        s1.record()
+        torch.cuda.synchronize()
+        ms = s0.elapsed_time(s1)
+        free, total_mem = torch.cuda.mem_get_info()
+        res["device_bytes_used_after_call"] = int(total_mem - free)
+        return ms, ph, out_g, out_e
+
+    runs = []
+    for r in range(max(1, repeats)):
+        ms, ph, og, oe = one("degree")
+        runs.append(ms)
+        log(f"cl-20m per-edge path, degree schedule: {ms / 1e3:.1f} s (" +
+            " ".join(f"{k}={v / 1e3:.1f}s" for k, v in ph.items() if v > 0) + ")")
+        outs["degree"] = (og, oe)
+        res["degree"] = {"ms": ms, "phase_ms": ph}
+    res["degree"]["ms_runs"] = runs
+    tg.release_scratch()
     model = tg.CostModel(seed=57)
     torch.cuda.synchronize()
     t0 = time.time()
     model.train(rp, ci, ty, g.L, sample_frac=0.01, seed=58, epochs=15)
-    train_ms = (time.time() - t0) * 1e3
-    res = {"workload": "cl-20m", "sample_edges": len(ids), "mlp_train_ms": train_ms}
-    rows = {}
-    for sched in ("degree", "learned"):
-        ph = {}
-        torch.cuda.synchronize()
-        t0 = time.time()
-        _, r, _ = tg.count(rp, ci, ty, g.L, edge_ids=d_ids, global_counts=False, schedule=sched,
-                           model=model if sched == "learned" else None, phase_ms=ph)
-        torch.cuda.synchronize()
-        res[sched] = {"ms": (time.time() - t0) * 1e3, "phase_ms": ph}
-        rows[sched] = r
-        log(f"cl-20m sample, {sched} schedule: " + " ".join(f"{k}={v:.0f}ms" for k, v in ph.items()))
-    res["equal"] = bool(torch.equal(rows["degree"].view(torch.int64), rows["learned"].view(torch.int64)))
-    log(f"cl-20m rows identical under both schedules: {res['equal']}")
+    res["mlp_train_ms"] = (time.time() - t0) * 1e3
+    ms, ph, og, oe = one("learned", model)
+    outs["learned"] = (og, oe)
+    res["learned"] = {"ms": ms, "phase_ms": ph}
+    log(f"cl-20m per-edge path, learned schedule: {ms / 1e3:.1f} s (" +
+        " ".join(f"{k}={v / 1e3:.1f}s" for k, v in ph.items() if v > 0) + f"), training {res['mlp_train_ms']:.0f} ms")
+    res["equal"] = bool(torch.equal(outs["degree"][0].view(torch.int64), outs["learned"][0].view(torch.int64)) and
+                        torch.equal(outs["degree"][1].view(torch.int64), outs["learned"][1].view(torch.int64)))
+    glob = outs["degree"][0].cpu().numpy().view(np.uint64)
+    total = int(sum(int(x) for x in glob))
+    res["typed_graphlets"] = total
+    res["edges_per_s"] = {k: g.m / (res[k]["ms"] * 1e-3) for k in ("degree", "learned")}
+    res["typed_graphlets_per_s"] = {k: total / (res[k]["ms"] * 1e-3) for k in ("degree", "learned")}
+    log(f"cl-20m: rows and global counts identical under both schedules: {res['equal']}")
+    del outs, rp, ci, ty
+    tg.release_scratch()
+    torch.cuda.empty_cache()
     return res
 
 
@@ -644,9 +710,10 @@ def main():
     ap.add_argument("--no-directed", action="store_true", help="skip the directed 3-node leg")
     ap.add_argument("--giant-global", action="store_true",
                     help="also count the 20M-node graph's global counts in full, typed and untyped (minutes)")
-    ap.add_argument("--giant-schedules", action="store_true",
-                    help="also compare the degree and learned schedules on a 1%% edge sample of the 20M-node graph "
-                         "(several minutes)")
+    ap.add_argument("--no-giant", action="store_true",
+                    help="skip the 20M-node graph's per-edge leg (every edge counted under the degree and the "
+                         "learned schedule, several minutes)")
+    ap.add_argument("--giant-repeats", type=int, default=1, help="degree-schedule calls of the 20M-node leg")
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -754,12 +821,22 @@ def main():
         rec["null_model"] = null_leg(tg, g, rp, ci, ty, permutations=args.permutations)
     if not args.no_directed:
         rec["directed3"] = directed_leg(tg, g, rp, ci, ty)
+        rec["directed4"] = directed4_leg(tg, dev)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
     if args.giant_global:
         rec["giant_global"] = giant_global_leg(tg, dev)
-    if args.giant_schedules:
-        rec["giant_schedules"] = giant_schedules_leg(tg, dev)
+    if not args.no_giant:
+        # the 20M-node graph needs most of the device: drop this graph's
+        # buffers and the library's cached scratch first
+        del out_e
+        tg.release_scratch()
+        torch.cuda.empty_cache()
+        try:
+            rec["giant_per_edge"] = giant_per_edge_leg(tg, dev, repeats=args.giant_repeats)
+        except Exception as ex:  # reported in the line; the rest of the run still counts
+            log(f"cl-20m per-edge leg failed: {ex}")
+            rec["giant_per_edge"] = {"error": str(ex)}
     if not args.no_batch:
         rec["batch"] = batch_leg(tg, dev)
     if not args.no_cpu_baseline:
