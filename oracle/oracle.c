@@ -297,6 +297,25 @@ static int classify_config(int ck, int cl, int kl, int* orbit) {
   return h;
 }
 
+/* classify_config for every (ck, cl, kl): the shapes and orbits of the 32
+ * configurations, computed once by that function. */
+typedef struct { int h, orbit; } or_config;
+static or_config g_config[4][4][2];
+static int g_config_ready = 0;
+
+static void config_table_init(void) {
+  if (g_config_ready) return;
+  for (int ck = 0; ck < 4; ++ck)
+    for (int cl = 0; cl < 4; ++cl)
+      for (int kl = 0; kl < 2; ++kl) {
+        int orb = 0;
+        const int h = classify_config(ck, cl, kl, &orb);
+        g_config[ck][cl][kl].h = h;
+        g_config[ck][cl][kl].orbit = orb;
+      }
+  g_config_ready = 1;
+}
+
 /* Counts one edge (i, j) into a graphlet row (width R) and, optionally, an
  * orbit row (width 2L + 10P). */
 static void count_edge(or_work* w, const int32_t* row_ptr, const int32_t* col_idx, const uint8_t* phi,
@@ -331,7 +350,6 @@ static void count_edge(or_work* w, const int32_t* row_ptr, const int32_t* col_id
   }
   /* (a) l outside U and not i or j, adjacent to k in U; (b) adjacent pairs
    * inside U, each once (from its smaller id) */
-  int orb;
   for (int64_t a = 0; a < nU; ++a) {
     const int32_t k = w->U[a];
     const int ck = cls[k];
@@ -339,19 +357,14 @@ static void count_edge(or_work* w, const int32_t* row_ptr, const int32_t* col_id
       const int32_t l = col_idx[s];
       if (l == i || l == j) continue;
       const int cl = cls[l];
-      if (cl == 0) {
-        const int h = classify_config(ck, 0, 1, &orb);
-        const int64_t p = pair_index(phi[k], phi[l]);
-        row[2 * L + (int64_t)(h - 2) * P + p]++;
-        if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p]++;
-      } else {
+      if (cl != 0) {
         ADJC(ck, phi[k], cl, phi[l])++;  /* every adjacent pair twice, once per order */
         if (l < k) continue;
-        const int h = classify_config(ck, cl, 1, &orb);
-        const int64_t p = pair_index(phi[k], phi[l]);
-        row[2 * L + (int64_t)(h - 2) * P + p]++;
-        if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p]++;
       }
+      const or_config c = g_config[ck][cl][1];
+      const int64_t p = pair_index(phi[k], phi[l]);
+      row[2 * L + (int64_t)(c.h - 2) * P + p]++;
+      if (orow) orow[2 * L + (int64_t)(c.orbit - 3) * P + p]++;
     }
   }
   /* (b) non-adjacent pairs of U, per unordered (class, type) combination */
@@ -364,10 +377,10 @@ static void count_edge(or_work* w, const int32_t* row_ptr, const int32_t* col_id
           const uint64_t adjacent = same ? ADJC(c1, t1, c2, t2) / 2 : ADJC(c1, t1, c2, t2);
           const uint64_t v = all - adjacent;
           if (!v) continue;
-          const int h = classify_config(c1, c2, 0, &orb);
+          const or_config c = g_config[c1][c2][0];
           const int64_t p = pair_index(t1, t2);
-          row[2 * L + (int64_t)(h - 2) * P + p] += v;
-          if (orow) orow[2 * L + (int64_t)(orb - 3) * P + p] += v;
+          row[2 * L + (int64_t)(c.h - 2) * P + p] += v;
+          if (orow) orow[2 * L + (int64_t)(c.orbit - 3) * P + p] += v;
         }
 #undef CNT
 #undef ADJC
@@ -393,6 +406,7 @@ int or_count_edges(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, co
   const int64_t dmax = max_degree(n, row_ptr);
   int status = OR_OK;
   if (nthreads < 1) nthreads = 1;
+  config_table_init();
 #pragma omp parallel num_threads(nthreads) reduction(min : status)
   {
     or_work w;
