@@ -714,6 +714,8 @@ def main():
                     help="skip the 20M-node graph's per-edge leg (every edge counted under the degree and the "
                          "learned schedule, several minutes)")
     ap.add_argument("--giant-repeats", type=int, default=1, help="degree-schedule calls of the 20M-node leg")
+    ap.add_argument("--giant-only", action="store_true",
+                    help="only run the 20M-node per-edge leg and print its object (for profiling)")
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -748,6 +750,10 @@ def main():
 
     graphgen.build(force=False)
     dev = torch.device("cuda:0")
+    if args.giant_only:
+        # the 20M-node per-edge leg alone (for profiling it), as its own line
+        print(json.dumps({"giant_per_edge": giant_per_edge_leg(tg, dev, repeats=args.giant_repeats)}), flush=True)
+        return
     t0 = time.time()
     g = graphgen.workload(args.workload)
     log(f"workload {g.name}: n={g.n} m={g.m} L={g.L} max_deg={int(np.diff(g.row_ptr).max())} "

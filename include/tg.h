@@ -125,9 +125,10 @@ typedef struct {
                                  per-edge step covers at least an eighth of the edges and no node has
                                  more than 4096 higher-ranked neighbours; 0 = the per-edge gather finds
                                  them from out-lists instead */
-  int32_t clique_pass_grid;   /* tg_count: workgroups of the clique pass for nodes with more than 256
-                                 higher-ranked neighbours, each with a global scratch slice
-                                 (0 = two per compute unit) */
+  int32_t clique_pass_grid;   /* tg_count: workgroups of the clique pass's global-scratch launch, each
+                                 with a slice of its own (0 = two per compute unit) */
+  int32_t clique_pass_lds_kib;/* tg_count: a tier of the clique pass keeps its bit rows in LDS when they
+                                 fit in this many KiB per workgroup, else in global scratch */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */
@@ -226,6 +227,33 @@ tg_status tg_edge_row_key(int L, uint8_t phi_i, uint8_t phi_j, size_t col, size_
 tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                    const uint8_t* node_types, int L, uint64_t* global_counts, uint64_t* edge_counts,
                    int32_t* edge_endpoints, const tg_options* opt, hipStream_t stream);
+
+/* tg_count with the paper's sparse per-edge output (the Sparse Typed Motif
+ * Format subsection: only the nonzero typed graphlet counts of each edge,
+ * with their ids), written by the row kernel itself: no dense per-edge row
+ * is ever stored, so the per-edge output of a graph whose dense rows would
+ * not fit can be taken in one call.  Arguments as for tg_count, with the
+ * edges of opt's range or id list (E of them) and, in place of the dense
+ * rows:
+ *   capacity    number of (key, count) pairs the caller's buffers hold
+ *   keys        device, uint32[capacity]: the pairs' global keys (dense
+ *               rank of tg_key_encode; tg_key_decode is the lookup table)
+ *   counts      device, uint64[capacity]: the pairs' counts (nonzero)
+ *   edge_start  device, int64[E]: first pair of edge q
+ *   edge_len    device, int32[E]: number of pairs of edge q, in the row's
+ *               column order
+ *   total       host: receives the number of pairs of all E edges
+ * The edges' pairs lie at arbitrary but disjoint places of [0, total).  L
+ * must be at most 8 (TG_ERR_UNSUPPORTED_L).  The call synchronises to read
+ * the total; with total > capacity it returns TG_ERR_INVALID_ARG after the
+ * counting (edge_start and edge_len are written, the pairs are not all
+ * written), so a caller may count once with capacity 0 and again with the
+ * reported total, or size the buffers by E * R(L).  global_counts may be
+ * NULL, as for tg_count. */
+tg_status tg_count_sparse(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                          const uint8_t* node_types, int L, uint64_t* global_counts, int64_t capacity,
+                          uint32_t* keys, uint64_t* counts, int64_t* edge_start, int32_t* edge_len,
+                          int64_t* total, const tg_options* opt, hipStream_t stream);
 
 /* Global counts only, every instance counted a fixed number of times instead
  * of once per edge (the Global Typed Graphlet Counts section notes that an

@@ -64,11 +64,11 @@ class Tuning(ctypes.Structure):
                 ("batch_variant", ctypes.c_int32 * 9), ("clique_team_max", ctypes.c_int32),
                 ("clique_wave_max", ctypes.c_int32), ("clique_lds_ids", ctypes.c_int32),
                 ("tlist_budget_mib", ctypes.c_int32), ("clique_pass", ctypes.c_int32),
-                ("clique_pass_grid", ctypes.c_int32)]
+                ("clique_pass_grid", ctypes.c_int32), ("clique_pass_lds_kib", ctypes.c_int32)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
                "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
                "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids", "tlist_budget_mib",
-               "clique_pass", "clique_pass_grid")
+               "clique_pass", "clique_pass_grid", "clique_pass_lds_kib")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}
@@ -134,6 +134,9 @@ def lib():
     L.tg_count.restype = i32
     L.tg_count.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(_Options), vp]
     L.tg_count_global.restype = i32
+    L.tg_count_sparse.restype = i32
+    L.tg_count_sparse.argtypes = [i64, i64, vp, vp, vp, i32, vp, i64, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(_Options), vp]
     L.tg_count_global.argtypes = [i64, i64, vp, vp, vp, i32, vp, ctypes.POINTER(_Options), vp]
     L.tg_count_global_types.restype = i32
     L.tg_count_directed3.restype = i32
@@ -554,6 +557,52 @@ def key_offsets(L_per_graph):
     off = np.zeros(len(sizes) + 1, dtype=np.int64)
     np.cumsum(sizes, out=off[1:])
     return off
+
+
+def count_sparse(row_ptr, col_idx, types, L, *, capacity=None, schedule="degree", edge_range=None, edge_ids=None,
+                 global_counts=True, model=None, tuning=None, check=True, validate=False, phase_ms=None):
+    """Sparse per-edge output straight from the row kernel (tg_count_sparse):
+    nonzero (global key, count) pairs of the edges in edge_range (default
+    all) or edge_ids.  capacity (pairs) defaults to E * R(L), the most
+    there can be.  Returns (global uint64 [K] or None, keys uint32 [total],
+    counts uint64 [total], start int64 [E], length int32 [E]); edge q's
+    pairs are keys[start[q]:start[q] + length[q]]."""
+    import torch
+    dev = row_ptr.device
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    m = nnz // 2
+    e0, e1 = (0, m) if edge_range is None else (int(edge_range[0]), int(edge_range[1]))
+    E = edge_ids.numel() if edge_ids is not None else e1 - e0
+    K, R = num_keys(L), edge_row_width(L)
+    cap = E * R if capacity is None else int(capacity)
+    keys = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    counts = torch.empty(max(cap, 1), dtype=torch.uint64, device=dev)
+    start = torch.empty(max(E, 1), dtype=torch.int64, device=dev)
+    length = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    g = torch.empty(K, dtype=torch.uint64, device=dev) if global_counts else None
+    opt = _Options()
+    lib().tg_options_default(ctypes.byref(opt))
+    opt.schedule = SCHEDULES[schedule]
+    opt.model = ctypes.c_void_p(model.handle) if model is not None else None
+    opt.tuning = ctypes.cast(ctypes.pointer(tuning), ctypes.c_void_p) if tuning is not None else None
+    opt.check = 1 if check else 0
+    opt.validate = 1 if validate else 0
+    opt.edge_begin, opt.edge_end = e0, e1
+    if edge_ids is not None:
+        opt.edge_ids = edge_ids.data_ptr()
+        opt.num_edge_ids = E
+    times = (ctypes.c_float * len(PHASES))() if phase_ms is not None else None
+    opt.phase_ms = ctypes.cast(times, ctypes.c_void_p) if times is not None else None
+    total = ctypes.c_int64(0)
+    st = lib().tg_count_sparse(n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(), types.data_ptr(), L,
+                               g.data_ptr() if g is not None else None, cap, keys.data_ptr(), counts.data_ptr(),
+                               start.data_ptr(), length.data_ptr(), ctypes.byref(total), ctypes.byref(opt),
+                               _stream_handle(torch, dev))
+    _check(st)
+    if times is not None:
+        phase_ms.update({name: float(times[q]) for q, name in enumerate(PHASES)})
+    t = int(total.value)
+    return g, keys[:t], counts[:t], start[:E], length[:E]
 
 
 def release_scratch():

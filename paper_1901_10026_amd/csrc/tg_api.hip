@@ -251,7 +251,9 @@ tg_status combine_class(hipStream_t st, const EdgeArgs& A, int64_t count, const 
   const int64_t per = 4ll * A.L * A.L * (int64_t)sizeof(AccT);
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(count, ea_budget / per));
   const size_t lds = combine_lds_bytes<TSIZE, AccT, PROBE>(A.L);
-  const size_t rlds = A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0;
+  const int R = 2 * A.L + 3 * A.L * (A.L + 1);
+  const size_t rlds = (A.gacc_in_lds ? (size_t)K * sizeof(uint64_t) : 0) +
+                      (A.sp_keys ? (size_t)16 * R * sizeof(uint64_t) : 0);
   for (int64_t c0 = 0; c0 < count; c0 += chunk) {
     const int64_t c = std::min(chunk, count - c0);
     const unsigned g = std::min(grid, grid_for(c, 256 / TSIZE));
@@ -500,22 +502,23 @@ tg_status k4_plan(Scratch& S, hipStream_t st, int64_t n, const int32_t* out_off,
 }
 
 // Launches the clique pass over the planned nodes.  Each tier takes a
-// wavefront team per node with LDS rows when they fit in 64 KiB per
-// workgroup, else a workgroup team with LDS rows, else a workgroup team
-// with rows in global scratch.
+// wavefront team per node with LDS rows when they fit in lds_kib KiB per
+// workgroup (at most 64), else a workgroup team with LDS rows, else a
+// workgroup team with rows in global scratch.
 template <bool GLOB>
 tg_status k4_launch(Scratch& S, hipStream_t st, const K4Args& K, const K4Plan& plan, int cus, int grid_big,
-                    GAcc ga) {
+                    int lds_kib, GAcc ga) {
   const int L = K.L;
   const size_t gb = GLOB ? gacc_bytes(ga) : 0;
+  const size_t cap = (size_t)std::max(0, std::min(lds_kib, 64)) << 10;
   auto run = [&](int64_t cnt, const int32_t* list, int dcap) -> tg_status {
     if (cnt <= 0) return TG_OK;
     const size_t l64 = 4 * (size_t)k4_team_lds<64, false>(dcap, L);
     const size_t l256 = (size_t)k4_team_lds<256, false>(dcap, L);
-    if (dcap <= 64 && l64 + gb <= (64u << 10)) {
+    if (dcap <= 64 && l64 + gb <= cap) {
       k_k4_low<64, false, GLOB><<<grid_for(cnt, 4, 8192), 256, l64 + gb, st>>>(K, cnt, list, dcap, nullptr, 0, ga);
       TG_LAUNCHED("k_k4_low<64>");
-    } else if (l256 + gb <= (64u << 10)) {
+    } else if (l256 + gb <= cap) {
       k_k4_low<256, false, GLOB><<<grid_for(cnt, 1, 4096), 256, l256 + gb, st>>>(K, cnt, list, dcap, nullptr, 0, ga);
       TG_LAUNCHED("k_k4_low<256>");
     } else {
@@ -542,9 +545,21 @@ tg_status k4_launch(Scratch& S, hipStream_t st, const K4Args& K, const K4Plan& p
 // global_counts then receives nty vectors of K(L) counts; the work that does
 // not depend on types (degree order, out-lists, 4-cycle groups, 4-clique
 // edge classes) is done once.
+// Sparse per-edge output of tg_count_sparse: nonzero (key, count) pairs of
+// the requested edges, edge q's at [start[q], start[q] + len[q]).
+struct SparseOut {
+  uint32_t* keys = nullptr;
+  uint64_t* counts = nullptr;
+  int64_t* start = nullptr;
+  int32_t* len = nullptr;
+  int64_t cap = 0;
+  int64_t* total = nullptr;  // host
+};
+
 tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const uint8_t* ty, int L,
                      uint64_t* global_counts, uint64_t* edge_counts, int32_t* edge_endpoints,
-                     const tg_options* opt_in, hipStream_t st, bool once = false, int64_t nty = 1) {
+                     const tg_options* opt_in, hipStream_t st, bool once = false, int64_t nty = 1,
+                     const SparseOut* sparse = nullptr) {
   tg_options opt;
   tg_options_default(&opt);
   if (opt_in) opt = *opt_in;
@@ -564,8 +579,13 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   if (n < 0 || nnz < 0 || n >= (1ll << 31) || nnz >= (1ll << 31))
     return fail(TG_ERR_INVALID_ARG, "n and nnz must be in [0, 2^31)");
   if (n * (int64_t)L >= (1ll << 31)) return fail(TG_ERR_INVALID_ARG, "n * L must be below 2^31");
-  if (!rp || (!global_counts && !edge_counts && !opt.edge_orbits) || (nnz > 0 && !ci) || (n > 0 && !ty))
+  if (!rp || (!global_counts && !edge_counts && !opt.edge_orbits && !sparse) || (nnz > 0 && !ci) || (n > 0 && !ty))
     return fail(TG_ERR_INVALID_ARG, "null input or output pointer");
+  if (sparse && L > 8) return fail(TG_ERR_UNSUPPORTED_L, "sparse per-edge output takes L <= 8");
+  if (sparse && (!sparse->start || !sparse->len || !sparse->total || sparse->cap < 0 ||
+                 (sparse->cap > 0 && (!sparse->keys || !sparse->counts))))
+    return fail(TG_ERR_INVALID_ARG, "null sparse output pointer or negative capacity");
+  if (sparse) *sparse->total = 0;
   if (nnz % 2) return fail(TG_ERR_INVALID_GRAPH, "nnz is odd: some edge is stored in one direction only");
   if (opt.schedule < TG_SCHED_NONE || opt.schedule > TG_SCHED_LEARNED)
     return fail(TG_ERR_INVALID_ARG, "unknown schedule");
@@ -710,6 +730,14 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
   }
   TG_LAUNCHED("k_fill_u64");
+  // degree and type of every slot's column node, so that the wedge walks read
+  // them in row order (one type vector only; degrees below 2^28)
+  uint32_t* cdt = nullptr;
+  if (nty == 1 && max_deg < (1ll << 28)) {
+    TG_HIP(S.get(&cdt, nnz));
+    k_slot_dt<<<grid_for(nnz, 256, 16384), 256, 0, st>>>(nnz, ci, W.deg, ty, cdt);
+    TG_LAUNCHED("k_slot_dt");
+  }
   // once: the 4-cycle keys, summed twice per cycle
   const int64_t C3k = per_shape(L, 3), C4k = per_shape(L, 4);
   // key copies of type vector b's 4-cycle sums within `budget` bytes
@@ -720,31 +748,31 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     const GAcc ga_cyc = gacc_cyc(b, 8 << 10);
     if (n_t1 > 0) {
       k_c4_hash<1, 8, uint32_t, true><<<grid_for(n_t1, 4, 4096), 256, gacc_bytes(ga_cyc), st>>>(
-          n_t1, W.nlist + cur[257], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc);
+          n_t1, W.nlist + cur[257], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt);
       TG_LAUNCHED("k_c4_hash<1, glob>");
     }
     if (n_t2 > 0) {
       k_c4_hash<4, 12, uint32_t, true><<<grid_for(n_t2, 1, 2048), 256, gacc_bytes(ga_cyc), st>>>(
-          n_t2, W.nlist + cur[258], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc);
+          n_t2, W.nlist + cur[258], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt);
       TG_LAUNCHED("k_c4_hash<4, glob>");
     }
   }
   if (!once && n_t1 > 0) {
     if (c4_wide)
       k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4w_t, crows, GAcc{});
+                                                                         L, s2x, C4w_t, crows, GAcc{}, cdt);
     else
       k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4n_t, crows, GAcc{});
+                                                                         L, s2x, C4n_t, crows, GAcc{}, cdt);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (!once && n_t2 > 0) {
     if (c4_wide)
       k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4w_t, crows, GAcc{});
+                                                                          ty, L, s2x, C4w_t, crows, GAcc{}, cdt);
     else
       k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4n_t, crows, GAcc{});
+                                                                          ty, L, s2x, C4n_t, crows, GAcc{}, cdt);
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -947,7 +975,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   k_c4_group<PH, T, HF, HS><<<PH == 3 ? grid3 : grid, 256,                                                         \
                               PH == 3 ? gacc_bytes(ga_cyc_g) : ((PH == 1 && STG) ? xu_lds : 0), st>>>(             \
       Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, tyb,   \
-      L, s2x, C4P, crows, STG, ga_cyc_g)
+      L, s2x, C4P, crows, STG, ga_cyc_g, cdt)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
@@ -1018,7 +1046,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     for (int64_t b = 0; plan.ok && b < nty; ++b) {
       const K4Args K{W.deg, ty + b * n, L, W.out_off, W.out_col, nullptr, m, nullptr, nullptr};
       const GAcc ga_k4 = make_gacc(global_counts + b * nkeys(L), 2 * C3k + 5 * C4k, C4k, 16 << 10);
-      if (tg_status s2 = k4_launch<true>(S, st, K, plan, cus, tune.clique_pass_grid, ga_k4)) return s2;
+      if (tg_status s2 = k4_launch<true>(S, st, K, plan, cus, tune.clique_pass_grid, tune.clique_pass_lds_kib,
+                                         ga_k4))
+        return s2;
     }
     k4_glob_done = plan.ok;
   }
@@ -1047,7 +1077,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
         K.K4n = K4n;
       }
       TG_LAUNCHED("k_fill");
-      if (tg_status s2 = k4_launch<false>(S, st, K, plan, cus, tune.clique_pass_grid, GAcc{})) return s2;
+      if (tg_status s2 = k4_launch<false>(S, st, K, plan, cus, tune.clique_pass_grid, tune.clique_pass_lds_kib,
+                                          GAcc{}))
+        return s2;
     }
   }
 
@@ -1159,6 +1191,24 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.K4n = K4n;
   A.K4w = K4w;
   A.m = m;
+  A.sp_keys = nullptr;
+  A.sp_counts = nullptr;
+  A.sp_start = nullptr;
+  A.sp_len = nullptr;
+  A.sp_cursor = nullptr;
+  A.sp_cap = 0;
+  if (sparse) {
+    TG_HIP(S.get(&A.sp_cursor, 1));
+    k_fill_u64<<<1, 64, 0, st>>>(reinterpret_cast<uint64_t*>(A.sp_cursor), 1, 0);
+    TG_LAUNCHED("k_fill_u64");
+    // the keys pointer also switches the row kernel to sparse output; with
+    // no capacity it points at a dummy word that is never written
+    A.sp_keys = sparse->keys ? sparse->keys : reinterpret_cast<uint32_t*>(A.sp_cursor);
+    A.sp_counts = sparse->counts;
+    A.sp_start = sparse->start;
+    A.sp_len = sparse->len;
+    A.sp_cap = sparse->cap;
+  }
   const bool probe = !K4n && !K4w;
   // gathered accumulators of one batch of edges (reused by every class and
   // batch: all launches are ordered on st)
@@ -1202,6 +1252,15 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     if (hf) return fail(TG_ERR_INTERNAL, "a global sum is not a multiple of its shape's edge count");
   }
   timer.finish();
+  if (sparse) {
+    uint64_t tot = 0;
+    TG_HIP(hipMemcpyAsync(&tot, A.sp_cursor, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    TG_HIP(hipStreamSynchronize(st));
+    *sparse->total = (int64_t)tot;
+    if ((int64_t)tot > sparse->cap)
+      return fail(TG_ERR_INVALID_ARG, "sparse capacity " + std::to_string(sparse->cap) + " is below the " +
+                                          std::to_string(tot) + " nonzero pairs (reported in *total)");
+  }
   return TG_OK;
 }
 
@@ -1550,6 +1609,12 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.K4n = nullptr;
   A.K4w = nullptr;
   A.m = m;
+  A.sp_keys = nullptr;
+  A.sp_counts = nullptr;
+  A.sp_start = nullptr;
+  A.sp_len = nullptr;
+  A.sp_cursor = nullptr;
+  A.sp_cap = 0;
   const unsigned grid = grid_for(count, 1, 1024);
   int32_t* t_over = nullptr;
   int64_t t_cap = 0;
@@ -1751,6 +1816,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->tlist_budget_mib = 16384;
   t->clique_pass = 1;
   t->clique_pass_grid = 0;
+  t->clique_pass_lds_kib = 64;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
@@ -1895,6 +1961,31 @@ tg_status tg_count(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t
   try {
     return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, edge_counts, edge_endpoints, opt,
                       stream);
+  } catch (const std::exception& ex) {
+    return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
+  } catch (...) {
+    return fail(TG_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+tg_status tg_count_sparse(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                          const uint8_t* node_types, int L, uint64_t* global_counts, int64_t capacity,
+                          uint32_t* keys, uint64_t* counts, int64_t* edge_start, int32_t* edge_len,
+                          int64_t* total, const tg_options* opt, hipStream_t stream) {
+  try {
+    SparseOut sp;
+    sp.keys = keys;
+    sp.counts = counts;
+    sp.start = edge_start;
+    sp.len = edge_len;
+    sp.cap = capacity;
+    sp.total = total;
+    tg_options o;
+    tg_options_default(&o);
+    if (opt) o = *opt;
+    o.edge_orbits = nullptr;
+    return count_impl(n, nnz, row_ptr, col_idx, node_types, L, global_counts, nullptr, nullptr, &o, stream, false,
+                      1, &sp);
   } catch (const std::exception& ex) {
     return fail(TG_ERR_INTERNAL, std::string("exception: ") + ex.what());
   } catch (...) {

@@ -106,8 +106,10 @@ __device__ __forceinline__ int32_t k4_scan(int32_t v, int32_t* total, int32_t* s
 
 // Bytes of LDS per team.
 //   ids[dcap] i32, pos[dcap] i32, tq[dcap] u8, tstart/fill 2 x 17 i32,
-//   scan 4 + 3 * TSIZE i32 (workgroup teams), rows dcap * NW u64 and
-//   acc dcap * P u32 (when not GSCR)
+//   scan 4 + 3 * TSIZE i32 (workgroup teams), then rows dcap * NW u64 and
+//   acc dcap * P u32 (LDS teams), or (GSCR) the position -> index map
+//   qpos[dcap] i32, the type by position ptype[dcap] u8 and one P-counter
+//   accumulator per wavefront
 template <int TSIZE, bool GSCR>
 __host__ __device__ inline int k4_team_lds(int dcap, int L) {
   const int P = L * (L + 1) / 2, NW = (dcap + 63) / 64;
@@ -117,13 +119,15 @@ __host__ __device__ inline int k4_team_lds(int dcap, int L) {
   if (TSIZE > TG_WAVE) b += 4 * (4 + 3 * TSIZE);
   b = (b + 7) & ~7;
   if (!GSCR) b += 8 * dcap * NW + 4 * dcap * P;
+  else b += ((5 * dcap + 3) & ~3) + 4 * (TSIZE / TG_WAVE) * P;
   return (b + 15) & ~15;
 }
 
-// Global scratch bytes per workgroup for GSCR teams (rows, accumulators).
+// Global scratch bytes per workgroup for GSCR teams (the bit rows).
 __host__ __device__ inline int64_t k4_gscr_bytes(int dcap, int L) {
-  const int64_t P = L * (L + 1) / 2, NW = (dcap + 63) / 64;
-  const int64_t b = 8 * (int64_t)dcap * NW + 4 * (int64_t)dcap * P;
+  const int64_t NW = (dcap + 63) / 64;
+  const int64_t b = 8 * (int64_t)dcap * NW;
+  (void)L;
   return (b + 255) & ~(int64_t)255;
 }
 
@@ -150,11 +154,15 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
   char* after = reinterpret_cast<char*>(scan) + (TSIZE > TG_WAVE ? 4 * (4 + 3 * TSIZE) : 0);
   after = reinterpret_cast<char*>(((uintptr_t)after + 7) & ~(uintptr_t)7);
   uint64_t* rows;
-  uint32_t* acc;
+  uint32_t* acc = nullptr;
+  int32_t* qpos = nullptr;
+  uint8_t* ptype = nullptr;
+  uint32_t* accw = nullptr;
   if (GSCR) {
-    char* g = gscr + (int64_t)blockIdx.x * gscr_stride;
-    rows = reinterpret_cast<uint64_t*>(g);
-    acc = reinterpret_cast<uint32_t*>(g + 8 * (int64_t)dcap * NW);
+    rows = reinterpret_cast<uint64_t*>(gscr + (int64_t)blockIdx.x * gscr_stride);
+    qpos = reinterpret_cast<int32_t*>(after);
+    ptype = reinterpret_cast<uint8_t*>(qpos + dcap);
+    accw = reinterpret_cast<uint32_t*>(after + ((5 * dcap + 3) & ~3)) + (tid / TG_WAVE) * P;
   } else {
     rows = reinterpret_cast<uint64_t*>(after);
     acc = reinterpret_cast<uint32_t*>(after + 8 * dcap * NW);
@@ -190,11 +198,16 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
     k4_sync<TSIZE>();
     for (int32_t q = tid; q < D; q += TSIZE) {
       const int t = tq[q];
-      pos[q] = tstart[t] + atomicAdd(&fill[t], 1);
+      const int32_t pq = tstart[t] + atomicAdd(&fill[t], 1);
+      pos[q] = pq;
+      if (GSCR) {
+        qpos[pq] = q;
+        ptype[pq] = (uint8_t)t;
+      }
     }
     // clear rows and accumulators
     for (int64_t x = tid; x < (int64_t)D * NW; x += TSIZE) rows[x] = 0;
-    if (!GLOB)
+    if (!GLOB && !GSCR)
       for (int64_t x = tid; x < (int64_t)D * P; x += TSIZE) acc[x] = 0;
     k4_sync<TSIZE>();
     const int NWa = (D + 63) / 64;  // words per row for this node
@@ -260,21 +273,62 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
               continue;
             }
             k4_credit(A, pair_index(phia, u), e_bc, nv);
-            atomicAdd(&acc[(int64_t)pb * P + pair_index(tc, u)], nv);
-            atomicAdd(&acc[(int64_t)pc * P + pair_index(tb, u)], nv);
+            if (!GSCR) {
+              atomicAdd(&acc[(int64_t)pb * P + pair_index(tc, u)], nv);
+              atomicAdd(&acc[(int64_t)pc * P + pair_index(tb, u)], nv);
+            }
           }
         }
         if (TSIZE > TG_WAVE) __syncthreads();
       }
       k4_sync<TSIZE>();
     }
-    // ---- flush the edges at a (sums are twice the counts)
-    if (!GLOB) {
+    // ---- the edges at a (sums are twice the counts)
+    if (!GLOB && !GSCR) {
       for (int64_t x = tid; x < (int64_t)D * P; x += TSIZE) {
         const int32_t q = (int32_t)(x / P);
         const int p = (int)(x - (int64_t)q * P);
-        const uint32_t v = k4_load32<GSCR>(&acc[(int64_t)pos[q] * P + p]);
+        const uint32_t v = acc[(int64_t)pos[q] * P + p];
         if (v) k4_credit(A, p, A.out_eid[oa + q], v >> 1);
+      }
+    }
+    if (!GLOB && GSCR) {
+      // rows in global memory: instead of two global atomics per G_a edge,
+      // each wavefront takes whole rows b and sums, over every neighbour c
+      // of b in G_a, the typed popcounts of row(b) & row(c) in its own LDS
+      // counters, then credits edge (a, b) once per type pair
+      const int wv = tid / TG_WAVE, ln = lane();
+      for (int32_t pb = wv; pb < D; pb += TSIZE / TG_WAVE) {
+        for (int p = ln; p < P; p += TG_WAVE) accw[p] = 0u;
+        wave_sync();
+        const uint64_t* rb = rows + (int64_t)pb * NW;
+        for (int32_t k = ln; k < NWa; k += TG_WAVE) {
+          uint64_t bits = k4_load64<true>(rb + k);
+          while (bits) {
+            const int32_t pc = (k << 6) + __builtin_ctzll(bits);
+            bits &= bits - 1ull;
+            const uint64_t* rc = rows + (int64_t)pc * NW;
+            const int tc = ptype[pc];
+            for (int u = 0; u < L; ++u) {
+              const int32_t s0 = tstart[u], s1 = tstart[u + 1];
+              if (s0 >= s1) continue;
+              uint32_t nv = 0;
+              for (int32_t w = s0 >> 6; w <= (s1 - 1) >> 6; ++w) {
+                const int32_t b0 = max(s0 - (w << 6), 0), b1 = min(s1 - (w << 6), 64);
+                const uint64_t msk = (b1 >= 64 ? ~0ull : ((1ull << b1) - 1ull)) & ~((1ull << b0) - 1ull);
+                nv += (uint32_t)__popcll(k4_load64<true>(rb + w) & k4_load64<true>(rc + w) & msk);
+              }
+              if (nv) atomicAdd(&accw[pair_index(tc, u)], nv);
+            }
+          }
+        }
+        wave_sync();
+        const int32_t e_ab = A.out_eid[oa + qpos[pb]];
+        for (int p = ln; p < P; p += TG_WAVE) {
+          const uint32_t v = accw[p];
+          if (v) k4_credit(A, p, e_ab, v >> 1);
+        }
+        wave_sync();
       }
     }
     k4_sync<TSIZE>();

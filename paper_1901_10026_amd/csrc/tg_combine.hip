@@ -356,7 +356,8 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
 // shorter row).  One team of TSIZE lanes per edge.
 template <int TSIZE, class AccT>
 __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const AccT* __restrict__ ea,
-                                          uint64_t* gacc, int tid) {
+                                          uint64_t* gacc, int tid, uint64_t* stage = nullptr,
+                                          int64_t* opos_out = nullptr) {
   const int L = A.L, LL = L * L, P = L * (L + 1) / 2;
   const int R = 2 * L + 6 * P;
   const int32_t i = A.ei[e], j = A.ej[e];
@@ -378,7 +379,7 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
   const uint64_t* Pj = A.Pn + (int64_t)j * LL;
   // output position of this edge (listed ids or range), -1 if none
   int64_t opos = -1;
-  if (A.edge_counts || A.edge_orbits) {
+  if (A.edge_counts || A.edge_orbits || A.sp_keys) {
     if (A.edge_ids) {
       int64_t lo = 0, hi = A.n_edge_ids;  // first id >= e
       while (lo < hi) {
@@ -391,6 +392,8 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
     }
   }
   uint64_t* row = (A.edge_counts && opos >= 0) ? A.edge_counts + opos * R : nullptr;
+  if (stage && opos >= 0) row = stage;  // sparse output: the row is staged, then emitted
+  if (opos_out) *opos_out = opos;
   // orbit row: g1[t], g2[t], then g3..g12 in blocks of P
   uint64_t* orow = (A.edge_orbits && opos >= 0) ? A.edge_orbits + opos * (2 * L + 10 * P) : nullptr;
   auto gadd = [&](int64_t key, int64_t v) {
@@ -551,6 +554,53 @@ inline size_t combine_lds_bytes(int L) {
   return (size_t)(256 / TSIZE) * region;
 }
 
+// Nonzero (global key, count) pairs of one row staged in LDS, in column
+// order: columns are taken TS at a time, one per lane, and the nonzero ones
+// are packed by a ballot; the edge's pairs go at a cursor reserved once per
+// edge.
+template <int TS>
+__device__ __forceinline__ void sparse_emit(const EdgeArgs& A, int32_t e, int64_t opos, const uint64_t* stage,
+                                            int R, int tid) {
+  const int L = A.L, P = L * (L + 1) / 2;
+  wave_sync();  // the staged row was written by the other lanes of the team
+  int32_t nz = 0;
+  for (int c0 = 0; c0 < R; c0 += TS) {
+    const bool on = c0 + tid < R && stage[c0 + tid] != 0;
+    nz += __popcll(team_bits<TS>(ballot(on)));
+  }
+  int64_t base = 0;
+  if (tid == 0) base = (int64_t)atomicAdd(A.sp_cursor, (unsigned long long)nz);
+  base = __shfl(base, (lane() / TS) * TS, TG_WAVE);
+  if (tid == 0) {
+    A.sp_start[opos] = base;
+    A.sp_len[opos] = nz;
+  }
+  if (base + nz > A.sp_cap) return;  // counted, not written: the caller sees the total
+  const int pi = A.ty[A.ei[e]], pj = A.ty[A.ej[e]];
+  int64_t at = base;
+  for (int c0 = 0; c0 < R; c0 += TS) {
+    const int c = c0 + tid;
+    const uint64_t v = c < R ? stage[c] : 0ull;
+    const uint64_t mask = team_bits<TS>(ballot(v != 0));
+    if (v) {
+      int64_t key;
+      if (c < 2 * L) {
+        key = key_of(L, c / L, pi, pj, c % L, 0);
+      } else {
+        const int h = (c - 2 * L) / P, p = (c - 2 * L) % P;
+        int u = 0;
+        while ((u + 1) * (u + 2) / 2 <= p) ++u;
+        key = key_of(L, 2 + h, pi, pj, p - u * (u + 1) / 2, u);
+      }
+      const int64_t q = at + __popcll(mask & bits_below(tid));
+      A.sp_keys[q] = (uint32_t)key;
+      A.sp_counts[q] = v;
+    }
+    at += __popcll(mask);
+  }
+  wave_sync();  // the stage is rewritten by the team's next edge
+}
+
 // Row kernel: one 16-lane team per edge of list[0, count), accumulators
 // from ea (as written by the gather kernel over the same list); global key
 // sums are gathered in LDS first when gacc_in_lds.
@@ -565,8 +615,15 @@ __global__ void __launch_bounds__(256) k_combine_rows(EdgeArgs A, int64_t count,
     for (int x = threadIdx.x; x < nkeys; x += blockDim.x) gacc[x] = 0;
   __syncthreads();
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS)
-    edge_rows<TS, AccT>(A, list[w], ea + w * 4 * LL, gacc, tid);
+  const int P = A.L * (A.L + 1) / 2, R = 2 * A.L + 6 * P;
+  // sparse output: each team's row staged in LDS after the key sums
+  uint64_t* stage = A.sp_keys ? smem_rows + (A.gacc_in_lds ? nkeys : 0) + team * R : nullptr;
+  for (int64_t w = (int64_t)blockIdx.x * TEAMS + team; w < count; w += (int64_t)gridDim.x * TEAMS) {
+    const int32_t e = list[w];
+    int64_t opos = -1;
+    edge_rows<TS, AccT>(A, e, ea + w * 4 * LL, gacc, tid, stage, &opos);
+    if (stage && opos >= 0) sparse_emit<TS>(A, e, opos, stage, R, tid);
+  }
   __syncthreads();
   if (gacc)
     for (int x = threadIdx.x; x < nkeys; x += blockDim.x)

@@ -102,6 +102,17 @@ struct EdgeArgs {
   const uint32_t* K4n;
   const uint64_t* K4w;
   int64_t m;
+  // sparse per-edge output (instead of dense rows, L <= 8): each team of
+  // the row kernel stages its edge's row in LDS and appends the nonzero
+  // (key, count) pairs at an atomic cursor; sp_start[q] and sp_len[q] give
+  // edge q's pairs; pairs past sp_cap are not written (the cursor still
+  // counts them).  sp_keys null: dense rows as usual.
+  uint32_t* sp_keys;
+  uint64_t* sp_counts;
+  int64_t* sp_start;
+  int32_t* sp_len;
+  unsigned long long* sp_cursor;
+  int64_t sp_cap;
 };
 
 // Global key sums of one kernel: keys [k0, k0 + nk) are summed in `copies`

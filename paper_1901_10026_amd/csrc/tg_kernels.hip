@@ -448,7 +448,8 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
                                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  int L, const int32_t* __restrict__ s2e,
-                                                 C4T* __restrict__ C4, int64_t crows, GAcc ga) {
+                                                 C4T* __restrict__ C4, int64_t crows, GAcc ga,
+                                                 const uint32_t* __restrict__ cdt) {
   extern __shared__ uint64_t hash_gacc[];
   if (GLOB) gacc_init(ga, hash_gacc);
   constexpr int CAP = 1 << LOG2CAP;
@@ -481,7 +482,10 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
         for (int32_t b0 = 0; b0 < du; b0 += TG_WAVE) {
           if (b0 + ln >= du) continue;
           const int32_t w = ci[bu + b0 + ln];
-          if (!precedes(deg[w], w, dx, x)) continue;
+          // degree and type of w: packed per slot when cdt is given (read in
+          // row order), else gathered by node id
+          const uint32_t dtw = cdt ? cdt[bu + b0 + ln] : 0u;
+          if (!precedes(cdt ? (int32_t)(dtw >> 4) : deg[w], w, dx, x)) continue;
           if (pass == 0) {
             const int h = hash_insert(kw, LOG2CAP, w);
             atomicAdd(&tw[h], 1u);
@@ -492,7 +496,7 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
             if (tw[h] < 2) continue;
             const int32_t e_xu = s2e ? s2e[bx + q] : bx + q;
             const int32_t e_uw = s2e ? s2e[bu + b0 + ln] : bu + b0 + ln;
-            const int phw = ty[w];
+            const int phw = cdt ? (int)(dtw & 15u) : ty[w];
             for (int t = 0; t < L; ++t) {
               const int g = hash_find(kt, LOG2CAP, w * L + t);
               if (GLOB) {
@@ -611,7 +615,8 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
                                                   const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
-                                                  int64_t crows, int stage_xu, GAcc ga) {
+                                                  int64_t crows, int stage_xu, GAcc ga,
+                                                  const uint32_t* __restrict__ cdt) {
   // credits to the edges (x, u) of the window's 64 slots are summed in LDS
   // first (stage_xu: L <= 8 and every sum fits 32 bits); dynamic LDS of
   // 4 * 64 * P words in phase 1 with stage_xu, the key copies of ga in
@@ -700,9 +705,16 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         sv[k] = o_bu + o_off + (v - o_excl);
         wv[k] = ok[k] ? ci[sv[k]] : 0;
       }
+      // degree and type of w: packed per slot when cdt is given (read in row
+      // order, next to the ids), else gathered by node id
       int32_t dw[U];
+      int tw[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) dw[k] = ok[k] ? deg[wv[k]] : 0;
+      for (int k = 0; k < U; ++k) {
+        const uint32_t dt = (ok[k] && cdt) ? cdt[sv[k]] : 0u;
+        dw[k] = ok[k] ? (cdt ? (int32_t)(dt >> 4) : deg[wv[k]]) : 0;
+        tw[k] = (int)(dt & 15u);
+      }
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int o = ov[k];
@@ -757,7 +769,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
           }
           for (int t = 0; t < L; ++t) sum += c[t];
           if (sum < 2) continue;
-          const int phw = ty[w];
+          const int phw = cdt ? tw[k] : ty[w];
           if (PHASE == 3) {
             for (int t = 0; t < L; ++t) {
               const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
@@ -793,6 +805,17 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
   }
   }
   if (PHASE == 3) gacc_flush(ga, gsm);
+}
+
+// Degree and type of every slot's column node, packed as deg << 4 | type
+// (degrees below 2^28, types below 16), so that wedge walks read them in row
+// order instead of gathering them by node id.
+__global__ void k_slot_dt(int64_t nnz, const int32_t* __restrict__ ci, const int32_t* __restrict__ deg,
+                          const uint8_t* __restrict__ ty, uint32_t* __restrict__ cdt) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nnz; s += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t w = ci[s];
+    cdt[s] = ((uint32_t)deg[w] << 4) | (uint32_t)ty[w];
+  }
 }
 
 // Per-edge 4-cycle rows (edge-major, P per edge) from type-pair-major

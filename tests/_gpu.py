@@ -34,5 +34,17 @@ def gpu_count(row_ptr, col_idx, types, L, per_edge=True, **kw):
 
 
 def note(msg):
+    """Progress line: printed, and appended to gpurun_out/gpu_tests.log under
+    the repository root, so that a long GPU test is seen to progress even
+    while pytest captures its output."""
     print(msg, flush=True)
     sys.stdout.flush()
+    try:
+        import os
+        import time
+        out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "gpu_tests.log"), "a") as f:
+            f.write(f"{time.strftime('%H:%M:%S')} {msg}\n")
+    except OSError:
+        pass

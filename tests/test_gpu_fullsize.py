@@ -129,7 +129,8 @@ def test_clique_pass_equals_out_list_probes_at_full_size(big):
 
     import paper_1901_10026_amd as tg
     g, rp, ci, ty, glob, rows = big
-    for d in ({"clique_pass": 0}, {"clique_pass": 1, "clique_pass_grid": 7}):
+    for d in ({"clique_pass": 0}, {"clique_pass": 1, "clique_pass_grid": 7},
+              {"clique_pass_lds_kib": 0, "clique_pass_grid": 300}, {"clique_pass_lds_kib": 40}):
         g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=tg.Tuning.from_dict(d))
         torch.cuda.synchronize()
         note(f"tuning {d}: same rows")

@@ -40,10 +40,12 @@ def test_giant_sampled_rows():
     import torch
 
     import paper_1901_10026_amd as tg
+    note("cl-20m: generating")
     g = graphgen.workload("cl-20m")
     d = np.diff(g.row_ptr).astype(np.int64)
     note(f"cl-20m n={g.n} m={g.m} L={g.L} max_deg={d.max()}")
     ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    note("cl-20m: canonical edges listed")
     cs = np.concatenate([[0], np.cumsum(d[g.col_idx])])
     s = cs[g.row_ptr[1:]] - cs[g.row_ptr[:-1]]  # neighbour degree sums
     del cs
@@ -53,6 +55,7 @@ def test_giant_sampled_rows():
          f"largest oracle cost {(s[ei[ids]] + s[ej[ids]]).max():.3e}")
     rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
     dev_ids = torch.from_numpy(ids).to(rp.device)
+    note("cl-20m: counting the sampled rows (the 4-cycle pass covers the whole graph)")
     ph = {}
     glob, rows, ends = tg.count(rp, ci, ty, g.L, per_edge=True, edge_ids=dev_ids, global_counts=False,
                                 endpoints=True, phase_ms=ph)
@@ -63,6 +66,7 @@ def test_giant_sampled_rows():
     ends = ends.cpu().numpy()
     assert np.array_equal(ends[:, 0], ei[ids]) and np.array_equal(ends[:, 1], ej[ids])
     got = rows.cpu().numpy().view(np.uint64)
+    note("cl-20m: oracle on the sampled edges")
     want, _ = oracle.count_edges(g.row_ptr, g.col_idx, g.types, g.L, ei[ids], ej[ids], nthreads=16)
     bad = np.nonzero((got != want).any(axis=1))[0]
     assert len(bad) == 0, f"{len(bad)} of {len(ids)} sampled rows differ, first edge {ids[bad[0]]}"

@@ -143,7 +143,7 @@ def test_full_size_equals_per_edge_path():
     assert torch.equal(got2.view(torch.int64), want.view(torch.int64))
     # 4-cliques from the edge classes instead of the clique pass, and the
     # pass with few workgroups for its global-scratch tier
-    for d in ({"clique_pass": 0}, {"clique_pass_grid": 5}):
+    for d in ({"clique_pass": 0}, {"clique_pass_grid": 5}, {"clique_pass_lds_kib": 0, "clique_pass_grid": 200}):
         got3 = tg.count_global(rp, ci, ty, g.L, tuning=tg.Tuning.from_dict(d))
         torch.cuda.synchronize()
         assert torch.equal(got3.view(torch.int64), want.view(torch.int64)), d

@@ -115,3 +115,71 @@ def test_sparse_rows_of_an_edgeless_graph():
     torch.cuda.synchronize()
     assert rows.shape == (0, tg.edge_row_width(2))
     assert off.cpu().tolist() == [0] and keys.numel() == 0 and cnts.numel() == 0
+
+
+def _sparse_of_rows(rows, ei, ej, ty, L):
+    """Per edge, the oracle row's nonzero entries as (global key, count) in
+    column order."""
+    out = []
+    for q in range(len(rows)):
+        cols = np.nonzero(rows[q])[0]
+        out.append([(oracle.row_key(L, int(ty[ei[q]]), int(ty[ej[q]]), int(c)), int(rows[q, c])) for c in cols])
+    return out
+
+
+def _pairs(keys, counts, start, length):
+    keys = keys.cpu().numpy().view(np.uint32)
+    counts = counts.cpu().numpy().view(np.uint64)
+    start, length = start.cpu().numpy(), length.cpu().numpy()
+    return [list(zip(keys[s:s + n].astype(int).tolist(), counts[s:s + n].astype(int).tolist()))
+            for s, n in zip(start, length)]
+
+
+def test_sparse_output_straight_from_the_row_kernel():
+    """tg_count_sparse on the 2000-node graph: every edge's pairs are the
+    oracle row's nonzero entries (keys through the oracle's key map), the
+    global counts equal tg_count's, and a range and an id list give the same
+    pairs as the full call."""
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    glob, keys, counts, start, length = tg.count_sparse(rp, ci, ty, g.L)
+    torch.cuda.synchronize()
+    ei, ej = oracle.canonical_edges(g.row_ptr, g.col_idx)
+    want_rows, want_glob = oracle.count_all(g.row_ptr, g.col_idx, g.types, g.L, nthreads=8)
+    want = _sparse_of_rows(want_rows, ei, ej, g.types, g.L)
+    got = _pairs(keys, counts, start, length)
+    assert got == want
+    assert np.array_equal(glob.cpu().numpy().view(np.uint64), want_glob)
+    s = start.cpu().numpy()
+    ln = length.cpu().numpy()
+    spans = sorted(zip(s.tolist(), (s + ln).tolist()))
+    assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:])) and spans[-1][1] == keys.numel()
+    g2, k2, c2, s2, l2 = tg.count_sparse(rp, ci, ty, g.L, edge_range=(500, 2500), global_counts=False)
+    assert g2 is None and _pairs(k2, c2, s2, l2) == want[500:2500]
+    ids = np.arange(7, g.m, 29, dtype=np.int64)
+    _, k3, c3, s3, l3 = tg.count_sparse(rp, ci, ty, g.L, edge_ids=torch.from_numpy(ids).to(rp.device))
+    assert _pairs(k3, c3, s3, l3) == [want[q] for q in ids]
+
+
+def test_sparse_output_capacity_and_limits():
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g = graphgen.chung_lu_small()
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    _, keys, _, _, _ = tg.count_sparse(rp, ci, ty, g.L, edge_range=(0, 300))
+    need = keys.numel()
+    with pytest.raises(tg.TGError) as ex:
+        tg.count_sparse(rp, ci, ty, g.L, edge_range=(0, 300), capacity=need - 1)
+    assert ex.value.name == "TG_ERR_INVALID_ARG" and str(need) in str(ex.value)
+    # pairs of different edges land in any order: compare them edge by edge
+    _, k0, c0, s0, l0 = tg.count_sparse(rp, ci, ty, g.L, edge_range=(0, 300), capacity=need)
+    _, k1, c1, s1, l1 = tg.count_sparse(rp, ci, ty, g.L, edge_range=(0, 300))
+    assert k0.numel() == need and _pairs(k0, c0, s0, l0) == _pairs(k1, c1, s1, l1)
+    rp2, ci2 = graphgen.gnp(30, 0.3, 5)
+    with pytest.raises(tg.TGError) as ex:
+        tg.count_sparse(*to_dev(rp2, ci2, np.zeros(30, np.uint8)), 9)
+    assert ex.value.name == "TG_ERR_UNSUPPORTED_L"

@@ -131,7 +131,7 @@ def test_rows_only_counting():
     assert g3 is None and np.array_equal(r3, rr[100:1500])
 
 
-@pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5)])
+@pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5), (420, 8)])
 def test_complete_graphs_hit_heavy_paths(n, L):
     # |T_ij| = n - 2 exceeds one wavefront's capacity for n >= 131, and the
     # highest-ranked nodes carry enough wedges for the grouped dense path.
@@ -230,6 +230,24 @@ def test_validation_reports_bad_graphs(case, status):
     with pytest.raises(tg.TGError) as e:
         gpu_count(rp, ci, ty, 2, validate=True)
     assert e.value.name == status, str(e.value)
+
+
+def test_clique_pass_tiers_on_a_dense_graph():
+    """G(450, 0.75), L = 8: the lowest nodes have up to ~330 higher
+    neighbours; every clique-pass tier (wavefront, workgroup LDS rows, global
+    rows by LDS limit) and the out-list probes give the oracle's rows."""
+    import paper_1901_10026_amd as tg
+    rp, ci = graphgen.gnp(450, 0.75, 31)
+    ty = graphgen.types_uniform(450, 8, 31)
+    ei, ej = oracle.canonical_edges(rp, ci)
+    sample = np.linspace(0, len(ei) - 1, 60).astype(np.int64)
+    want_rows, _ = oracle.count_edges(rp, ci, ty, 8, ei[sample], ej[sample], nthreads=8)
+    base_g, base_r, _ = gpu_count(rp, ci, ty, 8)
+    assert np.array_equal(base_r[sample], want_rows)
+    for d in ({"clique_pass": 0}, {"clique_pass_lds_kib": 0}, {"clique_pass_lds_kib": 16, "clique_pass_grid": 3}):
+        gg, rr, _ = gpu_count(rp, ci, ty, 8, tuning=tg.Tuning.from_dict(d))
+        note(f"G(450, 0.75) with {d}")
+        assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
 
 def test_release_scratch_between_calls():
