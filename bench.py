@@ -499,7 +499,7 @@ def directed4_leg(tg, dev, steps=3):
             "nonzero_keys": int(glob.view(torch.int64).ne(0).sum().item())}
 
 
-def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1):
+def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1, learned=True):
     """The 20M-node skewed graph (300M edges, L = 8) through the whole
     per-edge path: one tg_count over every edge, with global counts from the
     per-edge sums (Eq. 17) and per-edge rows for the first `rows_edges`
@@ -550,6 +550,8 @@ def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1):
         res["degree"] = {"ms": ms, "phase_ms": ph}
     res["degree"]["ms_runs"] = runs
     tg.release_scratch()
+    if not learned:
+        return res
     model = tg.CostModel(seed=57)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -716,6 +718,8 @@ def main():
     ap.add_argument("--giant-repeats", type=int, default=1, help="degree-schedule calls of the 20M-node leg")
     ap.add_argument("--giant-only", action="store_true",
                     help="only run the 20M-node per-edge leg and print its object (for profiling)")
+    ap.add_argument("--giant-degree-only", action="store_true",
+                    help="with --giant-only: the degree schedule only")
     ap.add_argument("--permutations", type=int, default=100, help="permutations of the null-model leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -752,7 +756,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.giant_only:
         # the 20M-node per-edge leg alone (for profiling it), as its own line
-        print(json.dumps({"giant_per_edge": giant_per_edge_leg(tg, dev, repeats=args.giant_repeats)}), flush=True)
+        print(json.dumps({"giant_per_edge": giant_per_edge_leg(tg, dev, repeats=args.giant_repeats,
+                                                               learned=not args.giant_degree_only)}), flush=True)
         return
     t0 = time.time()
     g = graphgen.workload(args.workload)
