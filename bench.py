@@ -32,12 +32,13 @@ def log(msg):
 # code of tg_count's kernels and their helpers (the host launch code in
 # tg_api.hip is not hashed).
 _KERNEL_SOURCES = ("paper_1901_10026_amd/csrc/tg_combine.hip", "paper_1901_10026_amd/csrc/tg_clique.hip",
-                   "paper_1901_10026_amd/csrc/tg_kernels.hip", "paper_1901_10026_amd/csrc/tg_device.h",
-                   "paper_1901_10026_amd/csrc/tg_internal.h")
+                   "paper_1901_10026_amd/csrc/tg_c4part.hip", "paper_1901_10026_amd/csrc/tg_kernels.hip",
+                   "paper_1901_10026_amd/csrc/tg_device.h", "paper_1901_10026_amd/csrc/tg_internal.h")
 _TRAFFIC_FILE = "profiles/tg_count_cl-1m_l2_traffic.txt"
 # kernels of each timed phase of tg_count (rocprofv3 kernel-name prefixes)
 PHASE_KERNELS = {
-    "cycles": ("k_c4_hash", "k_c4_group", "k_c4_slot_wedges", "k_c4_fold", "k_fill_u32", "k_fill_u64"),
+    "cycles": ("k_c4_hash", "k_c4_group", "k_c4_bwalk", "k_c4_bcount", "k_c4_slot_wedges", "k_c4_fold", "k_fill_u32",
+               "k_fill_u64"),
     "cliques": ("k_k4_low", "k_k4_tier", "k_k4_zero", "k_max_tsum_all"),
     "combine": ("k_combine",),
 }

@@ -129,6 +129,14 @@ typedef struct {
                                  with a slice of its own (0 = two per compute unit) */
   int32_t clique_pass_lds_kib;/* tg_count: a tier of the clique pass keeps its bit rows in LDS when they
                                  fit in this many KiB per workgroup, else in global scratch */
+  int32_t c4_parts;           /* tg_count: 1 = the dense groups of the 4-cycle pass take their middle
+                                 counts from records bucketed by far-end id range and summed in LDS
+                                 instead of from global atomics (L <= 8, maximum degree below 65536,
+                                 one slice); 0 = never */
+  int32_t c4_part_lds_kib;    /* tg_count: LDS per workgroup of the range table, capped by the device's
+                                 limit */
+  int32_t c4_part_chunk;      /* tg_count: wedges per walk item of that pass (256 to 32768) */
+  int32_t c4_part_hash_ratio; /* tg_count: c4_hash_ratio in effect when that pass is on */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */

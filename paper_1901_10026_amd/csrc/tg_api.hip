@@ -818,7 +818,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       while ((1ll << lg) < want) ++lg;
       return lg;
     };
-    const int hash_ratio = std::max(0, tune.c4_hash_ratio);
+    // the bucketed counts of dense groups (below) shift the balance towards
+    // hash tables for the lighter nodes: their own ratio applies then
+    const bool parts_ok = !once && tune.c4_parts != 0 && cdt && half && L <= 8 && tune.c4_slices <= 1 && nty == 1;
+    const int hash_ratio = std::max(0, parts_ok ? tune.c4_part_hash_ratio : tune.c4_hash_ratio);
     int64_t qd = n_t3;  // nodes [0, qd) dense, [qd, n_t3) hashed
     if (hash_ratio > 0) {
       qd = 0;
@@ -901,10 +904,68 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     TG_HIP(S.get(&d_wp, nslots + 1));
     TG_HIP(hipMemcpyAsync(d_gx, gx.data(), n_t3 * sizeof(int32_t), hipMemcpyHostToDevice, st));
     TG_HIP(hipMemcpyAsync(d_hs, hs.data(), (n_t3 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // Dense groups may take their middle counts from records bucketed by
+    // far-end id range and summed in LDS (k_c4_bwalk, k_c4_bcount) instead of
+    // from global atomics; every row of a node's dense array is then written,
+    // so the array needs no clearing.
+    bool use_parts = false;
+    int64_t partR = 0, partK = 0;
+    size_t bw_lds = 0, bc_lds = 0;
+    const int part_rw = (L + 1) / 2;
+    const int CHW = std::max(256, std::min(32768, tune.c4_part_chunk));
+    std::vector<int64_t> gwalk(ngroups + 1, 0);  // walk items of each group (a prefix)
+    std::vector<int64_t> gnit(ngroups + 1, 0);   // each group's per-node item starts in d_nit
+    int32_t* d_nit = nullptr;
+    uint32_t* d_region = nullptr;
+    int32_t* d_runs = nullptr;
+    if (parts_ok && nsl == 1 && qd > 0) {
+      int dev = 0, max_lds = 0;
+      TG_HIP(hipGetDevice(&dev));
+      TG_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      const size_t cap = std::min<size_t>((size_t)std::max(0, max_lds),
+                                          (size_t)std::max(0, tune.c4_part_lds_kib) << 10);
+      const size_t fixed = c4_bcount_lds(0, 0, 256);
+      // R rows of part_rw words, R a multiple of 4 so that the table is whole uint4s
+      partR = cap > fixed ? (int64_t)((cap - fixed) / ((size_t)part_rw * 4)) / 4 * 4 : 0;
+      partK = partR > 0 ? (n + partR - 1) / partR : 0;
+      bw_lds = c4_bwalk_lds(CHW, (int)std::min<int64_t>(partK, 1 << 20));
+      bc_lds = c4_bcount_lds((int)partR, part_rw, 256);
+      if (partR >= 64 && partK < 65536 && bw_lds <= (size_t)max_lds) {
+        // per dense group: each node's first walk item (group-local), then the total
+        std::vector<int32_t> nit;
+        int64_t max_items = 0, total = 0;
+        for (int64_t g = 0; g < ngroups; ++g) {
+          gwalk[g] = total;
+          gnit[g] = (int64_t)nit.size();
+          if (gstart[g] >= qd) continue;
+          int64_t items = 0;
+          for (int64_t c = 0; c < gcount[g]; ++c) {
+            nit.push_back((int32_t)items);
+            items += ((int64_t)hw[order[gstart[g] + c]] + CHW - 1) / CHW;
+          }
+          nit.push_back((int32_t)items);
+          total += items;
+          max_items = std::max(max_items, items);
+        }
+        gwalk[ngroups] = total;
+        gnit[ngroups] = (int64_t)nit.size();
+        if (max_items > 0 && max_items < (1ll << 31)) {
+          TG_HIP(S.get(&d_nit, (int64_t)nit.size()));
+          TG_HIP(S.get(&d_region, max_items * CHW));
+          TG_HIP(S.get(&d_runs, max_items * (partK + 1)));
+          TG_HIP(hipMemcpyAsync(d_nit, nit.data(), nit.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+          // the copy reads the host vector until it is done
+          TG_HIP(hipStreamSynchronize(st));
+          use_parts = true;
+        }
+      }
+    }
     if (G > 0) {
       TG_HIP(S.get(&dense, G * stride));
-      k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
-      TG_LAUNCHED("k_fill_u32");
+      if (!use_parts) {
+        k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
+        TG_LAUNCHED("k_fill_u32");
+      }
     }
     if (max_hrows > 0) {
       TG_HIP(S.get(&d_hoff, n_t3));
@@ -978,7 +1039,17 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       L, s2x, C4P, crows, STG, ga_cyc_g, cdt)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
-    TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                           \
+    if (!HS && use_parts) {                                                                                        \
+      if (gwalk[g + 1] > gwalk[g]) {                                                                               \
+        k_c4_bwalk<TG_C4P_NW><<<(unsigned)(gwalk[g + 1] - gwalk[g]), TG_C4P_NW * TG_WAVE, bw_lds, st>>>(           \
+            d_nit + gnit[g], Gg, CHW, (int)partR, (int)partK, gxg, gsl, wpg, rp, ci, cdt, d_region, d_runs);       \
+        k_c4_bcount<256><<<(unsigned)(Gg * partK), 256, bc_lds, st>>>((int)partK, (int)partR, part_rw, n,          \
+                                                                      d_nit + gnit[g], d_region, CHW, d_runs,      \
+                                                                      dense, stride);                              \
+      }                                                                                                            \
+    } else {                                                                                                       \
+      TG_C4_GROUP(0, T, HF, HS, C4P, STG);                                                                         \
+    }                                                                                                              \
     if (once && (HS || fill_clear)) {                                                                              \
       const int64_t nrows = HS ? rows : Gg * n;                                                                    \
       k_c4_scan<HF, HS><<<grid_for(nrows, 256, 2048), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
@@ -991,6 +1062,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       k_fill_u32<<<grid_for(rows, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(hkeys), rows,             \
                                                              0xffffffffu);                                         \
       k_fill_u32<<<grid_for(rows * RW, 256, 16384), 256, 0, st>>>(hcnt, rows * RW, 0);                             \
+    } else if (use_parts) {                                                                                        \
+      /* the next dense group's counts overwrite every row */                                                      \
     } else if (fill_clear) {                                                                                       \
       k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0);                        \
     } else {                                                                                                       \
@@ -1817,6 +1890,10 @@ void tg_tuning_default(tg_tuning* t) {
   t->clique_pass = 1;
   t->clique_pass_grid = 0;
   t->clique_pass_lds_kib = 64;
+  t->c4_parts = 1;
+  t->c4_part_lds_kib = 40;
+  t->c4_part_chunk = 4096;
+  t->c4_part_hash_ratio = 8;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,

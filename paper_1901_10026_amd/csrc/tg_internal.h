@@ -22,6 +22,7 @@
 #define TG_T_WAVE_CAP 128     // |T_ij| handled by one wavefront
 #define TG_T_WG_CAP 2048      // |T_ij| kept in LDS by a workgroup (larger: global scratch)
 #define TG_GACC_MAX_KEYS 5120 // global keys accumulated in LDS per workgroup
+#define TG_C4P_NW 8           // wavefronts of a k_c4_part workgroup
 
 namespace tg {
 

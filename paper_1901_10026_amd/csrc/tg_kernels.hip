@@ -830,6 +830,7 @@ __global__ void k_c4_fold(int64_t m, int P, int64_t nslots, const int32_t* __res
   }
 }
 
+#include "tg_c4part.hip"
 #include "tg_combine.hip"
 #include "tg_clique.hip"
 

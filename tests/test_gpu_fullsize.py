@@ -105,7 +105,8 @@ def test_schedules_agree_at_full_size(big):
 def test_launch_shapes_agree_at_full_size(big):
     """Hash tables for the lighter heavy nodes, small node groups and wedge
     chunks, other team thresholds, T_ij by row intersection instead of the
-    kept lists: the same counts."""
+    kept lists, every heavy node in the grouped 4-cycle pass (no id-range
+    parts): the same counts."""
     import torch
 
     import paper_1901_10026_amd as tg
@@ -113,11 +114,28 @@ def test_launch_shapes_agree_at_full_size(big):
     t = tg.Tuning.from_dict({"c4_hash_ratio": 4, "c4_footprint_mb": 32, "c4_group_kwedges": 512,
                              "c4_chunk": 256, "light_max_degree": 64, "heavy_min_degree": 1024,
                              "combine_grid": 1024, "wg_grid": 300, "c4_slot_budget_mb": 0, "c4_slices": 8,
-                             "tlist_budget_mib": 0})
+                             "tlist_budget_mib": 0, "c4_parts": 0})
     g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=t)
     torch.cuda.synchronize()
     assert torch.equal(g2.view(torch.int64), glob.view(torch.int64))
     assert torch.equal(r2.view(torch.int64), rows.view(torch.int64))
+
+
+def test_cycle_parts_at_full_size(big):
+    """Middle counts of every heavy node from range-bucketed records summed in
+    LDS (all of them in dense groups), also with small tables (more ranges)
+    and small walk items: the same counts as the default."""
+    import torch
+
+    import paper_1901_10026_amd as tg
+    g, rp, ci, ty, glob, rows = big
+    for d in ({"c4_part_hash_ratio": 0},
+              {"c4_part_hash_ratio": 0, "c4_part_lds_kib": 64, "c4_part_chunk": 512}):
+        note(f"cl-1m with {d}")
+        g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=tg.Tuning.from_dict(d))
+        torch.cuda.synchronize()
+        assert torch.equal(g2.view(torch.int64), glob.view(torch.int64)), d
+        assert torch.equal(r2.view(torch.int64), rows.view(torch.int64)), d
 
 
 def test_clique_pass_equals_out_list_probes_at_full_size(big):

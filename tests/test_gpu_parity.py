@@ -250,6 +250,35 @@ def test_clique_pass_tiers_on_a_dense_graph():
         assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
 
+@pytest.mark.parametrize("which,L,lds_kib", [("cl-2k", 3, 4), ("gnp", 5, 4), ("gnp", 8, 5), ("kab", 2, 4)])
+def test_cycle_parts_match_the_grouped_pass(which, L, lds_kib):
+    """Middle counts of the dense 4-cycle groups from records bucketed by
+    far-end id range and summed in LDS (every heavy node dense, tables small
+    enough for several ranges, small walk items) or from global atomics: the
+    same rows, and the oracle's on a sample."""
+    import paper_1901_10026_amd as tg
+    if which == "cl-2k":
+        g = graphgen.chung_lu_small()
+        rp, ci = g.row_ptr, g.col_idx
+        ty = graphgen.types_uniform(g.n, L, 5)
+    elif which == "gnp":
+        rp, ci = graphgen.gnp(450, 0.75, 31)
+        ty = graphgen.types_uniform(450, L, 31)
+    else:
+        rp, ci = complete_bipartite(40, 260)
+        ty = (np.arange(300) % L).astype(np.uint8)
+    note(f"cycle parts: {which} L={L}")
+    ei, ej = oracle.canonical_edges(rp, ci)
+    sample = np.linspace(0, len(ei) - 1, 50).astype(np.int64)
+    want_rows, _ = oracle.count_edges(rp, ci, ty, L, ei[sample], ej[sample], nthreads=8)
+    base_g, base_r, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict({"c4_parts": 0}))
+    assert np.array_equal(base_r[sample], want_rows)
+    for d in ({}, {"c4_part_hash_ratio": 0}, {"c4_part_hash_ratio": 0, "c4_part_lds_kib": lds_kib},
+              {"c4_part_hash_ratio": 0, "c4_part_lds_kib": lds_kib, "c4_part_chunk": 256}):
+        gg, rr, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict(d))
+        assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
+
+
 def test_release_scratch_between_calls():
     import paper_1901_10026_amd as tg
     g = graphgen.chung_lu_small()
