@@ -150,6 +150,31 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, cop
     print(f"source_sha256: {kernel_source_hash()}")
 
 
+LDS_COUNTERS = ("SQ_INSTS_LDS", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_ADDR_CONFLICT",
+                "SQ_ACTIVE_INST_LDS", "SQ_WAVES", "GRBM_GUI_ACTIVE")
+
+
+def summarize_lds(csv_path, calls_per_run, cus=256):
+    """Prints per-kernel LDS figures from one rocprofv3 --pmc run of the LDS
+    counters: LDS instructions, the fraction of CU-cycles in which the LDS
+    served indexed accesses (SQ_LDS_IDX_ACTIVE over GRBM_GUI_ACTIVE x CUs,
+    the share of the LDS's peak rate in use), and the share of those cycles
+    stalled by bank conflicts."""
+    vals = {c: _read_counter_csv(csv_path, c)[0] for c in LDS_COUNTERS}
+    calls = _read_counter_csv(csv_path, "SQ_INSTS_LDS")[1]
+    print(f"{'kernel':60s} {'calls':>6s} {'lds_insts':>12s} {'lds_busy':>9s} {'bank_confl':>10s} {'waves':>10s}")
+    for k in sorted(calls, key=lambda k: -vals["SQ_LDS_IDX_ACTIVE"].get(k, 0.0)):
+        gui = vals["GRBM_GUI_ACTIVE"].get(k, 0.0)
+        act = vals["SQ_LDS_IDX_ACTIVE"].get(k, 0.0)
+        if act <= 0 or gui <= 0:
+            continue
+        busy = act / (gui * cus)
+        conf = vals["SQ_LDS_BANK_CONFLICT"].get(k, 0.0) / act
+        print(f"{k[:60]:60s} {calls[k] / calls_per_run:6.0f} {vals['SQ_INSTS_LDS'].get(k, 0.0) / calls_per_run:12.4g} "
+              f"{busy:9.4f} {conf:10.4f} {vals['SQ_WAVES'].get(k, 0.0) / calls_per_run:10.4g}")
+    print(f"source_sha256: {kernel_source_hash()}")
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, for scaling the FETCH_SIZE
     and WRITE_SIZE counters."""
@@ -728,6 +753,8 @@ def main():
                                                              "COPY_WRITE_CSV"),
                     help="only print the L2-egress summary of rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the "
                          "benchmark step and of --copy-calibration (counter_collection.csv files) and exit")
+    ap.add_argument("--summarize-lds", metavar="COUNTER_CSV",
+                    help="print per-kernel LDS figures of a rocprofv3 --pmc run of the LDS counters and exit")
     ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
                     help="only print the per-kernel summary of a rocprofv3 --kernel-trace --stats run and exit")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy (--summarize-counters)")
@@ -735,6 +762,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.calls)
+        return
+    if args.summarize_lds:
+        summarize_lds(args.summarize_lds, args.calls)
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, copy_bytes=args.copy_mib << 20, calls_per_run=args.calls)
