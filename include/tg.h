@@ -131,8 +131,8 @@ typedef struct {
                                  fit in this many KiB per workgroup, else in global scratch */
   int32_t c4_parts;           /* tg_count: 1 = the dense groups of the 4-cycle pass take their middle
                                  counts from records bucketed by far-end id range and summed in LDS
-                                 instead of from global atomics (L <= 8, maximum degree below 65536,
-                                 one slice); 0 = never */
+                                 instead of from global atomics (L <= 8, maximum degree below 65536);
+                                 0 = never */
   int32_t c4_part_lds_kib;    /* tg_count: LDS per workgroup of the range table, capped by the device's
                                  limit */
   int32_t c4_part_chunk;      /* tg_count: wedges per walk item of that pass (256 to 32768) */

@@ -820,7 +820,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     };
     // the bucketed counts of dense groups (below) shift the balance towards
     // hash tables for the lighter nodes: their own ratio applies then
-    const bool parts_ok = !once && tune.c4_parts != 0 && cdt && half && L <= 8 && tune.c4_slices <= 1 && nty == 1;
+    const bool parts_ok = !once && tune.c4_parts != 0 && cdt && half && L <= 8 && nty == 1;
     const int hash_ratio = std::max(0, parts_ok ? tune.c4_part_hash_ratio : tune.c4_hash_ratio);
     int64_t qd = n_t3;  // nodes [0, qd) dense, [qd, n_t3) hashed
     if (hash_ratio > 0) {
@@ -842,7 +842,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     for (int64_t q = 0; q < qd; ++q) dense_slots += hd[order[q]];
     const int nsl = (tune.c4_slices > 1 && dense_slots > 0 && dense_slots * tune.c4_slices * 16 <= (4ll << 30))
                         ? tune.c4_slices : 1;
-    const int64_t foot_dense = nsl > 1 ? (int64_t)nsl << 21 : foot;
+    // (with the bucketed counts, slices only split the credit walk, whose
+    // workgroups run node after node, so the groups keep their full size)
+    const int64_t foot_dense = (nsl > 1 && !parts_ok) ? (int64_t)nsl << 21 : foot;
     const int CH = std::max(64, tune.c4_chunk);
     std::vector<int64_t> gstart, gcount;
     std::vector<int64_t> hoff(n_t3, 0);
@@ -918,7 +920,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     int32_t* d_nit = nullptr;
     uint32_t* d_region = nullptr;
     int32_t* d_runs = nullptr;
-    if (parts_ok && nsl == 1 && qd > 0) {
+    if (parts_ok && qd > 0) {
       int dev = 0, max_lds = 0;
       TG_HIP(hipGetDevice(&dev));
       TG_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1042,7 +1044,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     if (!HS && use_parts) {                                                                                        \
       if (gwalk[g + 1] > gwalk[g]) {                                                                               \
         k_c4_bwalk<TG_C4P_NW><<<(unsigned)(gwalk[g + 1] - gwalk[g]), TG_C4P_NW * TG_WAVE, bw_lds, st>>>(           \
-            d_nit + gnit[g], Gg, CHW, (int)partR, (int)partK, gxg, gsl, wpg, rp, ci, cdt, d_region, d_runs);       \
+            d_nit + gnit[g], Gg, CHW, (int)partR, (int)partK, gxg, gsl, d_wp + hs[q0], rp, ci, cdt, d_region,     \
+            d_runs);                                                                                               \
         k_c4_bcount<256><<<(unsigned)(Gg * partK), 256, bc_lds, st>>>((int)partK, (int)partR, part_rw, n,          \
                                                                       d_nit + gnit[g], d_region, CHW, d_runs,      \
                                                                       dense, stride);                              \

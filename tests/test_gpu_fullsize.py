@@ -123,13 +123,14 @@ def test_launch_shapes_agree_at_full_size(big):
 
 def test_cycle_parts_at_full_size(big):
     """Middle counts of every heavy node from range-bucketed records summed in
-    LDS (all of them in dense groups), also with small tables (more ranges)
-    and small walk items: the same counts as the default."""
+    LDS (all of them in dense groups), the credit walk split into far-end
+    slices, small tables (more ranges) and small walk items: the same counts
+    as the default."""
     import torch
 
     import paper_1901_10026_amd as tg
     g, rp, ci, ty, glob, rows = big
-    for d in ({"c4_part_hash_ratio": 0},
+    for d in ({"c4_part_hash_ratio": 0}, {"c4_slices": 8},
               {"c4_part_hash_ratio": 0, "c4_part_lds_kib": 64, "c4_part_chunk": 512}):
         note(f"cl-1m with {d}")
         g2, r2, _ = tg.count(rp, ci, ty, g.L, per_edge=True, tuning=tg.Tuning.from_dict(d))

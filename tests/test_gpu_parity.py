@@ -274,7 +274,8 @@ def test_cycle_parts_match_the_grouped_pass(which, L, lds_kib):
     base_g, base_r, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict({"c4_parts": 0}))
     assert np.array_equal(base_r[sample], want_rows)
     for d in ({}, {"c4_part_hash_ratio": 0}, {"c4_part_hash_ratio": 0, "c4_part_lds_kib": lds_kib},
-              {"c4_part_hash_ratio": 0, "c4_part_lds_kib": lds_kib, "c4_part_chunk": 256}):
+              {"c4_part_hash_ratio": 0, "c4_part_lds_kib": lds_kib, "c4_part_chunk": 256},
+              {"c4_part_hash_ratio": 0, "c4_slices": 8}):
         gg, rr, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict(d))
         assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
