@@ -1872,15 +1872,15 @@ void tg_options_default(tg_options* opt) {
 
 void tg_tuning_default(tg_tuning* t) {
   if (!t) return;
-  t->light_max_degree = 64;
+  t->light_max_degree = 1024;
   t->heavy_min_degree = 4096;
   t->mid_log2_cost = 16;
   t->heavy_log2_cost = 64;
   t->combine_grid = 16384;
-  t->wg_grid = 4096;
+  t->wg_grid = 1024;
   t->c4_footprint_mb = 1024;
-  t->c4_group_kwedges = 32768;
-  t->c4_chunk = 256;
+  t->c4_group_kwedges = 65536;
+  t->c4_chunk = 1024;
   t->c4_hash_ratio = 16;
   t->c4_slot_budget_mb = 16384;
   t->c4_slices = 1;
@@ -2372,6 +2372,9 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
   axes.push_back({&t.c4_chunk, {256, 1024, 4096}});
   axes.push_back({&t.c4_hash_ratio, {0, 4, 16}});
   axes.push_back({&t.c4_slices, {1, 8}});
+  axes.push_back({&t.c4_part_hash_ratio, {2, 4, 8, 16}});
+  axes.push_back({&t.c4_part_lds_kib, {32, 40, 64}});
+  axes.push_back({&t.c4_part_chunk, {2048, 4096, 8192}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

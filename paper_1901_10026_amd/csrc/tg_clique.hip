@@ -22,7 +22,8 @@
 //     edges at b, so the sum is twice the count and is halved when flushed.
 // The three edges at a are credited by the second rule, the three others by
 // the first, so every clique through every edge is counted exactly once per
-// edge.  Counters are type-pair major: K4[p * m + e].
+// edge.  Counters are edge major, K4[e * P + p], so that the row kernel reads
+// an edge's counters from one cache line.
 // Global counts (GLOB): each triangle {b, c, d} of G_a is counted once, from
 // the edge of its two lowest positions, by restricting the popcounts to the
 // positions above both ends; its clique adds one to the 4-clique key of
@@ -48,14 +49,15 @@ struct K4Args {
   const int32_t* out_eid;  // canonical edge id of each out-list slot
   int64_t m;
   uint32_t* K4n;           // per-edge counters, 32-bit ...
-  uint64_t* K4w;           // ... or 64-bit (one of the two is set), K4[p * m + e]
+  uint64_t* K4w;           // ... or 64-bit (one of the two is set), K4[e * P + p]
 };
 
 #define TG_K4_LDS_IDS 4096  // largest |O| of the pass (ids of O are kept in LDS)
 
 __device__ __forceinline__ void k4_credit(const K4Args& A, int p, int32_t e, uint32_t v) {
-  if (A.K4w) atomicAdd((unsigned long long*)&A.K4w[(int64_t)p * A.m + e], (unsigned long long)v);
-  else atomicAdd(&A.K4n[(int64_t)p * A.m + e], v);
+  const int64_t q = (int64_t)e * (A.L * (A.L + 1) / 2) + p;
+  if (A.K4w) atomicAdd((unsigned long long*)&A.K4w[q], (unsigned long long)v);
+  else atomicAdd(&A.K4n[q], v);
 }
 
 template <bool DEV>

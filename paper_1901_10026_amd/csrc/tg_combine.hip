@@ -419,7 +419,7 @@ __device__ __forceinline__ void edge_rows(const EdgeArgs& A, int32_t e, const Ac
     // M(x, y): edges between T^x and T^y counted from both ends, i.e. the
     // 4-cliques through (i, j) with other types {x, y}, twice when x == y
     auto k4 = [&](int x, int y) -> int64_t {
-      const int64_t q = (int64_t)pair_index(x, y) * A.m + e;
+      const int64_t q = (int64_t)e * P + pair_index(x, y);
       return A.K4w ? (int64_t)A.K4w[q] : (int64_t)A.K4n[q];
     };
     const bool have_k4 = A.K4w || A.K4n;

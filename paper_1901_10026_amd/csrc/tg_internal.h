@@ -98,8 +98,8 @@ struct EdgeArgs {
   int gacc_in_lds;
   uint64_t* work;         // null, or per-edge element-visit counts (added atomically, by edge id)
   int thash_ok;           // node ids fit the packed (id << 4 | type) hash slots
-  // per-edge typed 4-clique counts from the clique pass, type-pair major
-  // (K4[p * m + e]), 32- or 64-bit; both null: the gather probes out-lists
+  // per-edge typed 4-clique counts from the clique pass, edge major
+  // (K4[e * P + p]), 32- or 64-bit; both null: the gather probes out-lists
   const uint32_t* K4n;
   const uint64_t* K4w;
   int64_t m;
