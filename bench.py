@@ -695,7 +695,8 @@ def phase_rooflines(tg, g, out_e, tau_sum, phases):
     scanned, oriented = cycle_wedges(st)
     models = {
         "cycles": (cycles_bytes(st, L, scanned, oriented, c4_width),
-                   "typed 4-cycle phase: k_c4_hash tiers, k_c4_group count/credit/clear, k_c4_fold",
+                   "typed 4-cycle phase: k_c4_hash tiers, k_c4_bwalk/k_c4_bcount bucketed counts, "
+                   "k_c4_group count/credit/clear, k_c4_fold",
                    f"{scanned} scanned and {oriented} oriented wedges; credits left out"),
         "cliques": (clique_bytes(st, L, k4_width) if pass_used else 0,
                     "typed 4-clique pass: k_k4_low over every node with 3 or more higher-ranked neighbours",
