@@ -163,7 +163,11 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
         if (Th) hash_member(k, t);
       }
     }
-  } else
+  } else {
+  // without PROBE nothing keeps T: |T_ij| is the sum of tau(i, j), and the
+  // members need no positions (no ballot, no barrier per chunk)
+  if (!PROBE)
+    for (int u = 0; u < L; ++u) nT += (int32_t)A.tau[(int64_t)e * L + u];
   for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
     const int32_t idx = b0 + tid;
     bool found = false;
@@ -178,6 +182,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       t = A.ty[k];
       add_member(k, t, ra + idx, rb + p);
     }
+    if (!PROBE) continue;
     const uint64_t wmask = ballot(found);
     int32_t before, total;
     if (TSIZE <= TG_WAVE) {
@@ -202,6 +207,7 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
       if (Th) hash_member(k, t);
     }
     nT += total;
+  }
   }
   tsync<TSIZE>();
 
