@@ -370,6 +370,18 @@ def compare_schedules(tg, g, rp, ci, ty, out_g, out_e, steps=5):
                                              model=model, tuning=t_l)
     res["learned_tuning"] = t_l.as_dict()
     log(f"learned schedule, autotuned: {res['learned_autotuned_ms']:.1f} ms (training {res['mlp_train_ms']:.0f} ms)")
+    # three more of each, interleaved, for the run-to-run spread
+    dr, lr = [res["degree_autotuned_ms"]], [res["learned_autotuned_ms"]]
+    for _ in range(3):
+        dr.append(time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="degree", tuning=t_deg))
+        lr.append(time_count(tg, g, rp, ci, ty, out_g, out_e, steps, schedule="learned", model=model, tuning=t_l))
+    res["degree_autotuned_runs_ms"], res["learned_autotuned_runs_ms"] = dr, lr
+    spread = max(dr) - min(dr)
+    gain = float(np.mean(dr) - np.mean(lr))
+    res["degree_autotuned_spread_ms"] = spread
+    res["learned_gain_ms"] = gain
+    res["learned_gain_over_spread"] = gain / spread if spread > 0 else None
+    log(f"autotuned, 4 runs each: degree {np.mean(dr):.1f} ms (spread {spread:.2f}), learned {np.mean(lr):.1f} ms")
     return res
 
 

@@ -1,11 +1,12 @@
-"""Skewed giant graph (Chung-Lu, 20M nodes, L=8 Zipf types).  Its per-edge
-rows do not fit in memory, so the call counts rows only for an edge sample
-(global_counts=False): the 4-cycle pass covers the whole graph, the
-per-edge step only the sample, and every sampled row must equal the
-oracle's.  The sample is stratified by degree product and also holds the
-heaviest edges of the graph (the largest d_i * d_j): hub-hub edges with the
-longest common-neighbour sets, which take the workgroup teams and the
-global-scratch path of T_ij."""
+"""Skewed giant graph (Chung-Lu, 20M nodes, L=8 Zipf types).  Its dense
+per-edge rows do not fit in memory; the call takes the sparse per-edge
+output (nonzero (key, count) pairs straight from the row kernel) of an edge
+sample only (global_counts=False): the 4-cycle and clique passes cover the
+whole graph, the per-edge step only the sample, and every sampled edge's
+pairs must be the oracle row's nonzero entries.  The sample is stratified
+by degree product and also holds the heaviest edges of the graph (the
+largest d_i * d_j): hub-hub edges with the longest common-neighbour sets,
+which take the workgroup teams."""
 import numpy as np
 import pytest
 
@@ -55,19 +56,28 @@ def test_giant_sampled_rows():
          f"largest oracle cost {(s[ei[ids]] + s[ej[ids]]).max():.3e}")
     rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
     dev_ids = torch.from_numpy(ids).to(rp.device)
-    note("cl-20m: counting the sampled rows (the 4-cycle pass covers the whole graph)")
+    note("cl-20m: counting the sampled edges, sparse output only (the 4-cycle and clique passes cover the "
+         "whole graph)")
     ph = {}
-    glob, rows, ends = tg.count(rp, ci, ty, g.L, per_edge=True, edge_ids=dev_ids, global_counts=False,
-                                endpoints=True, phase_ms=ph)
+    glob, keys, counts, start, length = tg.count_sparse(rp, ci, ty, g.L, edge_ids=dev_ids, global_counts=False,
+                                                        phase_ms=ph)
     torch.cuda.synchronize()
-    note("tg_count done: " + " ".join(f"{k}={v:.0f}ms" for k, v in ph.items()))
+    note("tg_count_sparse done: " + " ".join(f"{k}={v:.0f}ms" for k, v in ph.items()))
     assert glob is None
     del rp, ci, ty
-    ends = ends.cpu().numpy()
-    assert np.array_equal(ends[:, 0], ei[ids]) and np.array_equal(ends[:, 1], ej[ids])
-    got = rows.cpu().numpy().view(np.uint64)
+    keys = keys.cpu().numpy().view(np.uint32)
+    counts = counts.cpu().numpy().view(np.uint64)
+    start, length = start.cpu().numpy(), length.cpu().numpy()
     note("cl-20m: oracle on the sampled edges")
     want, _ = oracle.count_edges(g.row_ptr, g.col_idx, g.types, g.L, ei[ids], ej[ids], nthreads=16)
-    bad = np.nonzero((got != want).any(axis=1))[0]
-    assert len(bad) == 0, f"{len(bad)} of {len(ids)} sampled rows differ, first edge {ids[bad[0]]}"
-    note(f"{len(ids)} sampled rows match the oracle")
+    bad = []
+    for q in range(len(ids)):
+        a, b = int(g.types[ei[ids[q]]]), int(g.types[ej[ids[q]]])
+        cols = np.nonzero(want[q])[0]
+        exp = [(oracle.row_key(g.L, a, b, int(c)), int(want[q, c])) for c in cols]
+        s0, n0 = int(start[q]), int(length[q])
+        got = list(zip(keys[s0:s0 + n0].astype(int).tolist(), counts[s0:s0 + n0].astype(int).tolist()))
+        if got != exp:
+            bad.append(q)
+    assert not bad, f"{len(bad)} of {len(ids)} sampled edges differ, first edge {ids[bad[0]]}"
+    note(f"{len(ids)} sampled edges' sparse pairs match the oracle's nonzero row entries")
