@@ -373,11 +373,12 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
       TG_HIP(S.get(&W.tl_e, 2 * (int64_t)total));
     }
   }
+  W.tl_packed = n < (1ll << 27) ? 1 : 0;
   k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.es_lo,
-                                                   W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e);
+                                                   W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed);
   TG_LAUNCHED("k_tau<16>");
   k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.es_lo,
-                                                  W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e);
+                                                  W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed);
   TG_LAUNCHED("k_tau<64>");
   if (timer) timer->mark(TG_PHASE_TABLES);
   if (tables) {
@@ -1204,9 +1205,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                      W.wedge_work, W.nbr_deg_sum);
         TG_LAUNCHED("k_node_stats");
         k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
-                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
         k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
-                                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
         TG_LAUNCHED("k_tau");
       }
       const GAcc ga_all = make_gacc(gb, 0, K, 32 << 10);
@@ -1254,7 +1255,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
-  A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e;
+  A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e; A.tl_packed = W.tl_packed;
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
   A.c4_rows = slot_rows ? 0 : m;
@@ -1672,7 +1673,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   EdgeArgs A;
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
-  A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e;
+  A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e; A.tl_packed = W.tl_packed;
   A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
   A.c4_wide = 1;
   A.c4_rows = 0;

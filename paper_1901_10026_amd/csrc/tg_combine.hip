@@ -154,8 +154,9 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
     for (int u = 0; u < L; ++u) nT += (int32_t)A.tau[(int64_t)e * L + u];
     const int64_t base = A.tl_off[e];
     for (int32_t q = tid; q < nT; q += TSIZE) {
-      const int32_t k = A.tl_k[base + q];
-      const int t = A.ty[k];
+      const int32_t v = A.tl_k[base + q];
+      const int32_t k = A.tl_packed ? (v >> 4) : v;
+      const int t = A.tl_packed ? (v & 15) : A.ty[k];
       add_member(k, t, A.tl_e[2 * (base + q)], A.tl_e[2 * (base + q) + 1]);
       if (PROBE) {
         Tid[q] = k;

@@ -55,7 +55,8 @@ struct Work {
   uint32_t* tau;         // m*L
   uint32_t* tau_s;       // nnz*L: tau of each edge again at both of its CSR slots (per-edge counting only)
   int64_t* tl_off;       // m+1, or null: start of each edge's common-neighbour list kept by the tau pass
-  int32_t* tl_k;         // list entries: member ids ...
+  int tl_packed;         // list ids hold their node's type in the low 4 bits (n < 2^27)
+  int32_t* tl_k;         // list entries: member ids (id << 4 | type when tl_packed) ...
   int32_t* tl_e;         // ... and the CSR slots of k in the rows of a and b, two per member
   uint64_t* Pn;          // n*L*L
   uint64_t* Un;          // n*L*L
@@ -80,6 +81,7 @@ struct EdgeArgs {
   const uint32_t* tau;
   const uint32_t* tau_s;  // tau by CSR slot
   const int64_t* tl_off;  // common-neighbour lists of the edges (from the tau pass), or null
+  int tl_packed;          // list ids are id << 4 | type
   const int32_t* tl_k;
   const int32_t* tl_e;
   const uint64_t* Pn;

@@ -246,7 +246,8 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
                                              const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau,
                                              const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
                                              uint32_t* __restrict__ tau_s, const int64_t* __restrict__ tl_off,
-                                             int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e) {
+                                             int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e,
+                                             int tl_packed) {
   constexpr int TEAMS = 256 / TSIZE;
   // wavefront teams copy a longer row of at most STAGE ids to LDS and
   // search it there (16 KB per workgroup; 2048 ids measured slower, the
@@ -271,7 +272,8 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
       pb = sb;
     }
     // with lists, the edge keeps its common neighbours in id order, with
-    // their CSR slots in the rows of both ends
+    // their CSR slots in the rows of both ends (ids as id << 4 | type when
+    // tl_packed, so that the gather reads no type by id)
     const bool keep = tl_off != nullptr;
     const int64_t lbase = keep ? tl_off[e] : 0;
     int32_t nkept = 0;
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
       if (keep) {
         if (t >= 0) {
           const int64_t pos = lbase + nkept + __popcll(tm & ((1ull << tl) - 1ull));
-          tl_k[pos] = k;
+          tl_k[pos] = tl_packed ? ((k << 4) | t) : k;
           tl_e[2 * pos] = ra + b0 + tl;
           tl_e[2 * pos + 1] = rb + p;
         }
