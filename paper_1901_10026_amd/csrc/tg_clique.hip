@@ -108,10 +108,10 @@ __device__ __forceinline__ int32_t k4_scan(int32_t v, int32_t* total, int32_t* s
 
 // Bytes of LDS per team.
 //   ids[dcap] i32, pos[dcap] i32, tq[dcap] u8, tstart/fill 2 x 17 i32,
-//   scan 4 + 3 * TSIZE i32 (workgroup teams), then rows dcap * NW u64 and
-//   acc dcap * P u32 (LDS teams), or (GSCR) the position -> index map
-//   qpos[dcap] i32, the type by position ptype[dcap] u8 and one P-counter
-//   accumulator per wavefront
+//   scan 4 + 3 * TSIZE i32 (workgroup teams), then rows dcap * NW u64,
+//   acc dcap * P u32 and the position -> index map qpos[dcap] i32 (LDS
+//   teams), or (GSCR) qpos[dcap] i32, the type by position ptype[dcap] u8
+//   and one P-counter accumulator per wavefront
 template <int TSIZE, bool GSCR>
 __host__ __device__ inline int k4_team_lds(int dcap, int L) {
   const int P = L * (L + 1) / 2, NW = (dcap + 63) / 64;
@@ -120,7 +120,7 @@ __host__ __device__ inline int k4_team_lds(int dcap, int L) {
   b += 4 * 34;
   if (TSIZE > TG_WAVE) b += 4 * (4 + 3 * TSIZE);
   b = (b + 7) & ~7;
-  if (!GSCR) b += 8 * dcap * NW + 4 * dcap * P;
+  if (!GSCR) b += 8 * dcap * NW + 4 * dcap * P + 4 * dcap;
   else b += ((5 * dcap + 3) & ~3) + 4 * (TSIZE / TG_WAVE) * P;
   return (b + 15) & ~15;
 }
@@ -168,6 +168,7 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
   } else {
     rows = reinterpret_cast<uint64_t*>(after);
     acc = reinterpret_cast<uint32_t*>(after + 8 * dcap * NW);
+    qpos = reinterpret_cast<int32_t*>(acc + dcap * P);
   }
   int32_t* s_excl = scan + 4;  // workgroup teams: excl, out start, owner index
 
@@ -202,10 +203,8 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
       const int t = tq[q];
       const int32_t pq = tstart[t] + atomicAdd(&fill[t], 1);
       pos[q] = pq;
-      if (GSCR) {
-        qpos[pq] = q;
-        ptype[pq] = (uint8_t)t;
-      }
+      qpos[pq] = q;
+      if (GSCR) ptype[pq] = (uint8_t)t;
     }
     // clear rows and accumulators
     for (int64_t x = tid; x < (int64_t)D * NW; x += TSIZE) rows[x] = 0;
@@ -213,8 +212,10 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
       for (int64_t x = tid; x < (int64_t)D * P; x += TSIZE) acc[x] = 0;
     k4_sync<TSIZE>();
     const int NWa = (D + 63) / 64;  // words per row for this node
-    // ---- 2 and 3: two passes over the pairs (b, c), b in O, c in out(b)
-    for (int pass = 0; pass < 2; ++pass) {
+    // ---- 2 and 3: passes over the pairs (b, c), b in O, c in out(b): the
+    // first sets the bit rows; the second (GSCR teams only: the LDS teams
+    // take the edges of G_a from the rows, below) credits the cliques
+    for (int pass = 0; pass < (GSCR ? 2 : 1); ++pass) {
       for (int32_t q0 = 0; q0 < D; q0 += TSIZE) {
         const int32_t q = q0 + tid;
         int32_t ostart = 0, ocnt = 0;
@@ -279,6 +280,102 @@ __global__ void __launch_bounds__(256) k_k4_low(K4Args A, int64_t count, const i
               atomicAdd(&acc[(int64_t)pb * P + pair_index(tc, u)], nv);
               atomicAdd(&acc[(int64_t)pc * P + pair_index(tb, u)], nv);
             }
+          }
+        }
+        if (TSIZE > TG_WAVE) __syncthreads();
+      }
+      k4_sync<TSIZE>();
+    }
+    // ---- 3 (LDS teams): every edge (b, c) of G_a once, from the rows:
+    // position pb takes the set bits pc > pb of its row, dealt to lanes
+    // through a team prefix sum of their numbers
+    if (!GSCR) {
+      for (int32_t p0 = 0; p0 < D; p0 += TSIZE) {
+        const int32_t pbl = p0 + tid;
+        int32_t cnt = 0;
+        if (pbl < D) {
+          const uint64_t* rw = rows + (int64_t)pbl * NW;
+          for (int k = pbl >> 6; k < NWa; ++k) {
+            uint64_t w = rw[k];
+            if (k == (pbl >> 6)) w &= ((pbl & 63) == 63) ? 0ull : (~0ull << ((pbl & 63) + 1));
+            cnt += __popcll(w);
+          }
+        }
+        int32_t tot;
+        const int32_t excl = k4_scan<TSIZE>(cnt, &tot, scan, tid);
+        if (TSIZE > TG_WAVE) {
+          s_excl[tid] = excl;
+          __syncthreads();
+        }
+        for (int32_t v = tid; v - tid < tot; v += TSIZE) {
+          // owner: the largest lane o with excl[o] <= v
+          int o = 0;
+#pragma unroll
+          for (int step = TSIZE / 2; step > 0; step >>= 1) {
+            const int32_t ex = TSIZE <= TG_WAVE ? __shfl(excl, o + step, TSIZE) : s_excl[o + step];
+            if (ex <= v) o += step;
+          }
+          const int32_t o_excl = TSIZE <= TG_WAVE ? __shfl(excl, o, TSIZE) : s_excl[o];
+          if (v >= tot) continue;
+          const int32_t pb = p0 + o;
+          // pc: the (v - o_excl)-th set bit above pb in row(pb)
+          int32_t kth = v - o_excl, pc = -1;
+          const uint64_t* rb = rows + (int64_t)pb * NW;
+          for (int k = pb >> 6; k < NWa && pc < 0; ++k) {
+            uint64_t w = rb[k];
+            if (k == (pb >> 6)) w &= ((pb & 63) == 63) ? 0ull : (~0ull << ((pb & 63) + 1));
+            const int c = __popcll(w);
+            if (kth >= c) {
+              kth -= c;
+              continue;
+            }
+            int base = 0;
+            for (int sh = 32; sh > 0; sh >>= 1) {  // select the kth set bit
+              const uint64_t low = w & ((1ull << sh) - 1ull);
+              const int cl = __popcll(low);
+              if (kth >= cl) {
+                kth -= cl;
+                w >>= sh;
+                base += sh;
+              } else {
+                w = low;
+              }
+            }
+            pc = (k << 6) + base;
+          }
+          const int32_t qb = qpos[pb], qc = qpos[pc];
+          const int tb = tq[qb], tc = tq[qc];
+          const uint64_t* rc = rows + (int64_t)pc * NW;
+          int32_t e_bc = 0;
+          if (!GLOB) {
+            // the edge (b, c) sits in the out-list of its lower end
+            const int32_t b = O[qb], c = O[qc];
+            const bool b_low = precedes(A.deg[b], b, A.deg[c], c);
+            const int32_t lo_n = b_low ? b : c, hi_n = b_low ? c : b;
+            const int32_t s0 = A.out_off[lo_n];
+            const int32_t r = lower_bound(A.out_col + s0, A.out_off[lo_n + 1] - s0, hi_n);
+            e_bc = A.out_eid[s0 + r];
+          }
+          // typed popcounts of row(b) & row(c), one type range at a time
+          // (GLOB: positions above both ends only)
+          const int32_t lo_all = GLOB ? pc + 1 : 0;
+          for (int u = 0; u < L; ++u) {
+            const int32_t s0 = max(tstart[u], lo_all), s1 = tstart[u + 1];
+            if (s0 >= s1) continue;
+            uint32_t nv = 0;
+            for (int32_t k = s0 >> 6; k <= (s1 - 1) >> 6; ++k) {
+              const int32_t b0 = max(s0 - (k << 6), 0), b1 = min(s1 - (k << 6), 64);
+              const uint64_t msk = (b1 >= 64 ? ~0ull : ((1ull << b1) - 1ull)) & ~((1ull << b0) - 1ull);
+              nv += (uint32_t)__popcll(rb[k] & rc[k] & msk);
+            }
+            if (!nv) continue;
+            if (GLOB) {
+              gacc_add(ga, gsm, key_of(L, 7, phia, tb, tc, u), (uint64_t)nv);
+              continue;
+            }
+            k4_credit(A, pair_index(phia, u), e_bc, nv);
+            atomicAdd(&acc[(int64_t)pb * P + pair_index(tc, u)], nv);
+            atomicAdd(&acc[(int64_t)pc * P + pair_index(tb, u)], nv);
           }
         }
         if (TSIZE > TG_WAVE) __syncthreads();
