@@ -137,6 +137,9 @@ typedef struct {
                                  limit */
   int32_t c4_part_chunk;      /* tg_count: wedges per walk item of that pass (256 to 32768) */
   int32_t c4_part_hash_ratio; /* tg_count: c4_hash_ratio in effect when that pass is on */
+  int32_t tau_hub_min_degree; /* tg_count: the typed-triangle pass finds the common neighbours of an edge
+                                 whose longer row has more than this many entries in a bitmap of that
+                                 row (raised until the bitmaps fit in 4 GiB; 0 = binary search always) */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */

@@ -301,7 +301,7 @@ tg_status validate_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, con
 // pass also keeps them.
 tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                         const uint8_t* ty, int L, Work& W, PhaseTimer* timer, bool tables = true,
-                        int64_t list_budget = 0, bool out_eids = false) {
+                        int64_t list_budget = 0, bool out_eids = false, int32_t hub_min_degree = 4096) {
   const int64_t m = nnz / 2, P = (int64_t)L * (L + 1) / 2, LL = (int64_t)L * L;
   TG_HIP(S.get(&W.deg, n));
   TG_HIP(S.get(&W.D, n * L));
@@ -374,12 +374,68 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
     }
   }
   W.tl_packed = n < (1ll << 27) ? 1 : 0;
+  // Edges whose longer row is a hub's (degree above hub_min) are searched
+  // in a bitmap of the hub's row instead (k_tau_hub); the threshold rises
+  // until the bitmaps and their ranks (12 B per 64 node ids per hub) fit in
+  // 4 GiB.
+  int32_t hub_min = INT32_MAX;
+  int64_t nh = 0, hub_slots = 0;
+  const int64_t nw = (n + 63) / 64;
+  int32_t* hubs = nullptr;
+  int64_t* hoff = nullptr;
+  uint64_t* hbits = nullptr;
+  int32_t* hrank = nullptr;
+  if (hub_min_degree > 0 && m > 0) {
+    int32_t* d_cnt;
+    TG_HIP(S.get(&d_cnt, 1));
+    for (int32_t h = hub_min_degree; h > 0 && h < (1 << 30); h *= 2) {
+      k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(d_cnt), 1, 0u);
+      k_hubs_above<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, W.deg, h, 1, d_cnt, nullptr, nullptr);
+      TG_LAUNCHED("k_hubs_above");
+      int32_t c = 0;
+      TG_HIP(hipMemcpyAsync(&c, d_cnt, sizeof(c), hipMemcpyDeviceToHost, st));
+      TG_HIP(hipStreamSynchronize(st));
+      if ((int64_t)c * nw * 12 <= (4ll << 30)) {
+        hub_min = h;
+        nh = c;
+        break;
+      }
+    }
+    if (nh > 0) {
+      int64_t* hdeg;
+      TG_HIP(S.get(&hubs, nh));
+      TG_HIP(S.get(&hdeg, nh));
+      TG_HIP(S.get(&hoff, nh + 1));
+      k_fill_u32<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(d_cnt), 1, 0u);
+      k_hubs_above<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, W.deg, hub_min, 0, d_cnt, hubs, hdeg);
+      TG_LAUNCHED("k_hubs_above");
+      if (tg_status s = scan(S, st, nh, (const int64_t*)hdeg, hoff)) return s;
+      TG_HIP(hipMemcpyAsync(&hub_slots, hoff + nh, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      TG_HIP(S.get(&hbits, nh * nw));
+      TG_HIP(S.get(&hrank, nh * nw));
+      k_fill_u64<<<grid_for(nh * nw, 256, 16384), 256, 0, st>>>(hbits, nh * nw, 0);
+      TG_LAUNCHED("k_fill_u64");
+      TG_HIP(hipStreamSynchronize(st));
+      k_hub_bits<<<grid_for(hub_slots, 256, 16384), 256, 0, st>>>(hub_slots, nh, hubs, hoff, rp, ci, nw, hbits);
+      TG_LAUNCHED("k_hub_bits");
+      k_hub_rank<<<(unsigned)nh, 256, 0, st>>>(nw, hbits, hrank);
+      TG_LAUNCHED("k_hub_rank");
+    } else {
+      hub_min = INT32_MAX;
+    }
+  }
   k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.es_lo,
-                                                   W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed);
+                                                   W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed, hub_min);
   TG_LAUNCHED("k_tau<16>");
   k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, ty, L, W.tau, W.es_lo,
-                                                  W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed);
+                                                  W.es_hi, W.tau_s, W.tl_off, W.tl_k, W.tl_e, W.tl_packed, hub_min);
   TG_LAUNCHED("k_tau<64>");
+  if (nh > 0) {
+    k_tau_hub<<<grid_for(hub_slots, 4, 16384), 256, 0, st>>>(hub_slots, nh, hubs, hoff, nw, hbits, hrank, rp, ci,
+                                                             W.deg, W.s2e, ty, L, W.tau, W.es_lo, W.es_hi, W.tau_s,
+                                                             W.tl_off, W.tl_k, W.tl_e, W.tl_packed);
+    TG_LAUNCHED("k_tau_hub");
+  }
   if (timer) timer->mark(TG_PHASE_TABLES);
   if (tables) {
     k_node_tables<<<grid_for(n, 4), 256, (size_t)(4 * 2 * LL * sizeof(uint64_t)), st>>>(n, rp, ci, ty, L, W.D,
@@ -644,7 +700,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // 4-cliques of every edge in one pass over the graph (when the per-edge
   // step covers enough of the edges for a whole-graph pass to pay)
   const bool want_k4_pass = !once && tune.clique_pass != 0 && sel_count * 8 >= m;
-  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once, list_budget, want_k4_pass))
+  if (tg_status s = prepare_graph(S, st, n, nnz, rp, ci, ty, L, W, &timer, !once, list_budget, want_k4_pass,
+                                  std::max(0, tune.tau_hub_min_degree)))
     return s;
 
   // ---- schedule: edge classes and cost buckets, node tiers
@@ -1205,9 +1262,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                      W.wedge_work, W.nbr_deg_sum);
         TG_LAUNCHED("k_node_stats");
         k_tau<16><<<grid_for(m, 16, 8192), 256, 0, st>>>(m, -1, 48, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
-                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+                                                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                                         INT32_MAX);
         k_tau<64><<<grid_for(m, 4, 8192), 256, 0, st>>>(m, 48, INT32_MAX, W.ei, W.ej, rp, ci, W.deg, tyb, L, W.tau,
-                                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+                                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                                        INT32_MAX);
         TG_LAUNCHED("k_tau");
       }
       const GAcc ga_all = make_gacc(gb, 0, K, 32 << 10);
@@ -1898,6 +1957,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_part_lds_kib = 40;
   t->c4_part_chunk = 4096;
   t->c4_part_hash_ratio = 8;
+  t->tau_hub_min_degree = 4096;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,
@@ -2376,6 +2436,7 @@ tg_status tg_autotune(int64_t n, int64_t nnz, const int32_t* row_ptr, const int3
   axes.push_back({&t.c4_part_hash_ratio, {2, 4, 8, 16}});
   axes.push_back({&t.c4_part_lds_kib, {32, 40, 64}});
   axes.push_back({&t.c4_part_chunk, {2048, 4096, 8192}});
+  axes.push_back({&t.tau_hub_min_degree, {0, 256, 1024, 4096}});
   for (auto& ax : axes) {
     int32_t best_v = *ax.first;
     for (int32_t v : ax.second) {

@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
                                              const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
                                              uint32_t* __restrict__ tau_s, const int64_t* __restrict__ tl_off,
                                              int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e,
-                                             int tl_packed) {
+                                             int tl_packed, int32_t hub_min) {
   constexpr int TEAMS = 256 / TSIZE;
   // wavefront teams copy a longer row of at most STAGE ids to LDS and
   // search it there (16 KB per workgroup; 2048 ids measured slower, the
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
     const int32_t di = deg[i], dj = deg[j];
     const bool ia = di <= dj;
     const int32_t la = ia ? di : dj, lb = ia ? dj : di;
-    if (la <= dlo || la > dhi) continue;
+    if (la <= dlo || la > dhi || lb > hub_min) continue;  // hub rows: k_tau_hub
     const int32_t ra = rp[ia ? i : j], rb = rp[ia ? j : i];
     const int32_t* pa = ci + ra;
     const int32_t* pb = ci + rb;
@@ -307,6 +307,148 @@ __global__ void __launch_bounds__(256) k_tau(int64_t m, int32_t dlo, int32_t dhi
     }
     if (tl < L) {  // TSIZE >= 16 >= L
       tau[e * L + tl] = my_t;
+      if (tau_s) {
+        tau_s[(int64_t)es_lo[e] * L + tl] = my_t;
+        tau_s[(int64_t)es_hi[e] * L + tl] = my_t;
+      }
+    }
+  }
+}
+
+// Hub rows as bitmaps: for each hub (a node whose row is longer than the
+// tau pass's hub threshold) one bit per node id over nw = ceil(n / 64) words
+// and, per word, the number of set bits before it (its row position), so
+// that an edge whose longer row is a hub finds each id of its shorter row
+// with two loads instead of a binary search.  bits must be zero on entry.
+__global__ void k_hub_bits(int64_t nslots, int64_t nh, const int32_t* __restrict__ hubs,
+                           const int64_t* __restrict__ hoff, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ ci, int64_t nw, uint64_t* __restrict__ bits) {
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nslots; f += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nh;  // the largest h with hoff[h] <= f
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hoff[mid] <= f) lo = mid; else hi = mid;
+    }
+    const int32_t k = ci[rp[hubs[lo]] + (f - hoff[lo])];
+    atomicOr((unsigned long long*)&bits[lo * nw + (k >> 6)], 1ull << (k & 63));
+  }
+}
+
+// Nodes whose degree exceeds hmin: their number (count_only) or their list
+// and degrees (at cursor[0], any order).
+__global__ void __launch_bounds__(256) k_hubs_above(int64_t n, const int32_t* __restrict__ deg, int32_t hmin,
+                                                    int count_only, int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ hubs, int64_t* __restrict__ hdeg) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (deg[v] <= hmin) continue;
+    const int32_t q = atomicAdd(cursor, 1);
+    if (!count_only) {
+      hubs[q] = (int32_t)v;
+      hdeg[q] = deg[v];
+    }
+  }
+}
+
+// One workgroup per hub: rank[h][w] = set bits of hub h's words before w.
+__global__ void __launch_bounds__(256) k_hub_rank(int64_t nw, const uint64_t* __restrict__ bits,
+                                                  int32_t* __restrict__ rank) {
+  __shared__ int32_t part[256];
+  const int64_t h = blockIdx.x;
+  const uint64_t* b = bits + h * nw;
+  int32_t* r = rank + h * nw;
+  const int64_t per = (nw + 255) / 256;
+  const int64_t w0 = min(nw, (int64_t)threadIdx.x * per), w1 = min(nw, w0 + per);
+  int32_t c = 0;
+  for (int64_t w = w0; w < w1; ++w) c += __popcll(b[w]);
+  part[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int q = 0; q < 256; ++q) {
+      const int32_t v = part[q];
+      part[q] = s;
+      s += v;
+    }
+  }
+  __syncthreads();
+  int32_t s = part[threadIdx.x];
+  for (int64_t w = w0; w < w1; ++w) {
+    r[w] = s;
+    s += __popcll(b[w]);
+  }
+}
+
+// tau of the edges whose longer row is a hub's, hub by hub (consecutive
+// teams take consecutive slots of one hub's row, so its bitmap stays in
+// cache): one 64-lane team per slot s of hub b's row, for the edge (a, b)
+// with a = ci[rp[b] + s] when b is that edge's longer side (the side the
+// tau kernel searches); the same outputs as k_tau (tau, tau by slot, the
+// kept list in id order of the shorter row).
+__global__ void __launch_bounds__(256) k_tau_hub(int64_t nslots, int64_t nh, const int32_t* __restrict__ hubs,
+                                                 const int64_t* __restrict__ hoff, int64_t nw,
+                                                 const uint64_t* __restrict__ bits, const int32_t* __restrict__ rank,
+                                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const int32_t* __restrict__ deg, const int32_t* __restrict__ s2e,
+                                                 const uint8_t* __restrict__ ty, int L, uint32_t* __restrict__ tau,
+                                                 const int32_t* __restrict__ es_lo, const int32_t* __restrict__ es_hi,
+                                                 uint32_t* __restrict__ tau_s, const int64_t* __restrict__ tl_off,
+                                                 int32_t* __restrict__ tl_k, int32_t* __restrict__ tl_e, int tl_packed) {
+  constexpr int TSIZE = TG_WAVE, TEAMS = 256 / TSIZE;
+  const int team = threadIdx.x / TSIZE, tl = threadIdx.x % TSIZE;
+  for (int64_t f = (int64_t)blockIdx.x * TEAMS + team; f < nslots; f += (int64_t)gridDim.x * TEAMS) {
+    int64_t lo = 0, hi = nh;  // the largest h with hoff[h] <= f
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hoff[mid] <= f) lo = mid; else hi = mid;
+    }
+    const int32_t b = hubs[lo];
+    const int32_t rb = rp[b];
+    const int32_t a = ci[rb + (f - hoff[lo])];
+    const int32_t da = deg[a], db = deg[b];
+    // b is the longer side: i = min(a, b), j = max(a, b), the longer is j
+    // when d_i <= d_j, else i (the tau kernel's rule)
+    const bool b_is_j = b > a;
+    const bool b_longer = b_is_j ? (da <= db) : (db > da);
+    if (!b_longer) continue;
+    const int32_t e = s2e[rb + (f - hoff[lo])];
+    const int32_t ra = rp[a], la = da;
+    const uint64_t* hb = bits + lo * nw;
+    const int32_t* hr = rank + lo * nw;
+    const bool keep = tl_off != nullptr;
+    const int64_t lbase = keep ? tl_off[e] : 0;
+    int32_t nkept = 0;
+    uint32_t my_t = 0;
+    for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
+      int t = -1;
+      int32_t k = 0, p = 0;
+      if (b0 + tl < la) {
+        k = ci[ra + b0 + tl];
+        const uint64_t w = hb[k >> 6];
+        const uint64_t below = w & ((1ull << (k & 63)) - 1ull);
+        if ((w >> (k & 63)) & 1ull) {
+          p = hr[k >> 6] + __popcll(below);
+          t = ty[k];
+        }
+      }
+      const uint64_t tm = ballot(t >= 0);
+      if (keep) {
+        if (t >= 0) {
+          const int64_t pos = lbase + nkept + __popcll(tm & ((1ull << tl) - 1ull));
+          tl_k[pos] = tl_packed ? ((k << 4) | t) : k;
+          tl_e[2 * pos] = ra + b0 + tl;
+          tl_e[2 * pos + 1] = rb + p;
+        }
+        nkept += __popcll(tm);
+      }
+      if (tm) {
+        for (int tt = 0; tt < L; ++tt) {
+          const uint64_t bt = ballot(t == tt);
+          if (tl == tt) my_t += (uint32_t)__popcll(bt);
+        }
+      }
+    }
+    if (tl < L) {
+      tau[(int64_t)e * L + tl] = my_t;
       if (tau_s) {
         tau_s[(int64_t)es_lo[e] * L + tl] = my_t;
         tau_s[(int64_t)es_hi[e] * L + tl] = my_t;
