@@ -380,6 +380,10 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
   // 4 GiB.
   int32_t hub_min = INT32_MAX;
   int64_t nh = 0, hub_slots = 0;
+  W.hub_of = nullptr;
+  W.hub_bits = nullptr;
+  W.hub_rank = nullptr;
+  W.hub_nw = 0;
   const int64_t nw = (n + 63) / 64;
   int32_t* hubs = nullptr;
   int64_t* hoff = nullptr;
@@ -420,6 +424,14 @@ tg_status prepare_graph(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, cons
       TG_LAUNCHED("k_hub_bits");
       k_hub_rank<<<(unsigned)nh, 256, 0, st>>>(nw, hbits, hrank);
       TG_LAUNCHED("k_hub_rank");
+      // kept for the gather's row intersections
+      TG_HIP(S.get(&W.hub_of, n));
+      k_fill_u32<<<grid_for(n, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(W.hub_of), n, 0xffffffffu);
+      k_hub_index<<<grid_for(nh, 256, 1024), 256, 0, st>>>(nh, hubs, W.hub_of);
+      TG_LAUNCHED("k_hub_index");
+      W.hub_bits = hbits;
+      W.hub_rank = hrank;
+      W.hub_nw = nw;
     } else {
       hub_min = INT32_MAX;
     }
@@ -1315,6 +1327,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
   A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e; A.tl_packed = W.tl_packed;
+  A.hub_of = W.hub_of; A.hub_bits = W.hub_bits; A.hub_rank = W.hub_rank; A.hub_nw = W.hub_nw;
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
   A.c4_rows = slot_rows ? 0 : m;
@@ -1733,6 +1746,7 @@ tg_status measure_work(Scratch& S, hipStream_t st, int64_t n, int64_t nnz, const
   A.rp = rp; A.ci = ci; A.ty = ty; A.deg = W.deg; A.D = W.D; A.ei = W.ei; A.ej = W.ej; A.s2e = W.s2e;
   A.out_off = W.out_off; A.out_col = W.out_col; A.tau = W.tau; A.Pn = W.Pn; A.Un = W.Un; A.C4 = W.C4; A.L = L;
   A.tau_s = W.tau_s; A.tl_off = W.tl_off; A.tl_k = W.tl_k; A.tl_e = W.tl_e; A.tl_packed = W.tl_packed;
+  A.hub_of = W.hub_of; A.hub_bits = W.hub_bits; A.hub_rank = W.hub_rank; A.hub_nw = W.hub_nw;
   A.C4n = reinterpret_cast<const uint32_t*>(W.C4);
   A.c4_wide = 1;
   A.c4_rows = 0;

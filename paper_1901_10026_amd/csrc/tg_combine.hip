@@ -169,14 +169,24 @@ __device__ __forceinline__ void gather_edge(const EdgeArgs& A, int32_t e, int32_
   // members need no positions (no ballot, no barrier per chunk)
   if (!PROBE)
     for (int u = 0; u < L; ++u) nT += (int32_t)A.tau[(int64_t)e * L + u];
+  // a hub's row is searched in its bitmap (two loads per id)
+  const int32_t hb = A.hub_of ? A.hub_of[b] : -1;
+  const uint64_t* hbits = hb >= 0 ? A.hub_bits + (int64_t)hb * A.hub_nw : nullptr;
+  const int32_t* hrank = hb >= 0 ? A.hub_rank + (int64_t)hb * A.hub_nw : nullptr;
   for (int32_t b0 = 0; b0 < la; b0 += TSIZE) {
     const int32_t idx = b0 + tid;
     bool found = false;
     int32_t k = 0, p = 0;
     if (idx < la) {
       k = A.ci[ra + idx];
-      p = lower_bound(A.ci + rb, lb, k);
-      found = p < lb && A.ci[rb + p] == k;
+      if (hbits) {
+        const uint64_t w = hbits[k >> 6];
+        found = (w >> (k & 63)) & 1ull;
+        if (found) p = hrank[k >> 6] + __popcll(w & ((1ull << (k & 63)) - 1ull));
+      } else {
+        p = lower_bound(A.ci + rb, lb, k);
+        found = p < lb && A.ci[rb + p] == k;
+      }
     }
     int t = 0;
     if (found) {

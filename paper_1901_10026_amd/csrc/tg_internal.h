@@ -56,6 +56,10 @@ struct Work {
   uint32_t* tau_s;       // nnz*L: tau of each edge again at both of its CSR slots (per-edge counting only)
   int64_t* tl_off;       // m+1, or null: start of each edge's common-neighbour list kept by the tau pass
   int tl_packed;         // list ids hold their node's type in the low 4 bits (n < 2^27)
+  int32_t* hub_of;       // n, or null: index of each hub node (row bitmaps below), -1 for the others
+  uint64_t* hub_bits;    // hubs x hub_nw: bit k of a hub's bitmap = node k in its row
+  int32_t* hub_rank;     // hubs x hub_nw: set bits before each word (the row position)
+  int64_t hub_nw;        // words per hub bitmap, ceil(n / 64)
   int32_t* tl_k;         // list entries: member ids (id << 4 | type when tl_packed) ...
   int32_t* tl_e;         // ... and the CSR slots of k in the rows of a and b, two per member
   uint64_t* Pn;          // n*L*L
@@ -82,6 +86,10 @@ struct EdgeArgs {
   const uint32_t* tau_s;  // tau by CSR slot
   const int64_t* tl_off;  // common-neighbour lists of the edges (from the tau pass), or null
   int tl_packed;          // list ids are id << 4 | type
+  const int32_t* hub_of;  // row bitmaps of the hubs (see Work), or null
+  const uint64_t* hub_bits;
+  const int32_t* hub_rank;
+  int64_t hub_nw;
   const int32_t* tl_k;
   const int32_t* tl_e;
   const uint64_t* Pn;

@@ -349,6 +349,11 @@ __global__ void __launch_bounds__(256) k_hubs_above(int64_t n, const int32_t* __
   }
 }
 
+__global__ void k_hub_index(int64_t nh, const int32_t* __restrict__ hubs, int32_t* __restrict__ hub_of) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nh; q += (int64_t)gridDim.x * blockDim.x)
+    hub_of[hubs[q]] = (int32_t)q;
+}
+
 // One workgroup per hub: rank[h][w] = set bits of hub h's words before w.
 __global__ void __launch_bounds__(256) k_hub_rank(int64_t nw, const uint64_t* __restrict__ bits,
                                                   int32_t* __restrict__ rank) {
