@@ -131,10 +131,12 @@ def test_rows_only_counting():
     assert g3 is None and np.array_equal(r3, rr[100:1500])
 
 
-@pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5), (420, 8)])
+@pytest.mark.parametrize("n,L", [(12, 3), (60, 4), (200, 2), (301, 5), (302, 5), (420, 8)])
 def test_complete_graphs_hit_heavy_paths(n, L):
     # |T_ij| = n - 2 exceeds one wavefront's capacity for n >= 131, and the
     # highest-ranked nodes carry enough wedges for the grouped dense path.
+    # K_302: the lowest node's 301 higher neighbours take the clique pass's
+    # workgroup tier with LDS rows at an odd row count.
     rp, ci = complete(n)
     ty = (np.arange(n) % L).astype(np.uint8)
     note(f"K_{n} L={L}")
