@@ -978,8 +978,8 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     TG_HIP(hipMemcpyAsync(d_hs, hs.data(), (n_t3 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
     // Dense groups may take their middle counts from records bucketed by
     // far-end id range and summed in LDS (k_c4_bwalk, k_c4_bcount) instead of
-    // from global atomics; every row of a node's dense array is then written,
-    // so the array needs no clearing.
+    // from global atomics; every row that the credit walk reads is then
+    // written, so the array needs no clearing.
     bool use_parts = false;
     int64_t partR = 0, partK = 0;
     size_t bw_lds = 0, bc_lds = 0;
@@ -1136,7 +1136,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                              0xffffffffu);                                         \
       k_fill_u32<<<grid_for(rows * RW, 256, 16384), 256, 0, st>>>(hcnt, rows * RW, 0);                             \
     } else if (use_parts) {                                                                                        \
-      /* the next dense group's counts overwrite every row */                                                      \
+      /* the next dense group's counts overwrite every row it reads */                                                      \
     } else if (fill_clear) {                                                                                       \
       k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0);                        \
     } else {                                                                                                       \

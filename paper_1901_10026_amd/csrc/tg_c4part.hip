@@ -15,8 +15,9 @@
 //     item's own CHW words; runs[item][k] is where range k starts;
 //   k_c4_bcount: one workgroup per (node, range) adds the range's records of
 //     every item of the node into an LDS table of R rows (L 16-bit counts,
-//     two per word) and writes the table out as the range's dense rows (4
-//     words each, every row, so that the array needs no clearing).
+//     two per word) and writes out the rows of the far ends the node reaches
+//     (4 words each); the credit walk reads no other row, so the array needs
+//     no clearing.
 // The credit walk of the grouped kernel then reads the rows as before.
 //
 // Needs L <= 8, 16-bit middle counts (maximum degree below 65536), the packed
@@ -216,7 +217,9 @@ __global__ void __launch_bounds__(NT) k_c4_bcount(int K, int R, int RWp, int64_t
     }
     __syncthreads();
   }
-  // the range's rows out, padded to 4 words
+  // the range's rows out, padded to 4 words: only the rows of far ends
+  // that some wedge of the node reaches, the only rows the credit walk
+  // reads (a row left alone may hold an earlier node's counts)
   const int64_t lo = (int64_t)k * R;
   const int32_t nr = (int32_t)(lo + R < n ? R : n - lo);
   uint4* dst = reinterpret_cast<uint4*>(out + (int64_t)gi * stride + lo * 4);
@@ -224,7 +227,7 @@ __global__ void __launch_bounds__(NT) k_c4_bcount(int K, int R, int RWp, int64_t
     uint32_t v[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = j < RWp ? table[r * RWp + j] : 0u;
-    dst[r] = make_uint4(v[0], v[1], v[2], v[3]);
+    if (v[0] | v[1] | v[2] | v[3]) dst[r] = make_uint4(v[0], v[1], v[2], v[3]);
   }
 }
 
