@@ -1970,7 +1970,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_parts = 1;
   t->c4_part_lds_kib = 40;
   t->c4_part_chunk = 4096;
-  t->c4_part_hash_ratio = 8;
+  t->c4_part_hash_ratio = 16;
   t->tau_hub_min_degree = 4096;
 }
 
