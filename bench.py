@@ -537,6 +537,36 @@ def directed4_leg(tg, dev, steps=3):
             "nonzero_keys": int(glob.view(torch.int64).ne(0).sum().item())}
 
 
+def partite_leg(tg, dev, steps=3):
+    """The two part-structured graphs (bipartite 50M edges, L = 2;
+    3-partite 30M edges, L = 3): per-edge rows for every edge and global
+    counts, per call, with the phase times."""
+    import torch
+
+    import graphgen
+    res = {}
+    for name in ("bip-50m", "tri-30m"):
+        t0 = time.time()
+        g = graphgen.workload(name)
+        gen_s = time.time() - t0
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        ci = torch.from_numpy(g.col_idx).to(dev)
+        ty = torch.from_numpy(g.types).to(dev)
+        out_g = torch.empty(tg.num_keys(g.L), dtype=torch.uint64, device=dev)
+        out_e = torch.empty((g.m, tg.edge_row_width(g.L)), dtype=torch.uint64, device=dev)
+        tg.count(rp, ci, ty, g.L, out_global=out_g, out_edges=out_e)
+        ms = time_count(tg, g, rp, ci, ty, out_g, out_e, steps)
+        ph = {}
+        tg.count(rp, ci, ty, g.L, out_global=out_g, out_edges=out_e, phase_ms=ph)
+        torch.cuda.synchronize()
+        res[name] = {"n": g.n, "m": g.m, "L": g.L, "max_degree": int(np.diff(g.row_ptr).max()), "generate_s": gen_s,
+                     "ms": ms, "edges_per_s": g.m / (ms / 1e3), "phase_ms": ph}
+        log(f"{name}: m={g.m} {ms:.1f} ms per call ({g.m / (ms / 1e3) / 1e6:.1f} M edges/s)")
+        del rp, ci, ty, out_g, out_e
+        tg.release_scratch()
+    return res
+
+
 def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1, learned=True):
     """The 20M-node skewed graph (300M edges, L = 8) through the whole
     per-edge path: one tg_count over every edge, with global counts from the
@@ -751,6 +781,7 @@ def main():
     ap.add_argument("--no-directed", action="store_true", help="skip the directed 3-node leg")
     ap.add_argument("--giant-global", action="store_true",
                     help="also count the 20M-node graph's global counts in full, typed and untyped (minutes)")
+    ap.add_argument("--no-partite", action="store_true", help="skip the bipartite and 3-partite graphs")
     ap.add_argument("--no-giant", action="store_true",
                     help="skip the 20M-node graph's per-edge leg (every edge counted under the degree and the "
                          "learned schedule, several minutes)")
@@ -879,6 +910,12 @@ def main():
         rec["directed4"] = directed4_leg(tg, dev)
     if not args.no_outputs:
         rec["outputs"] = outputs_leg(tg, g, rp, ci, ty, out_g, out_e)
+    if not args.no_partite:
+        try:
+            rec["partite"] = partite_leg(tg, dev)
+        except Exception as ex:  # reported in the line; the rest of the run still counts
+            log(f"partite leg failed: {ex}")
+            rec["partite"] = {"error": str(ex)}
     if args.giant_global:
         rec["giant_global"] = giant_global_leg(tg, dev)
     if not args.no_giant:
