@@ -890,7 +890,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     };
     // the bucketed counts of dense groups (below) shift the balance towards
     // hash tables for the lighter nodes: their own ratio applies then
-    const bool parts_ok = !once && tune.c4_parts != 0 && cdt && half && L <= 8 && nty == 1;
+    const bool parts_ok = !once && tune.c4_parts != 0 && cdt && L <= 8 && nty == 1;
     const int hash_ratio = std::max(0, parts_ok ? tune.c4_part_hash_ratio : tune.c4_hash_ratio);
     int64_t qd = n_t3;  // nodes [0, qd) dense, [qd, n_t3) hashed
     if (hash_ratio > 0) {
@@ -984,8 +984,9 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     int64_t partR = 0, partK = 0;
     size_t bw_lds = 0, bc_lds = 0;
     const int part_rw = (L + 1) / 2;
-    const int CHW = std::max(256, std::min(32768, tune.c4_part_chunk));
+    int CHW = std::max(256, std::min(32768, tune.c4_part_chunk));
     std::vector<int64_t> gwalk(ngroups + 1, 0);  // walk items of each group (a prefix)
+    std::vector<char> gpart(ngroups, 0);          // dense groups counted by the bucketed pass
     std::vector<int64_t> gnit(ngroups + 1, 0);   // each group's per-node item starts in d_nit
     int32_t* d_nit = nullptr;
     uint32_t* d_region = nullptr;
@@ -1000,16 +1001,27 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       // R rows of part_rw words, R a multiple of 4 so that the table is whole uint4s
       partR = cap > fixed ? (int64_t)((cap - fixed) / ((size_t)part_rw * 4)) / 4 * 4 : 0;
       partK = partR > 0 ? (n + partR - 1) / partR : 0;
+      // every (node, range) workgroup reads its range's start in each walk
+      // item of the node: items of at least 2K wedges keep those reads below
+      // the records' own bytes (20M nodes, K = 7813: 16384 wedges per item,
+      // 4-cycle pass 73.3 -> 68.9 s)
+      while (CHW < 16384 && CHW < 2 * partK) CHW *= 2;
       bw_lds = c4_bwalk_lds(CHW, (int)std::min<int64_t>(partK, 1 << 20));
       bc_lds = c4_bcount_lds((int)partR, part_rw, 256);
       if (partR >= 64 && partK < 65536 && bw_lds <= (size_t)max_lds) {
-        // per dense group: each node's first walk item (group-local), then the total
+        // per dense group whose counts fit 16 bits (every node's degree below
+        // 65536: a count is at most d_x): each node's first walk item
+        // (group-local), then the total
         std::vector<int32_t> nit;
         int64_t max_items = 0, total = 0;
         for (int64_t g = 0; g < ngroups; ++g) {
           gwalk[g] = total;
           gnit[g] = (int64_t)nit.size();
           if (gstart[g] >= qd) continue;
+          int32_t gmax = 0;
+          for (int64_t c = 0; c < gcount[g]; ++c) gmax = std::max(gmax, hd[order[gstart[g] + c]]);
+          if (gmax >= 65536) continue;
+          gpart[g] = 1;
           int64_t items = 0;
           for (int64_t c = 0; c < gcount[g]; ++c) {
             nit.push_back((int32_t)items);
@@ -1032,11 +1044,16 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
         }
       }
     }
+    // dense rows left by a bucketed group are not zero: a grouped count
+    // after one clears its rows first
+    bool dense_dirty = false;
     if (G > 0) {
       TG_HIP(S.get(&dense, G * stride));
       if (!use_parts) {
         k_fill_u32<<<grid_for(G * stride, 256, 16384), 256, 0, st>>>(dense, G * stride, 0);
         TG_LAUNCHED("k_fill_u32");
+      } else {
+        dense_dirty = true;
       }
     }
     if (max_hrows > 0) {
@@ -1100,6 +1117,16 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       // wedge: 64, 128, 256 and 512 were measured); hashed groups always by a
       // fill of their rows
       const bool fill_clear = hashed || Gg * stride * (int64_t)sizeof(uint32_t) < Wn * 128;
+      // bucketed groups keep 16-bit counts (4-word rows) whatever the
+      // maximum degree
+      const bool gp = !hashed && use_parts && gpart[g];
+      const bool ghalf = half || gp;
+      const int RWg = ghalf ? CS / 2 : CS;
+      if (!hashed && !gp && dense_dirty) {
+        k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0);
+        TG_LAUNCHED("k_fill_u32");
+      }
+      if (!hashed) dense_dirty = gp;
       const int stage_xu = (L <= 8 && ch * max_deg < (1ll << 32)) ? 1 : 0;
       // phase 3 (once): at most a few resident waves of workgroups, so that
       // few LDS key copies are flushed
@@ -1107,11 +1134,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_GROUP(PH, T, HF, HS, C4P, STG)                                                                       \
   k_c4_group<PH, T, HF, HS><<<PH == 3 ? grid3 : grid, 256,                                                         \
                               PH == 3 ? gacc_bytes(ga_cyc_g) : ((PH == 1 && STG) ? xu_lds : 0), st>>>(             \
-      Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RW, hog, hlg, hkeys, rp, ci, W.deg, tyb,   \
+      Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RWg, hog, hlg, hkeys, rp, ci, W.deg, tyb,  \
       L, s2x, C4P, crows, STG, ga_cyc_g, cdt)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
-    if (!HS && use_parts) {                                                                                        \
+    if (!HS && gp) {                                                                                               \
       if (gwalk[g + 1] > gwalk[g]) {                                                                               \
         k_c4_bwalk<TG_C4P_NW><<<(unsigned)(gwalk[g + 1] - gwalk[g]), TG_C4P_NW * TG_WAVE, bw_lds, st>>>(           \
             d_nit + gnit[g], Gg, CHW, (int)partR, (int)partK, gxg, gsl, d_wp + hs[q0], rp, ci, cdt, d_region,     \
@@ -1126,7 +1153,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     if (once && (HS || fill_clear)) {                                                                              \
       const int64_t nrows = HS ? rows : Gg * n;                                                                    \
       k_c4_scan<HF, HS><<<grid_for(nrows, 256, 2048), 256, gacc_bytes(ga_cyc_g), st>>>(                            \
-          nrows, cnt_base, RW, n, Gg, gxg, hog, hkeys, tyb, L, ga_cyc_g);                                          \
+          nrows, cnt_base, RWg, n, Gg, gxg, hog, hkeys, tyb, L, ga_cyc_g);                                         \
       break;                                                                                                       \
     }                                                                                                              \
     if (once) TG_C4_GROUP(3, T, HF, HS, C4P, STG);                                                                 \
@@ -1135,7 +1162,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       k_fill_u32<<<grid_for(rows, 256, 16384), 256, 0, st>>>(reinterpret_cast<uint32_t*>(hkeys), rows,             \
                                                              0xffffffffu);                                         \
       k_fill_u32<<<grid_for(rows * RW, 256, 16384), 256, 0, st>>>(hcnt, rows * RW, 0);                             \
-    } else if (use_parts) {                                                                                        \
+    } else if (gp) {                                                                                               \
       /* the next dense group's counts overwrite every row it reads */                                                      \
     } else if (fill_clear) {                                                                                       \
       k_fill_u32<<<grid_for(Gg * stride, 256, 16384), 256, 0, st>>>(dense, Gg * stride, 0);                        \
@@ -1146,10 +1173,10 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
 #define TG_C4_ALL(HS)                                                  \
   do {                                                                 \
     if (c4_wide) {                                                     \
-      if (half) TG_C4_PHASES(uint64_t, true, HS, C4w_t, stage_xu);     \
+      if (ghalf) TG_C4_PHASES(uint64_t, true, HS, C4w_t, stage_xu);    \
       else TG_C4_PHASES(uint64_t, false, HS, C4w_t, stage_xu);         \
     } else {                                                           \
-      if (half) TG_C4_PHASES(uint32_t, true, HS, C4n_t, stage_xu);     \
+      if (ghalf) TG_C4_PHASES(uint32_t, true, HS, C4n_t, stage_xu);    \
       else TG_C4_PHASES(uint32_t, false, HS, C4n_t, stage_xu);         \
     }                                                                  \
   } while (0)

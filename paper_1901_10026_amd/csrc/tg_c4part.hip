@@ -20,9 +20,10 @@
 //     no clearing.
 // The credit walk of the grouped kernel then reads the rows as before.
 //
-// Needs L <= 8, 16-bit middle counts (maximum degree below 65536), the packed
-// degree and type of every slot's column node (cdt), degrees below 2^28,
-// CHW <= 32768 and fewer than 65536 ranges.
+// Needs L <= 8, 16-bit middle counts (every node of the group of degree below
+// 65536: rows of 4 words, also where other groups keep 32-bit counts), the
+// packed degree and type of every slot's column node (cdt), degrees below
+// 2^28, CHW <= 32768 and fewer than 65536 ranges.
 
 namespace tg {
 

@@ -252,14 +252,35 @@ def test_clique_pass_tiers_on_a_dense_graph():
         assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
 
-@pytest.mark.parametrize("which,L,lds_kib", [("cl-2k", 3, 4), ("gnp", 5, 4), ("gnp", 8, 5), ("kab", 2, 4)])
+def gnp_with_hub(leaves=66000, links=10):
+    """G(450, 0.75) and one more node (id 450) joined to nodes 0..links-1 and
+    to `leaves` new leaves: its degree passes 65535 while its wedge work stays
+    below that of the densest G(450, 0.75) nodes."""
+    rp, ci = graphgen.gnp(450, 0.75, 31)
+    src = np.repeat(np.arange(450), np.diff(rp))
+    keep = src < ci
+    edges = list(zip(src[keep].tolist(), ci[keep].tolist()))
+    edges += [(v, 450) for v in range(links)]
+    edges += [(450, 451 + v) for v in range(leaves)]
+    return csr_from_edges(451 + leaves, edges)
+
+
+@pytest.mark.parametrize("which,L,lds_kib", [("cl-2k", 3, 4), ("gnp", 5, 4), ("gnp", 8, 5), ("kab", 2, 4),
+                                             ("hub", 5, 4)])
 def test_cycle_parts_match_the_grouped_pass(which, L, lds_kib):
     """Middle counts of the dense 4-cycle groups from records bucketed by
     far-end id range and summed in LDS (every heavy node dense, tables small
     enough for several ranges, small walk items) or from global atomics: the
-    same rows, and the oracle's on a sample."""
+    same rows, and the oracle's on a sample.  With a node of degree 65536 or
+    more, only the groups whose nodes all have smaller degrees take the
+    bucketed pass (16-bit rows inside 32-bit row space), before and after a
+    group of 32-bit rows."""
     import paper_1901_10026_amd as tg
-    if which == "cl-2k":
+    if which == "hub":
+        rp, ci = gnp_with_hub()
+        ty = graphgen.types_uniform(len(rp) - 1, L, 31)
+        assert np.diff(rp).max() >= 65536
+    elif which == "cl-2k":
         g = graphgen.chung_lu_small()
         rp, ci = g.row_ptr, g.col_idx
         ty = graphgen.types_uniform(g.n, L, 5)
@@ -272,6 +293,8 @@ def test_cycle_parts_match_the_grouped_pass(which, L, lds_kib):
     note(f"cycle parts: {which} L={L}")
     ei, ej = oracle.canonical_edges(rp, ci)
     sample = np.linspace(0, len(ei) - 1, 50).astype(np.int64)
+    if which == "hub":  # the hub's edges into G(450, 0.75) too
+        sample = np.union1d(sample, np.nonzero((ej == 450) & (ei < 450))[0])
     want_rows, _ = oracle.count_edges(rp, ci, ty, L, ei[sample], ej[sample], nthreads=8)
     base_g, base_r, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict({"c4_parts": 0}))
     assert np.array_equal(base_r[sample], want_rows)
