@@ -132,11 +132,13 @@ typedef struct {
   int32_t c4_parts;           /* tg_count: 1 = the dense groups of the 4-cycle pass take their middle
                                  counts from records bucketed by far-end id range and summed in LDS
                                  instead of from global atomics (L <= 8; the groups whose nodes all
-                                 have degrees below 65536); 0 = never */
+                                 have degrees below 65536; graphs of at most 8192 id ranges of the
+                                 range table); 0 = never */
   int32_t c4_part_lds_kib;    /* tg_count: LDS per workgroup of the range table, capped by the device's
                                  limit */
   int32_t c4_part_chunk;      /* tg_count: wedges per walk item of that pass (256 to 32768; raised to
-                                 twice the number of id ranges, up to 16384) */
+                                 twice the number of id ranges, up to 16384, and the pass is off
+                                 when that is not enough) */
   int32_t c4_part_hash_ratio; /* tg_count: c4_hash_ratio in effect when that pass is on */
   int32_t tau_hub_min_degree; /* tg_count: the typed-triangle pass finds the common neighbours of an edge
                                  whose longer row has more than this many entries in a bitmap of that

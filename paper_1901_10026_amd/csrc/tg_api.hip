@@ -1003,12 +1003,13 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
       partK = partR > 0 ? (n + partR - 1) / partR : 0;
       // every (node, range) workgroup reads its range's start in each walk
       // item of the node: items of at least 2K wedges keep those reads below
-      // the records' own bytes (20M nodes, K = 7813: 16384 wedges per item,
-      // 4-cycle pass 73.3 -> 68.9 s)
+      // the records' own bytes, and graphs with more ranges than that allows
+      // keep the grouped count (20M nodes, K = 8461 at 40 KiB: the bucketed
+      // pass with 4096-wedge items took 73.3 s against 70.6 s)
       while (CHW < 16384 && CHW < 2 * partK) CHW *= 2;
       bw_lds = c4_bwalk_lds(CHW, (int)std::min<int64_t>(partK, 1 << 20));
       bc_lds = c4_bcount_lds((int)partR, part_rw, 256);
-      if (partR >= 64 && partK < 65536 && bw_lds <= (size_t)max_lds) {
+      if (partR >= 64 && 2 * partK <= CHW && bw_lds <= (size_t)max_lds) {
         // per dense group whose counts fit 16 bits (every node's degree below
         // 65536: a count is at most d_x): each node's first walk item
         // (group-local), then the total

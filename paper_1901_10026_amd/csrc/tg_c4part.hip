@@ -23,7 +23,7 @@
 // Needs L <= 8, 16-bit middle counts (every node of the group of degree below
 // 65536: rows of 4 words, also where other groups keep 32-bit counts), the
 // packed degree and type of every slot's column node (cdt), degrees below
-// 2^28, CHW <= 32768 and fewer than 65536 ranges.
+// 2^28, CHW <= 32768 and at most CHW / 2 ranges.
 
 namespace tg {
 
