@@ -635,6 +635,14 @@ def giant_per_edge_leg(tg, dev, rows_edges=100_000, repeats=1, learned=True):
     glob = outs["degree"][0].cpu().numpy().view(np.uint64)
     total = int(sum(int(x) for x in glob))
     res["typed_graphlets"] = total
+    # the phases a schedule decides: the edge order of the combine step and
+    # the ordering itself (the other phases do the same work under both)
+    res["scheduled_phases_ms"] = {k: res[k]["phase_ms"].get("schedule", 0.0) + res[k]["phase_ms"].get("combine", 0.0)
+                                  for k in ("degree", "learned")}
+    res["learned_gain_scheduled_phases"] = 1.0 - res["scheduled_phases_ms"]["learned"] / res["scheduled_phases_ms"][
+        "degree"]
+    log(f"cl-20m schedule + combine phases: degree {res['scheduled_phases_ms']['degree'] / 1e3:.2f} s, learned "
+        f"{res['scheduled_phases_ms']['learned'] / 1e3:.2f} s")
     res["edges_per_s"] = {k: g.m / (res[k]["ms"] * 1e-3) for k in ("degree", "learned")}
     res["typed_graphlets_per_s"] = {k: total / (res[k]["ms"] * 1e-3) for k in ("degree", "learned")}
     log(f"cl-20m: rows and global counts identical under both schedules: {res['equal']}")
