@@ -143,6 +143,11 @@ typedef struct {
   int32_t tau_hub_min_degree; /* tg_count: the typed-triangle pass finds the common neighbours of an edge
                                  whose longer row has more than this many entries in a bitmap of that
                                  row (raised until the bitmaps fit in 4 GiB; 0 = binary search always) */
+  int32_t c4_split_log2;      /* tg_count: when the 4-cycle counters need 64 bits and per-slot rows of
+                                 64-bit counters exceed c4_slot_budget_mb, per-slot rows of 32-bit
+                                 counters are kept if device memory allows, and an edge (a, b) with
+                                 (d_a - 1)(d_b - 1) >= 2^c4_split_log2 is counted in its 64-bit per-edge
+                                 counters instead (1 to 32; 0 = per-edge counters only) */
 } tg_tuning;
 
 /* Fills *t with the library's defaults. */

@@ -67,13 +67,13 @@ class Tuning(ctypes.Structure):
                 ("clique_pass_grid", ctypes.c_int32), ("clique_pass_lds_kib", ctypes.c_int32),
                 ("c4_parts", ctypes.c_int32), ("c4_part_lds_kib", ctypes.c_int32),
                 ("c4_part_chunk", ctypes.c_int32), ("c4_part_hash_ratio", ctypes.c_int32),
-                ("tau_hub_min_degree", ctypes.c_int32)]
+                ("tau_hub_min_degree", ctypes.c_int32), ("c4_split_log2", ctypes.c_int32)]
     SCALARS = ("light_max_degree", "heavy_min_degree", "mid_log2_cost", "heavy_log2_cost", "combine_grid",
                "wg_grid", "c4_footprint_mb", "c4_group_kwedges", "c4_chunk", "c4_hash_ratio", "c4_slot_budget_mb",
                "c4_slices", "clique_team_max", "clique_wave_max", "clique_lds_ids", "tlist_budget_mib",
                "clique_pass", "clique_pass_grid", "clique_pass_lds_kib", "c4_parts", "c4_part_lds_kib",
                "c4_part_chunk", "c4_part_hash_ratio",
-               "tau_hub_min_degree")
+               "tau_hub_min_degree", "c4_split_log2")
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k in self.SCALARS}

@@ -90,7 +90,7 @@ struct Scratch {
   hipStream_t stream;
   std::vector<void*> ptrs;  // pool allocations
   Workspace* ws = nullptr;  // held workspace, or null
-  size_t off = 0, total = 0;
+  size_t off = 0, total = 0, peak = 0;
   explicit Scratch(hipStream_t s) : stream(s) {
     Workspace* w = device_workspace();
     bool expect = false;
@@ -117,9 +117,25 @@ struct Scratch {
     if (ws->done) (void)hipEventRecord(ws->done, stream);
     ws->last = stream;
     ws->used = true;
-    ws->want = total;
+    ws->want = std::max(peak, total);
     ws->busy.store(false);
   }
+  // Everything obtained after a mark is given back by release(mark), in
+  // stream order: later allocations reuse it once the work enqueued before
+  // the release is done with it.
+  struct Mark {
+    size_t off, total, nptrs;
+  };
+  Mark mark() const { return Mark{off, total, ptrs.size()}; }
+  void release(const Mark& mk) {
+    for (size_t i = mk.nptrs; i < ptrs.size(); ++i) (void)hipFreeAsync(ptrs[i], stream);
+    ptrs.resize(mk.nptrs);
+    peak = std::max(peak, total);
+    off = mk.off;
+    total = mk.total;
+  }
+  // bytes left in the held workspace
+  size_t room() const { return (ws && ws->base && ws->cap > off) ? ws->cap - off : 0; }
   template <class T>
   hipError_t get(T** out, int64_t count) {
     *out = nullptr;
@@ -785,10 +801,33 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   // rows afterwards; else straight to per-edge rows.
   const int64_t c4_width = c4_wide ? 8 : 4;
   const bool slot_rows = !once && nnz * P * c4_width <= ((int64_t)std::max(0, tune.c4_slot_budget_mb) << 20);
-  const int32_t* s2x = slot_rows ? nullptr : W.s2e;
-  const int64_t crows = slot_rows ? nnz : m;  // counters are C4[p * crows + row]
+  // what the 4-cycle pass allocates from here on is given back after its fold
+  const Scratch::Mark c4_mark = S.mark();
+  // Split counters (C4Split): when 64-bit slot rows do not fit the budget,
+  // 32-bit slot rows if the device has room for them, the edges that may
+  // pass 2^c4_split_log2 cycles counted in their 64-bit per-edge counters.
+  bool split = false;
+  if (!once && c4_wide && !slot_rows && tune.c4_split_log2 > 0) {
+    size_t free_b = 0, total_b = 0;
+    TG_HIP(hipMemGetInfo(&free_b, &total_b));
+    // memory the default pool holds but has not handed out counts as free
+    int pdev = 0;
+    hipMemPool_t pool;
+    uint64_t reserved = 0, used = 0;
+    if (hipGetDevice(&pdev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, pdev) == hipSuccess &&
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &reserved) == hipSuccess &&
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemCurrent, &used) == hipSuccess && reserved > used)
+      free_b += (size_t)(reserved - used);
+    const size_t need = (size_t)nnz * (size_t)P * sizeof(uint32_t);
+    split = need + (8ull << 30) <= free_b + S.room();
+  }
+  const bool srows = slot_rows || split;  // counters per CSR slot
+  const bool c4s_wide = c4_wide && !split;  // width of the counters the walks credit
+  const int32_t* s2x = srows ? nullptr : W.s2e;
+  const int64_t crows = srows ? nnz : m;  // counters are C4[p * crows + row]
   uint64_t* C4w_t = W.C4;
   uint32_t* C4n_t = C4n;
+  C4Split c4x{};
   if (slot_rows) {
     uint64_t* c4s;
     TG_HIP(S.get(&c4s, (nnz * P * c4_width + 7) / 8));
@@ -796,6 +835,14 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
                                                                                  0);
     C4w_t = c4s;
     C4n_t = reinterpret_cast<uint32_t*>(c4s);
+  } else if (split) {
+    TG_HIP(S.get(&C4n_t, nnz * P));
+    k_fill_u32<<<grid_for(nnz * P, 256, 16384), 256, 0, st>>>(C4n_t, nnz * P, 0);
+    k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
+    c4x.C4e = W.C4;
+    c4x.s2e = W.s2e;
+    c4x.lim = 1ull << std::min(32, tune.c4_split_log2);
+    c4x.P = (int)P;
   } else if (!once) {
     k_fill_u64<<<grid_for(m * P, 256, 8192), 256, 0, st>>>(W.C4, m * P, 0);
   }
@@ -818,31 +865,31 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     const GAcc ga_cyc = gacc_cyc(b, 8 << 10);
     if (n_t1 > 0) {
       k_c4_hash<1, 8, uint32_t, true><<<grid_for(n_t1, 4, 4096), 256, gacc_bytes(ga_cyc), st>>>(
-          n_t1, W.nlist + cur[257], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt);
+          n_t1, W.nlist + cur[257], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt, C4Split{});
       TG_LAUNCHED("k_c4_hash<1, glob>");
     }
     if (n_t2 > 0) {
       k_c4_hash<4, 12, uint32_t, true><<<grid_for(n_t2, 1, 2048), 256, gacc_bytes(ga_cyc), st>>>(
-          n_t2, W.nlist + cur[258], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt);
+          n_t2, W.nlist + cur[258], rp, ci, W.deg, ty + b * n, L, nullptr, nullptr, 0, ga_cyc, cdt, C4Split{});
       TG_LAUNCHED("k_c4_hash<4, glob>");
     }
   }
   if (!once && n_t1 > 0) {
-    if (c4_wide)
+    if (c4s_wide)
       k_c4_hash<1, 8, uint64_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4w_t, crows, GAcc{}, cdt);
+                                                                         L, s2x, C4w_t, crows, GAcc{}, cdt, c4x);
     else
       k_c4_hash<1, 8, uint32_t><<<grid_for(n_t1, 4, 4096), 256, 0, st>>>(n_t1, W.nlist + cur[257], rp, ci, W.deg, ty,
-                                                                         L, s2x, C4n_t, crows, GAcc{}, cdt);
+                                                                         L, s2x, C4n_t, crows, GAcc{}, cdt, c4x);
     TG_LAUNCHED("k_c4_hash<1>");
   }
   if (!once && n_t2 > 0) {
-    if (c4_wide)
+    if (c4s_wide)
       k_c4_hash<4, 12, uint64_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4w_t, crows, GAcc{}, cdt);
+                                                                          ty, L, s2x, C4w_t, crows, GAcc{}, cdt, c4x);
     else
       k_c4_hash<4, 12, uint32_t><<<grid_for(n_t2, 1, 2048), 256, 0, st>>>(n_t2, W.nlist + cur[258], rp, ci, W.deg,
-                                                                          ty, L, s2x, C4n_t, crows, GAcc{}, cdt);
+                                                                          ty, L, s2x, C4n_t, crows, GAcc{}, cdt, c4x);
     TG_LAUNCHED("k_c4_hash<4>");
   }
   if (n_t3 > 0) {
@@ -1136,7 +1183,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   k_c4_group<PH, T, HF, HS><<<PH == 3 ? grid3 : grid, 256,                                                         \
                               PH == 3 ? gacc_bytes(ga_cyc_g) : ((PH == 1 && STG) ? xu_lds : 0), st>>>(             \
       Gg, gxg, gsl, wpg, wstride, gsl_n, bnd, (int)ch, cnt_base, stride, RWg, hog, hlg, hkeys, rp, ci, W.deg, tyb,  \
-      L, s2x, C4P, crows, STG, ga_cyc_g, cdt)
+      L, s2x, C4P, crows, STG, ga_cyc_g, cdt, c4x)
 #define TG_C4_PHASES(T, HF, HS, C4P, STG)                                                                          \
   do {                                                                                                             \
     if (!HS && gp) {                                                                                               \
@@ -1173,7 +1220,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   } while (0)
 #define TG_C4_ALL(HS)                                                  \
   do {                                                                 \
-    if (c4_wide) {                                                     \
+    if (c4s_wide) {                                                    \
       if (ghalf) TG_C4_PHASES(uint64_t, true, HS, C4w_t, stage_xu);    \
       else TG_C4_PHASES(uint64_t, false, HS, C4w_t, stage_xu);         \
     } else {                                                           \
@@ -1202,7 +1249,11 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
     else
       k_c4_fold<uint32_t><<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, nnz, W.es_lo, W.es_hi, C4n_t, C4n);
     TG_LAUNCHED("k_c4_fold");
+  } else if (split) {
+    k_c4_fold_add<<<grid_for(m * P, 256, 16384), 256, 0, st>>>(m, (int)P, nnz, W.es_lo, W.es_hi, C4n_t, W.C4);
+    TG_LAUNCHED("k_c4_fold_add");
   }
+  S.release(c4_mark);
 
   int dev = 0, cus = 0;
   TG_HIP(hipGetDevice(&dev));
@@ -1358,7 +1409,7 @@ tg_status count_impl(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* c
   A.hub_of = W.hub_of; A.hub_bits = W.hub_bits; A.hub_rank = W.hub_rank; A.hub_nw = W.hub_nw;
   A.C4n = C4n;
   A.c4_wide = c4_wide ? 1 : 0;
-  A.c4_rows = slot_rows ? 0 : m;
+  A.c4_rows = srows ? 0 : m;
   A.edge_counts = edge_counts; A.edge_begin = eb; A.edge_end = ee; A.global_sums = global_counts;
   A.edge_ids = ids; A.n_edge_ids = nids;
   A.edge_orbits = opt.edge_orbits;
@@ -2000,6 +2051,7 @@ void tg_tuning_default(tg_tuning* t) {
   t->c4_part_chunk = 4096;
   t->c4_part_hash_ratio = 16;
   t->tau_hub_min_degree = 4096;
+  t->c4_split_log2 = 32;
 }
 
 tg_status tg_count_batch(int64_t G, const int64_t* node_off, const int64_t* slot_off, const int32_t* row_ptr_local,

@@ -577,13 +577,37 @@ __device__ __forceinline__ void c4_add(uint64_t* C4, int64_t idx, uint64_t v) {
   atomicAdd((unsigned long long*)&C4[idx], (unsigned long long)v);
 }
 
+// Split counters: where per-slot 64-bit rows would not fit, the slot rows
+// are kept in 32 bits and the few edges whose count may reach lim (an edge
+// (a, b) lies on at most (d_a - 1)(d_b - 1) 4-cycles) are credited in 64-bit
+// per-edge counters C4e[e * P + p] instead; k_c4_fold_add then adds the slot
+// rows of every edge to them.  C4e null: no split.
+struct C4Split {
+  uint64_t* C4e;
+  const int32_t* s2e;  // slot -> canonical edge id
+  uint64_t lim;
+  int P;
+};
+
+// Credit v cycles of type pair p to row `row` (a slot or an edge id) of the
+// edge (a, b) of degrees da, db.
+template <class C4T>
+__device__ __forceinline__ void c4_credit(C4T* __restrict__ C4, int64_t crows, int p, int32_t row, uint64_t v,
+                                          const C4Split& X, int32_t da, int32_t db) {
+  if (X.C4e && (uint64_t)(da - 1) * (uint64_t)(db - 1) >= X.lim)
+    atomicAdd((unsigned long long*)&X.C4e[(int64_t)X.s2e[row] * X.P + p], (unsigned long long)v);
+  else
+    c4_add(C4, (int64_t)p * crows + row, v);
+}
+
 template <class C4T>
 __device__ __forceinline__ void credit_wedge(C4T* __restrict__ C4, int64_t crows, int32_t e_xu, int32_t e_uw,
-                                             int phx, int phu, int phw, int t, uint32_t cnt_t) {
+                                             int phx, int phu, int phw, int t, uint32_t cnt_t, const C4Split& X,
+                                             int32_t dx, int32_t du, int32_t dw) {
   const int64_t c = (int64_t)cnt_t - (t == phu ? 1 : 0);
   if (c > 0) {
-    c4_add(C4, (int64_t)pair_index(phw, t) * crows + e_xu, (uint64_t)c);
-    c4_add(C4, (int64_t)pair_index(phx, t) * crows + e_uw, (uint64_t)c);
+    c4_credit(C4, crows, pair_index(phw, t), e_xu, (uint64_t)c, X, dx, du);
+    c4_credit(C4, crows, pair_index(phx, t), e_uw, (uint64_t)c, X, du, dw);
   }
 }
 
@@ -598,7 +622,7 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
                                                  const int32_t* __restrict__ deg, const uint8_t* __restrict__ ty,
                                                  int L, const int32_t* __restrict__ s2e,
                                                  C4T* __restrict__ C4, int64_t crows, GAcc ga,
-                                                 const uint32_t* __restrict__ cdt) {
+                                                 const uint32_t* __restrict__ cdt, C4Split X) {
   extern __shared__ uint64_t hash_gacc[];
   if (GLOB) gacc_init(ga, hash_gacc);
   constexpr int CAP = 1 << LOG2CAP;
@@ -634,7 +658,8 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
           // degree and type of w: packed per slot when cdt is given (read in
           // row order), else gathered by node id
           const uint32_t dtw = cdt ? cdt[bu + b0 + ln] : 0u;
-          if (!precedes(cdt ? (int32_t)(dtw >> 4) : deg[w], w, dx, x)) continue;
+          const int32_t dw = cdt ? (int32_t)(dtw >> 4) : deg[w];
+          if (!precedes(dw, w, dx, x)) continue;
           if (pass == 0) {
             const int h = hash_insert(kw, LOG2CAP, w);
             atomicAdd(&tw[h], 1u);
@@ -652,7 +677,7 @@ __global__ void __launch_bounds__(256) k_c4_hash(int64_t count, const int32_t* _
                 const int64_t c = (int64_t)(g >= 0 ? ct[g] : 0u) - (t == phu ? 1 : 0);
                 if (c > 0) gacc_add(ga, hash_gacc, key_of(L, 4, phx, phu, phw, t), (uint64_t)c);
               } else {
-                credit_wedge(C4, crows, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u);
+                credit_wedge(C4, crows, e_xu, e_uw, phx, phu, phw, t, g >= 0 ? ct[g] : 0u, X, dx, du, dw);
               }
             }
           }
@@ -765,7 +790,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
                                                   const uint8_t* __restrict__ ty, int L,
                                                   const int32_t* __restrict__ s2e, C4T* __restrict__ C4,
                                                   int64_t crows, int stage_xu, GAcc ga,
-                                                  const uint32_t* __restrict__ cdt) {
+                                                  const uint32_t* __restrict__ cdt, C4Split X) {
   // credits to the edges (x, u) of the window's 64 slots are summed in LDS
   // first (stage_xu: L <= 8 and every sum fits 32 bits); dynamic LDS of
   // 4 * 64 * P words in phase 1 with stage_xu, the key copies of ga in
@@ -805,7 +830,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
     }
     // this lane's slot and the part of its wedges inside [wbeg, wend)
     const int64_t sl = sa + ln;
-    int32_t x = 0, dx = 0, bu = 0, cu = 0, off = 0, e_xu = 0, gi = 0;
+    int32_t x = 0, dx = 0, du = 0, bu = 0, cu = 0, off = 0, e_xu = 0, gi = 0;
     int phx = 0, phu = 0;
     if (sl < S) {
       const int64_t ws = wpk[sl] - W0, we = wpk[sl + 1] - W0;
@@ -821,6 +846,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         dx = deg[x];
         const int32_t sx = rp[x] + (int32_t)(sl - (gslot[a] - sbase));
         const int32_t u = ci[sx];
+        if (PHASE == 1) du = cdt ? (int32_t)(cdt[sx] >> 4) : deg[u];
         cu = (int32_t)(hi - lo);
         off = (int32_t)(lo - ws);
         bu = rp[u] + (nsl > 1 ? bnd[(int64_t)u * (nsl + 1) + ksl] : 0);
@@ -873,6 +899,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
         const int o_phx = __shfl(phx, o, TG_WAVE);
         const int o_phu = __shfl(phu, o, TG_WAVE);
         const int32_t o_exu = __shfl(e_xu, o, TG_WAVE);
+        const int32_t o_du = PHASE == 1 ? __shfl(du, o, TG_WAVE) : 0;
         const int32_t w = wv[k], suw = sv[k];
         if (!ok[k] || !precedes(dw[k], w, o_dx, o_x)) continue;
         uint32_t* row;
@@ -930,9 +957,9 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
           for (int t = 0; t < L; ++t) {
             const int64_t cc = (int64_t)c[t] - (t == o_phu ? 1 : 0);
             if (cc <= 0) continue;
-            c4_add(C4, (int64_t)pair_index(o_phx, t) * crows + e_uw, (uint64_t)cc);
+            c4_credit(C4, crows, pair_index(o_phx, t), e_uw, (uint64_t)cc, X, o_du, dw[k]);
             if (stage_xu) atomicAdd(&xacc[o * P + pair_index(phw, t)], (uint32_t)cc);
-            else c4_add(C4, (int64_t)pair_index(phw, t) * crows + o_exu, (uint64_t)cc);
+            else c4_credit(C4, crows, pair_index(phw, t), o_exu, (uint64_t)cc, X, o_dx, o_du);
           }
         } else {
           for (int q4 = 0; q4 < RW / 4; ++q4) reinterpret_cast<uint4*>(row)[q4] = make_uint4(0u, 0u, 0u, 0u);
@@ -944,7 +971,7 @@ __global__ void __launch_bounds__(256) k_c4_group(int G, const int32_t* __restri
       wave_sync();
       for (int p = 0; p < P; ++p) {
         const uint32_t val = xacc[ln * P + p];
-        if (val) c4_add(C4, (int64_t)p * crows + e_xu, (uint64_t)val);
+        if (val) c4_credit(C4, crows, p, e_xu, (uint64_t)val, X, dx, du);
       }
       wave_sync();
     }
@@ -976,6 +1003,18 @@ __global__ void k_c4_fold(int64_t m, int P, int64_t nslots, const int32_t* __res
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = x / P, p = x - e * P;
     C4e[x] = C4s[p * nslots + es_lo[e]] + C4s[p * nslots + es_hi[e]];
+  }
+}
+
+// Split counters: adds the two 32-bit slot rows of every edge to its 64-bit
+// counters (which hold the credits of the edges counted there directly).
+__global__ void k_c4_fold_add(int64_t m, int P, int64_t nslots, const int32_t* __restrict__ es_lo,
+                              const int32_t* __restrict__ es_hi, const uint32_t* __restrict__ C4s,
+                              uint64_t* __restrict__ C4e) {
+  const int64_t total = m * P;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = x / P, p = x - e * P;
+    C4e[x] += (uint64_t)C4s[p * nslots + es_lo[e]] + (uint64_t)C4s[p * nslots + es_hi[e]];
   }
 }
 

@@ -252,17 +252,24 @@ def test_clique_pass_tiers_on_a_dense_graph():
         assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
 
-def gnp_with_hub(leaves=66000, links=10):
-    """G(450, 0.75) and one more node (id 450) joined to nodes 0..links-1 and
-    to `leaves` new leaves: its degree passes 65535 while its wedge work stays
-    below that of the densest G(450, 0.75) nodes."""
-    rp, ci = graphgen.gnp(450, 0.75, 31)
-    src = np.repeat(np.arange(450), np.diff(rp))
+def edge_list(rp, ci, shift=0):
+    src = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
     keep = src < ci
-    edges = list(zip(src[keep].tolist(), ci[keep].tolist()))
-    edges += [(v, 450) for v in range(links)]
-    edges += [(450, 451 + v) for v in range(leaves)]
-    return csr_from_edges(451 + leaves, edges)
+    return list(zip((src[keep] + shift).tolist(), (ci[keep] + shift).tolist()))
+
+
+def with_hub(n, edges, leaves=66000, links=10):
+    """The graph on nodes 0..n-1 and one more node (id n) joined to nodes
+    0..links-1 and to `leaves` new leaves: its degree passes 65535."""
+    edges = edges + [(v, n) for v in range(links)] + [(n, n + 1 + v) for v in range(leaves)]
+    return csr_from_edges(n + 1 + leaves, edges)
+
+
+def gnp_with_hub(leaves=66000, links=10):
+    """G(450, 0.75) with a hub (id 450) whose wedge work stays below that of
+    the densest G(450, 0.75) nodes."""
+    rp, ci = graphgen.gnp(450, 0.75, 31)
+    return with_hub(450, edge_list(rp, ci), leaves, links)
 
 
 @pytest.mark.parametrize("which,L,lds_kib", [("cl-2k", 3, 4), ("gnp", 5, 4), ("gnp", 8, 5), ("kab", 2, 4),
@@ -303,6 +310,35 @@ def test_cycle_parts_match_the_grouped_pass(which, L, lds_kib):
               {"c4_part_hash_ratio": 0, "c4_slices": 8}):
         gg, rr, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict(d))
         assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
+
+
+def test_split_cycle_counters():
+    """A graph with a node of degree 66010, so that a 4-cycle count may need
+    64 bits: per-slot rows of 32-bit counters, with every edge (a, b) of
+    (d_a - 1)(d_b - 1) >= 2^k counted in its 64-bit per-edge counters instead
+    (k = 32: none of them; 10 and 1: most edges away from the leaves), give
+    the rows of 64-bit slot rows, and so do 64-bit per-edge counters alone
+    (split off); also with one node per group and every heavy node dense."""
+    import paper_1901_10026_amd as tg
+    # G(450, 0.75) (dense groups) and the Chung-Lu graph on 2000 nodes (every
+    # node tier) side by side, then the hub
+    rg, cg = graphgen.gnp(450, 0.75, 31)
+    c = graphgen.chung_lu_small()
+    rp, ci = with_hub(450 + c.n, edge_list(rg, cg) + edge_list(c.row_ptr, c.col_idx, shift=450))
+    hub = 450 + c.n
+    L = 5
+    ty = graphgen.types_uniform(len(rp) - 1, L, 31)
+    ei, ej = oracle.canonical_edges(rp, ci)
+    sample = np.union1d(np.linspace(0, len(ei) - 1, 60).astype(np.int64), np.nonzero((ej == hub) & (ei < hub))[0])
+    want_rows, _ = oracle.count_edges(rp, ci, ty, L, ei[sample], ej[sample], nthreads=8)
+    base_g, base_r, _ = gpu_count(rp, ci, ty, L)
+    assert np.array_equal(base_r[sample], want_rows)
+    for k in (32, 10, 1, 0):
+        for extra in ({}, {"c4_group_kwedges": 1, "c4_hash_ratio": 0, "c4_part_hash_ratio": 0}):
+            d = dict({"c4_slot_budget_mb": 0, "c4_split_log2": k}, **extra)
+            note(f"split counters {d}")
+            gg, rr, _ = gpu_count(rp, ci, ty, L, tuning=tg.Tuning.from_dict(d))
+            assert np.array_equal(gg, base_g) and np.array_equal(rr, base_r), d
 
 
 def test_release_scratch_between_calls():
