@@ -104,7 +104,22 @@ struct Scratch {
       ws->cap = 0;
       const size_t cap = ws->want + ws->want / 10;
       void* p = nullptr;
-      if (hipMallocAsync(&p, cap, stream) == hipSuccess) {
+      if (hipMallocAsync(&p, cap, stream) != hipSuccess) {
+        // A workspace that does not fit is no error: the call then takes its
+        // memory piece by piece.  Clear the error (the launch checks read
+        // it), give the pool's cached memory back and try once more.
+        p = nullptr;
+        (void)hipGetLastError();
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipStreamSynchronize(stream) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && hipMemPoolTrimTo(pool, 0) == hipSuccess &&
+            hipMallocAsync(&p, cap, stream) != hipSuccess) {
+          p = nullptr;
+        }
+        (void)hipGetLastError();
+      }
+      if (p) {
         ws->base = (char*)p;
         ws->cap = cap;
       }

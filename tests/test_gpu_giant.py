@@ -81,3 +81,17 @@ def test_giant_sampled_rows():
             bad.append(q)
     assert not bad, f"{len(bad)} of {len(ids)} sampled edges differ, first edge {ids[bad[0]]}"
     note(f"{len(ids)} sampled edges' sparse pairs match the oracle's nonzero row entries")
+
+
+def test_small_call_after_the_giant_one():
+    """The call after a 20M-node one: growing the workspace to that call's
+    size does not fit next to what the pool caches; the call allocates piece
+    by piece instead and is exact."""
+    import paper_1901_10026_amd as tg
+    g = graphgen.tiny_graph(7)
+    rb, _, gb = oracle.brute(g.row_ptr, g.col_idx, g.types, g.L)
+    rp, ci, ty = to_dev(g.row_ptr, g.col_idx, g.types)
+    glob, rows, _ = tg.count(rp, ci, ty, g.L)
+    assert np.array_equal(glob.cpu().numpy().view(np.uint64), gb)
+    assert np.array_equal(rows.cpu().numpy().view(np.uint64), rb)
+    tg.release_scratch()
