@@ -143,6 +143,8 @@ def test_type_permutations_keep_type_frequencies():
 def test_tuning_defaults_and_round_trip():
     t = tg.Tuning.default()
     assert t.tlist_budget_mib == 16384 and t.clique_lds_ids == 4096
+    # the last fields land where the library writes them (same layout)
+    assert t.c4_parts == 1 and t.tau_hub_min_degree == 4096 and t.c4_split_log2 == 32
     d = t.as_dict()
     d["tlist_budget_mib"] = 0
     assert tg.Tuning.from_dict(d).as_dict() == d
